@@ -1,0 +1,671 @@
+/*
+ * kr_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Only tests, the package smoke check and the benchmark's CPU-baseline leg
+ * use this file.  It shares no code with the HIP library: it parses the
+ * network description itself, derives reverse rates itself and implements
+ * every step of the per-cell integration sequentially, in FP64, in the order
+ * the method takes them.  It is deliberately unoptimised: no blocking, no
+ * fusion, no reordering.
+ *
+ * Method (paper Sec. 2.2):
+ *   dn^i/dt = sum_r nu_ri w_r(n, T)                    (eq. method-ode-thermochem,
+ *   d eps/dt = Q(n, T) = sum_r qhat_r w_r                mass-action form)
+ *   eps = T * sum_s c_s n_s                              (T = eps / c_V)
+ * with w_r = k_f(T) prod_{reac} n - k_r(T) prod_{prod} n and modified
+ * Arrhenius coefficients k = A T^b exp(-E/T) (Sec. 2.2.1, item 1).  The
+ * reverse coefficient follows from detailed balance with per-species
+ * formation energy h_s and entropy s_s at the standard-state pressure p_ref
+ * (reference density n_ref = p_ref / (k_B T)); with dnu = #products -
+ * #reactants, K_eq = n_ref^dnu exp(dS - dH/T) and
+ *   k_r = k_f / K_eq  =>  A_r = A (k_B/p_ref)^dnu e^{-dS}, b_r = b + dnu,
+ *                          E_r = E - dH.
+ * qhat_r = -dH_r is the heat released per forward event, which makes
+ * U = sum_s n_s (c_s T + h_s) an exact invariant of each BE substep.
+ *
+ * Each substep is backward Euler, R(y) = 0 with
+ *   R_s = n_s - n_s^(n) - h f_s(y),   R_E = eps(y) - eps(y^(n)) - h Q(y),
+ * solved by Newton iteration with the analytic Jacobian (Sec. 2.2.1,
+ * eq. method-jacobian; T is the energy unknown so the thermal column is
+ * d/dT, the paper's dk/deps = (1/c_V) dk/dT being the same column rescaled)
+ * and an LU decomposition with implicit row scaling and partial pivoting
+ * (Algorithm algo:lu-decomp, taken sequentially).  The substep size is set by
+ * an error controller; pre-processing follows Sec. 2.2.2 (floors, T limits)
+ * and post-processing and the retry/revert ladder follow Sec. 2.2.3.
+ */
+#include "kr_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KRO_MAXN 64
+#define KRO_KB 1.380649e-16   /* Boltzmann constant, erg/K */
+
+struct kro_net {
+  int S, n_rows, n_elem, R;
+  int32_t *comp;     /* [n_rows][S] */
+  int32_t *res;      /* [n_rows] */
+  double *cv, *h, *s;
+  int32_t *reac, *prod; /* [R][3] */
+  int32_t *nu;       /* [R][S] net stoichiometry */
+  double *par;       /* [R][2][3] (A, b, E) forward / reverse */
+  double *qhat;      /* [R] heat released per forward event (K) */
+  double T_min, T_max;
+};
+
+/* ------------------------------------------------------------------------ */
+/* network                                                                   */
+/* ------------------------------------------------------------------------ */
+
+kro_net *kro_net_create(int S, int n_rows, int n_elem, const int32_t *comp,
+                        const int32_t *reservoir, const double *cv,
+                        const double *h_form, const double *s_form, int R,
+                        const int32_t *reac, const int32_t *prod,
+                        const double *arr_f, const double *arr_r,
+                        double p_ref, double T_min, double T_max, int *err) {
+  *err = 0;
+  if (S < 1 || S + 1 > KRO_MAXN || n_rows < 0 || n_elem < 0 ||
+      n_elem > n_rows || R < 0 || !(p_ref > 0.0)) {
+    *err = 1;
+    return NULL;
+  }
+  for (int r = 0; r < R; ++r)
+    for (int k = 0; k < 3; ++k) {
+      if (reac[3 * r + k] >= S || prod[3 * r + k] >= S) { *err = 1; return NULL; }
+    }
+  kro_net *n = (kro_net *)calloc(1, sizeof(kro_net));
+  n->S = S; n->n_rows = n_rows; n->n_elem = n_elem; n->R = R;
+  n->T_min = T_min; n->T_max = T_max;
+  n->comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_rows * S + 1));
+  n->res = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_rows + 1));
+  n->cv = (double *)malloc(sizeof(double) * S);
+  n->h = (double *)malloc(sizeof(double) * S);
+  n->s = (double *)malloc(sizeof(double) * S);
+  n->reac = (int32_t *)malloc(sizeof(int32_t) * (size_t)(3 * R + 1));
+  n->prod = (int32_t *)malloc(sizeof(int32_t) * (size_t)(3 * R + 1));
+  n->nu = (int32_t *)calloc((size_t)(R * S + 1), sizeof(int32_t));
+  n->par = (double *)malloc(sizeof(double) * (size_t)(6 * R + 1));
+  n->qhat = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+  memcpy(n->comp, comp, sizeof(int32_t) * (size_t)(n_rows * S));
+  memcpy(n->res, reservoir, sizeof(int32_t) * (size_t)n_rows);
+  memcpy(n->cv, cv, sizeof(double) * S);
+  memcpy(n->h, h_form, sizeof(double) * S);
+  memcpy(n->s, s_form, sizeof(double) * S);
+  memcpy(n->reac, reac, sizeof(int32_t) * (size_t)(3 * R));
+  memcpy(n->prod, prod, sizeof(int32_t) * (size_t)(3 * R));
+
+  for (int r = 0; r < R; ++r) {
+    for (int k = 0; k < 3; ++k) {
+      if (reac[3 * r + k] >= 0) n->nu[r * S + reac[3 * r + k]] -= 1;
+      if (prod[3 * r + k] >= 0) n->nu[r * S + prod[3 * r + k]] += 1;
+    }
+    /* every reaction must conserve every row (elements and charge) */
+    for (int v = 0; v < n_rows; ++v) {
+      long sum = 0;
+      for (int sp = 0; sp < S; ++sp) sum += (long)comp[v * S + sp] * n->nu[r * S + sp];
+      if (sum != 0) { *err = 2; kro_net_destroy(n); return NULL; }
+    }
+    double dH = 0.0, dS = 0.0;
+    int dnu = 0;
+    for (int sp = 0; sp < S; ++sp) {
+      dH += n->nu[r * S + sp] * h_form[sp];
+      dS += n->nu[r * S + sp] * s_form[sp];
+      dnu += n->nu[r * S + sp];
+    }
+    n->qhat[r] = -dH;
+    double *pf = n->par + 6 * r, *pr = pf + 3;
+    pf[0] = arr_f[3 * r]; pf[1] = arr_f[3 * r + 1]; pf[2] = arr_f[3 * r + 2];
+    if (arr_r) {
+      pr[0] = arr_r[3 * r]; pr[1] = arr_r[3 * r + 1]; pr[2] = arr_r[3 * r + 2];
+    } else {
+      /* detailed balance: k_r = k_f / K_eq,
+       * K_eq = (p_ref / (k_B T))^dnu exp(dS - dH/T) */
+      pr[0] = pf[0] * pow(KRO_KB / p_ref, dnu) * exp(-dS);
+      pr[1] = pf[1] + dnu;
+      pr[2] = pf[2] - dH;
+    }
+  }
+  /* a reservoir must carry only its own row */
+  for (int v = 0; v < n_rows; ++v) {
+    int rs = reservoir[v];
+    if (rs < 0 || rs >= S || comp[v * S + rs] == 0) { *err = 3; kro_net_destroy(n); return NULL; }
+    for (int u = 0; u < n_rows; ++u)
+      if (u != v && comp[u * S + rs] != 0) { *err = 3; kro_net_destroy(n); return NULL; }
+  }
+  return n;
+}
+
+void kro_net_destroy(kro_net *n) {
+  if (!n) return;
+  free(n->comp); free(n->res); free(n->cv); free(n->h); free(n->s);
+  free(n->reac); free(n->prod); free(n->nu); free(n->par); free(n->qhat);
+  free(n);
+}
+
+void kro_arrhenius(const kro_net *n, double *out) {
+  memcpy(out, n->par, sizeof(double) * (size_t)(6 * n->R));
+}
+
+/* ------------------------------------------------------------------------ */
+/* rates, right-hand side, Jacobian                                          */
+/* ------------------------------------------------------------------------ */
+
+/* modified Arrhenius coefficient A T^b exp(-E/T) */
+static double arrhenius(const double *p, double T) {
+  return p[0] * exp(p[1] * log(T) - p[2] / T);
+}
+
+void kro_rate_coeffs(const kro_net *n, double T, double *kf, double *kr) {
+  for (int r = 0; r < n->R; ++r) {
+    kf[r] = arrhenius(n->par + 6 * r, T);
+    kr[r] = arrhenius(n->par + 6 * r + 3, T);
+  }
+}
+
+/* rate of one direction: q = k * product over the side's species slots */
+static double side_rate(double k, const int32_t *side, const double *nn) {
+  double q = k;
+  for (int i = 0; i < 3; ++i)
+    if (side[i] >= 0) q *= nn[side[i]];
+  return q;
+}
+
+/* d q / d n_m by the product rule over the side's slots */
+static double side_rate_dn(double k, const int32_t *side, const double *nn, int m) {
+  double d = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    if (side[i] != m) continue;
+    double t = k;
+    for (int j = 0; j < 3; ++j)
+      if (j != i && side[j] >= 0) t *= nn[side[j]];
+    d += t;
+  }
+  return d;
+}
+
+void kro_rhs(const kro_net *n, const double *y, double *f, double *Q) {
+  const int S = n->S;
+  const double T = y[S];
+  for (int s = 0; s < S; ++s) f[s] = 0.0;
+  double q = 0.0;
+  for (int r = 0; r < n->R; ++r) {
+    double kf = arrhenius(n->par + 6 * r, T), kr = arrhenius(n->par + 6 * r + 3, T);
+    double w = side_rate(kf, n->reac + 3 * r, y) - side_rate(kr, n->prod + 3 * r, y);
+    for (int s = 0; s < S; ++s) f[s] += n->nu[r * S + s] * w;
+    q += n->qhat[r] * w;
+  }
+  *Q = q;
+}
+
+void kro_jacobian(const kro_net *n, const double *y, double *J) {
+  const int S = n->S, N = S + 1;
+  const double T = y[S];
+  memset(J, 0, sizeof(double) * (size_t)(N * N));
+  for (int r = 0; r < n->R; ++r) {
+    const double *pf = n->par + 6 * r, *pr = pf + 3;
+    double kf = arrhenius(pf, T), kr = arrhenius(pr, T);
+    const int32_t *rc = n->reac + 3 * r, *pd = n->prod + 3 * r;
+    double qf = side_rate(kf, rc, y), qr = side_rate(kr, pd, y);
+    /* d k/dT = k (b + E/T) / T for each direction */
+    double dwdT = qf * (pf[1] + pf[2] / T) / T - qr * (pr[1] + pr[2] / T) / T;
+    double dwdn[KRO_MAXN];
+    for (int m = 0; m < S; ++m)
+      dwdn[m] = side_rate_dn(kf, rc, y, m) - side_rate_dn(kr, pd, y, m);
+    for (int s = 0; s < S; ++s) {
+      int v = n->nu[r * S + s];
+      if (!v) continue;
+      for (int m = 0; m < S; ++m) J[s * N + m] += v * dwdn[m];
+      J[s * N + S] += v * dwdT;
+    }
+    for (int m = 0; m < S; ++m) J[S * N + m] += n->qhat[r] * dwdn[m];
+    J[S * N + S] += n->qhat[r] * dwdT;
+  }
+}
+
+static double heat_capacity(const kro_net *n, const double *y) {
+  double c = 0.0;
+  for (int s = 0; s < n->S; ++s) c += n->cv[s] * y[s];
+  return c;
+}
+
+void kro_residual(const kro_net *n, const double *y, const double *yn, double h,
+                  double *R) {
+  const int S = n->S;
+  double f[KRO_MAXN], Q;
+  kro_rhs(n, y, f, &Q);
+  for (int s = 0; s < S; ++s) R[s] = y[s] - yn[s] - h * f[s];
+  R[S] = y[S] * heat_capacity(n, y) - yn[S] * heat_capacity(n, yn) - h * Q;
+}
+
+void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
+  const int S = n->S, N = S + 1;
+  double J[KRO_MAXN * KRO_MAXN];
+  kro_jacobian(n, y, J);
+  for (int s = 0; s < S; ++s) {
+    for (int m = 0; m < N; ++m) M[s * N + m] = (s == m ? 1.0 : 0.0) - h * J[s * N + m];
+  }
+  /* d eps / d n_m = c_m T ; d eps / d T = c_V */
+  for (int m = 0; m < S; ++m) M[S * N + m] = n->cv[m] * y[S] - h * J[S * N + m];
+  M[S * N + S] = heat_capacity(n, y) - h * J[S * N + S];
+}
+
+/* ------------------------------------------------------------------------ */
+/* dense linear algebra                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Crout's method with implicit row scaling: for each column j compute the
+ * U entries (rows <= j) and the not-yet-divided L entries (rows > j) from
+ * already finished columns; pick as pivot the row i >= j with the largest
+ * |a_ij| / v_i (v_i = largest magnitude in the original row i; the lowest
+ * row wins ties); exchange rows (and their scales); divide the L entries by
+ * the pivot. */
+int kro_lu_decompose(int N, double *a, int32_t *p) {
+  double v[KRO_MAXN];
+  for (int i = 0; i < N; ++i) {
+    double m = 0.0;
+    for (int j = 0; j < N; ++j) m = fmax(m, fabs(a[i * N + j]));
+    if (!(m > 0.0) || !isfinite(m)) return -1;
+    v[i] = m;
+  }
+  for (int j = 0; j < N; ++j) {
+    for (int i = 0; i < N; ++i) {
+      int kmax = (i < j ? i : j);
+      double sum = a[i * N + j];
+      for (int k = 0; k < kmax; ++k) sum -= a[i * N + k] * a[k * N + j];
+      a[i * N + j] = sum;
+    }
+    int imax = j;
+    double best = fabs(a[j * N + j]) / v[j];
+    for (int i = j + 1; i < N; ++i) {
+      double t = fabs(a[i * N + j]) / v[i];
+      if (t > best) { best = t; imax = i; }
+    }
+    if (imax != j) {
+      for (int k = 0; k < N; ++k) {
+        double tmp = a[imax * N + k]; a[imax * N + k] = a[j * N + k]; a[j * N + k] = tmp;
+      }
+      double tv = v[imax]; v[imax] = v[j]; v[j] = tv;
+    }
+    p[j] = imax;
+    double piv = a[j * N + j];
+    if (piv == 0.0 || !isfinite(piv)) return -1;
+    for (int i = j + 1; i < N; ++i) a[i * N + j] /= piv;
+  }
+  return 0;
+}
+
+void kro_lu_solve(int N, const double *a, const int32_t *p, double *b) {
+  for (int j = 0; j < N; ++j) {
+    int q = p[j];
+    if (q != j) { double t = b[q]; b[q] = b[j]; b[j] = t; }
+  }
+  for (int i = 0; i < N; ++i) {             /* L y = P b, unit diagonal */
+    double sum = b[i];
+    for (int k = 0; k < i; ++k) sum -= a[i * N + k] * b[k];
+    b[i] = sum;
+  }
+  for (int i = N - 1; i >= 0; --i) {        /* U x = y */
+    double sum = b[i];
+    for (int k = i + 1; k < N; ++k) sum -= a[i * N + k] * b[k];
+    b[i] = sum / a[i * N + i];
+  }
+}
+
+int kro_gauss_full_pivot(int N, const double *a_in, const double *b_in, double *x) {
+  double a[KRO_MAXN * KRO_MAXN], b[KRO_MAXN];
+  int col[KRO_MAXN];
+  memcpy(a, a_in, sizeof(double) * (size_t)(N * N));
+  memcpy(b, b_in, sizeof(double) * (size_t)N);
+  for (int j = 0; j < N; ++j) col[j] = j;
+  for (int k = 0; k < N; ++k) {
+    int pr = k, pc = k;
+    double best = -1.0;
+    for (int i = k; i < N; ++i)
+      for (int j = k; j < N; ++j)
+        if (fabs(a[i * N + j]) > best) { best = fabs(a[i * N + j]); pr = i; pc = j; }
+    if (!(best > 0.0)) return -1;
+    if (pr != k) {
+      for (int j = 0; j < N; ++j) { double t = a[pr * N + j]; a[pr * N + j] = a[k * N + j]; a[k * N + j] = t; }
+      double t = b[pr]; b[pr] = b[k]; b[k] = t;
+    }
+    if (pc != k) {
+      for (int i = 0; i < N; ++i) { double t = a[i * N + pc]; a[i * N + pc] = a[i * N + k]; a[i * N + k] = t; }
+      int t = col[pc]; col[pc] = col[k]; col[k] = t;
+    }
+    for (int i = k + 1; i < N; ++i) {
+      double l = a[i * N + k] / a[k * N + k];
+      for (int j = k; j < N; ++j) a[i * N + j] -= l * a[k * N + j];
+      b[i] -= l * b[k];
+    }
+  }
+  double z[KRO_MAXN];
+  for (int i = N - 1; i >= 0; --i) {
+    double sum = b[i];
+    for (int j = i + 1; j < N; ++j) sum -= a[i * N + j] * z[j];
+    z[i] = sum / a[i * N + i];
+  }
+  for (int j = 0; j < N; ++j) x[col[j]] = z[j];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* backward-Euler substep by Newton iteration                                */
+/* ------------------------------------------------------------------------ */
+
+void kro_default_opts(kro_opts *o) {
+  o->rtol = 1e-6;
+  o->floor = 1e-20;
+  o->newton_tol = 1e-3;
+  o->rho_floor = 0.0;
+  o->max_newton = 10;
+  o->max_substeps = 100000;
+  o->mode = KRO_ADAPTIVE;
+  o->n_fixed = 1;
+}
+
+/* Newton from the plain guess y = yn.  Each iteration solves M d = -R and
+ * applies d.  Converged when max_i |d_i| / w_i <= newton_tol with
+ * w_i = atol_i + rtol * max(|yn_i|, |y_i|).  Fails on a singular matrix, a
+ * non-finite value, T <= 0, two consecutive growths of the update norm, or
+ * no convergence within max_newton iterations. */
+int kro_be_substep(const kro_net *n, const kro_opts *o, const double *yn,
+                   const double *atol, double h, double *y, int32_t *iters) {
+  const int N = n->S + 1;
+  double R[KRO_MAXN], M[KRO_MAXN * KRO_MAXN], d[KRO_MAXN];
+  int32_t p[KRO_MAXN];
+  for (int i = 0; i < N; ++i) y[i] = yn[i];
+  double prev = INFINITY;
+  int grow = 0;
+  for (int k = 0; k < o->max_newton; ++k) {
+    kro_residual(n, y, yn, h, R);
+    kro_newton_matrix(n, y, h, M);
+    *iters += 1;
+    if (kro_lu_decompose(N, M, p) != 0) return -1;
+    for (int i = 0; i < N; ++i) d[i] = -R[i];
+    kro_lu_solve(N, M, p, d);
+    double norm = 0.0;
+    int finite = 1;
+    for (int i = 0; i < N; ++i) {
+      y[i] += d[i];
+      if (!isfinite(d[i]) || !isfinite(y[i])) finite = 0;
+    }
+    if (!finite || !(y[N - 1] > 0.0)) return -1;
+    for (int i = 0; i < N; ++i) {
+      double w = atol[i] + o->rtol * fmax(fabs(yn[i]), fabs(y[i]));
+      double e = fabs(d[i]) / w;
+      if (e > norm) norm = e;
+    }
+    if (norm <= o->newton_tol) return 0;
+    if (norm > prev) {
+      if (++grow >= 2) return -1;
+    } else {
+      grow = 0;
+    }
+    prev = norm;
+  }
+  return -1;
+}
+
+/* g = (f_0..f_{S-1}, Q / c_V): the rate of change of each unknown */
+static void unknown_rates(const kro_net *n, const double *y, double *g) {
+  double Q;
+  kro_rhs(n, y, g, &Q);
+  g[n->S] = Q / heat_capacity(n, y);
+}
+
+typedef struct {
+  double h0, safety, growth;
+} attempt_params;
+
+/* One attempt over [0, dt].  Adaptive: after each converged substep the
+ * local error estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i
+ * (w_i from both end points) decides; accepted when err <= 1, after which
+ * h *= min(growth, max(0.2, safety/sqrt(max(err,1e-10)))); a rejected step
+ * uses h *= max(0.2, safety/sqrt(err)); a Newton failure quarters h.  The
+ * step is clipped to land on dt exactly.  Fails when h < 1e-12 dt or the
+ * number of substep attempts reaches max_substeps. */
+static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *y0,
+                             const double *atol, double dt, attempt_params ap,
+                             double *y_out, int32_t *st) {
+  const int N = n->S + 1;
+  double yn[KRO_MAXN], y[KRO_MAXN], gn[KRO_MAXN], g[KRO_MAXN];
+  memcpy(yn, y0, sizeof(double) * (size_t)N);
+  if (o->mode == KRO_FIXED) {
+    double h = dt / (double)o->n_fixed;
+    for (int k = 0; k < o->n_fixed; ++k) {
+      if (kro_be_substep(n, o, yn, atol, h, y, &st[1]) != 0) { st[3]++; return -1; }
+      memcpy(yn, y, sizeof(double) * (size_t)N);
+      st[0]++;
+    }
+    memcpy(y_out, yn, sizeof(double) * (size_t)N);
+    return 0;
+  }
+  unknown_rates(n, yn, gn);
+  double t = 0.0, h = ap.h0;
+  int attempts = 0;
+  for (;;) {
+    if (attempts >= o->max_substeps) return -1;
+    int final = 0;
+    if (h >= dt - t) { h = dt - t; final = 1; }
+    else if (h < 1e-12 * dt) return -1;
+    attempts++;
+    if (kro_be_substep(n, o, yn, atol, h, y, &st[1]) != 0) {
+      st[3]++;
+      h *= 0.25;
+      continue;
+    }
+    unknown_rates(n, y, g);
+    double err = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double w = atol[i] + o->rtol * fmax(fabs(yn[i]), fabs(y[i]));
+      double e = fabs(0.5 * h * (g[i] - gn[i])) / w;
+      if (e > err) err = e;
+    }
+    if (!isfinite(err)) { st[2]++; h *= 0.2; continue; }
+    if (err <= 1.0) {
+      memcpy(yn, y, sizeof(double) * (size_t)N);
+      memcpy(gn, g, sizeof(double) * (size_t)N);
+      st[0]++;
+      if (final) break;
+      t += h;
+      h *= fmin(ap.growth, fmax(0.2, ap.safety / sqrt(fmax(err, 1e-10))));
+    } else {
+      st[2]++;
+      h *= fmax(0.2, ap.safety / sqrt(err));
+    }
+  }
+  memcpy(y_out, yn, sizeof(double) * (size_t)N);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* conservation, post-processing                                             */
+/* ------------------------------------------------------------------------ */
+
+static double nuclei(const kro_net *n, const double *nn) {
+  double t = 0.0;
+  for (int s = 0; s < n->S; ++s) {
+    int atoms = 0;
+    for (int v = 0; v < n->n_elem; ++v) atoms += n->comp[v * n->S + s];
+    t += atoms * nn[s];
+  }
+  return t;
+}
+
+static void row_totals(const kro_net *n, const double *nn, double *E) {
+  for (int v = 0; v < n->n_rows; ++v) {
+    double t = 0.0;
+    for (int s = 0; s < n->S; ++s) t += n->comp[v * n->S + s] * nn[s];
+    E[v] = t;
+  }
+}
+
+static double cell_element_residual(const kro_net *n, const double *before,
+                                     const double *after) {
+  double nn = nuclei(n, before), worst = 0.0;
+  for (int v = 0; v < n->n_rows; ++v) {
+    double diff = 0.0, D = 0.0;
+    for (int s = 0; s < n->S; ++s) {
+      diff += n->comp[v * n->S + s] * (after[s] - before[s]);
+      D += abs(n->comp[v * n->S + s]) * before[s];
+    }
+    if (v >= n->n_elem) D = nn;
+    double e = fabs(diff) / fmax(D, 1e-300);
+    if (!(e <= worst)) worst = e;   /* NaN propagates */
+  }
+  return worst;
+}
+
+void kro_element_residual(const kro_net *n, int64_t n_cells, const double *before,
+                          const double *after, int64_t ld, double *resid) {
+  double b[KRO_MAXN], a[KRO_MAXN];
+  for (int64_t c = 0; c < n_cells; ++c) {
+    for (int s = 0; s < n->S; ++s) { b[s] = before[s * ld + c]; a[s] = after[s * ld + c]; }
+    resid[c] = cell_element_residual(n, b, a);
+  }
+}
+
+/* Stage 1: negative abundances become zero.  Stage 2: for each conserved row
+ * in order, the row's reservoir species absorbs the difference between the
+ * initial and current totals.  Stage 3: if a reservoir is then negative, the
+ * most abundant species that carries the row with the reservoir's sign is
+ * broken up into the reservoirs of all its rows, just enough to bring the
+ * reservoir to zero (moving to the next most abundant if one is used up). */
+void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
+  const int S = n->S;
+  for (int s = 0; s < S; ++s)
+    if (nn[s] < 0.0) nn[s] = 0.0;
+  for (int v = 0; v < n->n_rows; ++v) {
+    double E = 0.0;
+    for (int s = 0; s < S; ++s) E += n->comp[v * S + s] * nn[s];
+    int rs = n->res[v];
+    nn[rs] += (E0[v] - E) / n->comp[v * S + rs];
+  }
+  for (int v = 0; v < n->n_rows; ++v) {
+    int rs = n->res[v];
+    int sign_r = n->comp[v * S + rs] > 0 ? 1 : -1;
+    int used[KRO_MAXN] = {0};
+    while (nn[rs] < 0.0) {
+      int best = -1;
+      for (int s = 0; s < S; ++s) {
+        if (s == rs || used[s]) continue;
+        int a = n->comp[v * S + s];
+        if (a == 0 || (a > 0 ? 1 : -1) != sign_r) continue;
+        if (nn[s] <= 0.0) continue;
+        if (best < 0 || nn[s] > nn[best]) best = s;
+      }
+      if (best < 0) break;
+      used[best] = 1;
+      /* converting x of species `best` changes the reservoir of row v by
+       * x * N_v,best / N_v,rs; the x that brings it to zero */
+      double need = -nn[rs] * n->comp[v * S + rs] / n->comp[v * S + best];
+      double x = need < nn[best] ? need : nn[best];
+      nn[best] -= x;
+      for (int u = 0; u < n->n_rows; ++u) {
+        int a = n->comp[u * S + best];
+        if (a) nn[n->res[u]] += x * a / n->comp[u * S + n->res[u]];
+      }
+      if (x == need) nn[rs] = 0.0;   /* drop the rounding residue */
+    }
+  }
+}
+
+double kro_fastest_timescale(const kro_net *n, const double *y) {
+  const int S = n->S, N = S + 1;
+  double J[KRO_MAXN * KRO_MAXN];
+  kro_jacobian(n, y, J);
+  /* the largest self-coupling rate: species diagonal, and the thermal mode
+   * d(Q/c_V)/dT ~ (dQ/dT)/c_V */
+  double m = 0.0;
+  for (int s = 0; s < S; ++s) m = fmax(m, fabs(J[s * N + s]));
+  double cv = heat_capacity(n, y);
+  if (cv > 0.0) m = fmax(m, fabs(J[S * N + S]) / cv);
+  if (!(m > 0.0) || !isfinite(m)) return 1e7;
+  double tau = 1.0 / m;
+  return tau < 1e7 ? tau : 1e7;
+}
+
+/* ------------------------------------------------------------------------ */
+/* per-cell driver                                                           */
+/* ------------------------------------------------------------------------ */
+
+static int cell_ok(const kro_net *n, const double *before, const double *y, double n_nuc) {
+  for (int i = 0; i <= n->S; ++i)
+    if (!isfinite(y[i])) return 0;
+  for (int s = 0; s < n->S; ++s)
+    if (y[s] < -1e-10 * n_nuc) return 0;
+  return cell_element_residual(n, before, y) <= 1e-10;
+}
+
+static int32_t integrate_cell(const kro_net *n, const kro_opts *o, double *nn,
+                              double *T, double rho, double dt, int32_t *st) {
+  const int S = n->S, N = S + 1;
+  double y0[KRO_MAXN], y[KRO_MAXN], atol[KRO_MAXN], E0[KRO_MAXN];
+  /* non-finite input: leave the cell as it came */
+  int bad = !isfinite(*T) || !isfinite(dt) || !(dt >= 0.0);
+  for (int s = 0; s < S; ++s) bad |= !isfinite(nn[s]);
+  if (bad) return 2;
+  /* pre-processing (Sec. 2.2.2): floors, density floor rescale, T limits */
+  for (int s = 0; s < S; ++s) y0[s] = nn[s] > 0.0 ? nn[s] : 0.0;
+  if (o->rho_floor > 0.0 && rho > 0.0 && rho < o->rho_floor)
+    for (int s = 0; s < S; ++s) y0[s] *= o->rho_floor / rho;
+  y0[S] = fmin(fmax(*T, n->T_min), n->T_max);
+  if (dt == 0.0) {
+    for (int s = 0; s < S; ++s) nn[s] = y0[s];
+    *T = y0[S];
+    return 0;
+  }
+  row_totals(n, y0, E0);
+  double n_nuc = nuclei(n, y0);
+  for (int s = 0; s < S; ++s) atol[s] = o->floor * n_nuc;
+  atol[S] = 0.0;
+
+  /* attempt 0, then the retry with a reduced initial step and tighter step
+   * control, then reversion to the pre-evolution values (Sec. 2.2.3) */
+  attempt_params ap[2] = {{dt, 0.9, 5.0}, {dt / 100.0, 0.5, 2.0}};
+  int32_t status = 2;
+  for (int a = 0; a < 2; ++a) {
+    if (integrate_attempt(n, o, y0, atol, dt, ap[a], y, st) == 0 && cell_ok(n, y0, y, n_nuc)) {
+      status = a;
+      break;
+    }
+    if (o->mode == KRO_FIXED) break;   /* a fixed sequence has no retry */
+  }
+  if (status == 2) return 2;
+  kro_postprocess(n, E0, y);
+  for (int s = 0; s < S; ++s) nn[s] = y[s];
+  *T = y[S];
+  (void)N;
+  return status;
+}
+
+int kro_integrate(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
+                  double *T, const double *rho, const double *dt, double dt_scalar,
+                  const kro_opts *o, int32_t *status, int32_t *cell_stats, int nthreads) {
+  if (!n || !states || !T || ld < n_cells || n_cells < 0 || !o) return -1;
+  if (o->mode == KRO_FIXED && o->n_fixed < 1) return -1;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+  for (int64_t c = 0; c < n_cells; ++c) {
+    double nn[KRO_MAXN];
+    int32_t st[4] = {0, 0, 0, 0};
+    for (int s = 0; s < n->S; ++s) nn[s] = states[s * ld + c];
+    double Tc = T[c];
+    double step = dt ? dt[c] : dt_scalar;
+    int32_t code = integrate_cell(n, o, nn, &Tc, rho ? rho[c] : 0.0, step, st);
+    if (code != 2) {
+      for (int s = 0; s < n->S; ++s) states[s * ld + c] = nn[s];
+      T[c] = Tc;
+    }
+    if (status) status[c] = code;
+    if (cell_stats) memcpy(cell_stats + 4 * c, st, sizeof(st));
+  }
+  (void)nthreads;
+  return 0;
+}

@@ -1,0 +1,353 @@
+"""Seeded synthetic reaction networks and cell states.
+
+This module only *describes* inputs: species, their element/charge
+composition, reaction lists with forward Arrhenius parameters, species
+thermodynamic data and per-cell initial states.  It contains none of the
+integration method's arithmetic (no rate evaluation, no reverse-rate
+derivation, no Jacobians); both the CPU oracle and the HIP library receive
+the same description and derive everything else themselves.
+
+The networks stand in for the paper's workloads (a 12-species/116-reaction
+H2/O2 combustion network, astro H/He/e- chemistry and "10-30 species per
+cell", Sec. 2.3.2): the paper's own mechanism data (GRI-Mech, UMIST) are not
+available, so shapes and value ranges follow the benchmark recipe documented
+alongside the benchmark, and every draw is seeded.
+
+Conventions (cgs, energies divided by k_B so they are in K):
+  * composition[nu][s]   atoms of element row nu in species s; the rows after
+                         ``n_elem`` are charge-like rows (+1 per positive
+                         charge, -1 for the electron).
+  * reservoir[nu]        the single-row species that absorbs element/charge
+                         corrections for row nu (post-processing stage 2).
+  * reac/prod[r][3]      species indices of the reactant/product multisets of
+                         reaction r, padded with -1 (at most 3 per side).
+  * arr_f[r] = (A, b, E) forward rate coefficient k = A T^b exp(-E/T).
+  * h_form, s_form       per-species formation energy [K] and entropy [k_B]
+                         at the standard-state pressure p_ref (reference
+                         density p_ref / (k_B T)), from which detailed balance
+                         fixes the reverse rate.
+  * cv                   per-particle heat capacity at constant volume [k_B].
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 2504_04941
+K_BOLTZ = 1.380649e-16      # erg / K
+ATM = 1.01325e6             # dyn / cm^2
+
+
+def rng_for(config_index: int, salt: int = 0) -> np.random.Generator:
+    """The seeded generator for one workload: Philox keyed on the config."""
+    return np.random.Generator(np.random.Philox(key=SEED_BASE + config_index + (salt << 32)))
+
+
+@dataclass
+class NetworkDesc:
+    name: str
+    species: list
+    rows: list                 # element rows then charge rows
+    n_elem: int
+    composition: np.ndarray    # int32 [n_rows, S]
+    reservoir: np.ndarray      # int32 [n_rows]
+    cv: np.ndarray             # float64 [S]
+    h_form: np.ndarray         # float64 [S]  (K)
+    s_form: np.ndarray         # float64 [S]  (k_B)
+    reac: np.ndarray           # int32 [R, 3]
+    prod: np.ndarray           # int32 [R, 3]
+    arr_f: np.ndarray          # float64 [R, 3]
+    arr_r: np.ndarray | None = None   # explicit reverse (A, b, E) or None
+    p_ref: float = ATM         # standard-state pressure of the thermo data (dyn cm^-2)
+    T_min: float = 1.0
+    T_max: float = 1.0e5
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_species(self) -> int:
+        return len(self.species)
+
+    @property
+    def n_rows(self) -> int:
+        return len(self.rows)
+
+    @property
+    def n_reactions(self) -> int:
+        return int(self.reac.shape[0])
+
+    @property
+    def n_unknowns(self) -> int:
+        return self.n_species + 1
+
+    def stoich(self) -> np.ndarray:
+        """Net stoichiometric matrix nu[r][s] = (#s in prod) - (#s in reac).
+
+        Pure bookkeeping of the description (integer counts)."""
+        nu = np.zeros((self.n_reactions, self.n_species), dtype=np.int64)
+        for r in range(self.n_reactions):
+            for s in self.reac[r]:
+                if s >= 0:
+                    nu[r, s] -= 1
+            for s in self.prod[r]:
+                if s >= 0:
+                    nu[r, s] += 1
+        return nu
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+
+def _heat_capacity(atoms: int, linear: bool) -> float:
+    """Per-particle c_V/k_B by rigid-rotor counting: 3/2 monatomic (and the
+    electron), 5/2 linear, 3 non-linear."""
+    if atoms <= 1:
+        return 1.5
+    return 2.5 if linear else 3.0
+
+
+def _thermo(rng, comp: np.ndarray, n_elem: int):
+    """Species formation energy and entropy (standard state p_ref).
+
+    Bond-counting model: every bond of a tree-shaped molecule lowers the
+    formation energy by a bond energy ~U[4e4, 6e4] K, every positive charge
+    raises it by an ionisation energy ~U[1.2e5, 1.6e5] K, plus U[-5e3, 5e3] K
+    of noise; entropy is ~12 k_B per particle (translation) with U[-2, 2]
+    noise.  This keeps detailed-balance reverse rates near gas-kinetic values
+    (dissociation endothermic, recombination exothermic), as for real
+    combustion and astro networks."""
+    S = comp.shape[1]
+    atoms = comp[:n_elem].sum(axis=0)
+    charge = comp[n_elem:].sum(axis=0) if comp.shape[0] > n_elem else np.zeros(S, int)
+    bonds = np.maximum(atoms - 1, 0)
+    h = (-bonds * rng.uniform(4e4, 6e4, size=S)
+         + np.maximum(charge, 0) * rng.uniform(1.2e5, 1.6e5, size=S)
+         + rng.uniform(-5e3, 5e3, size=S))
+    s = 12.0 + rng.uniform(-2.0, 2.0, size=S)
+    return h, s
+
+
+def _pad3(ms):
+    out = [-1, -1, -1]
+    for i, s in enumerate(ms):
+        out[i] = s
+    return out
+
+
+def enumerate_reactions(comp: np.ndarray, max_small: int, max_large: int,
+                        max_common: int = 1, spectator_only=()):
+    """All element- and charge-conserving reaction candidates between species
+    multisets.  One side has at most ``max_small`` species, the other at most
+    ``max_large``; sides share at most ``max_common`` distinct species (a
+    catalyst/third body); species in ``spectator_only`` may appear only as a
+    shared species.  Each unordered pair appears once, as (small, large)."""
+    S = comp.shape[1]
+    groups: dict = {}
+    for k in range(1, max_large + 1):
+        for m in itertools.combinations_with_replacement(range(S), k):
+            v = tuple(int(x) for x in comp[:, list(m)].sum(axis=1))
+            groups.setdefault(v, []).append(m)
+    out = []
+    for v, ms in groups.items():
+        for a, b in itertools.combinations(ms, 2):
+            if len(a) > len(b):
+                a, b = b, a
+            if len(a) > max_small:
+                continue
+            common = set(a) & set(b)
+            if len(common) > max_common:
+                continue
+            sa, sb = set(a) - common, set(b) - common
+            if any(s in sa or s in sb for s in spectator_only):
+                continue
+            # the net change must be nonzero
+            if sorted(a) == sorted(b):
+                continue
+            out.append((a, b))
+    return out
+
+
+def _span_ok(comp: np.ndarray, picks) -> bool:
+    S = comp.shape[1]
+    nu = np.zeros((len(picks), S))
+    for i, (a, b) in enumerate(picks):
+        for s in a:
+            nu[i, s] -= 1
+        for s in b:
+            nu[i, s] += 1
+    null_dim = S - np.linalg.matrix_rank(comp.astype(float))
+    return np.linalg.matrix_rank(nu) == null_dim
+
+
+def _choose_reactions(rng, comp, cands, n_react, must_touch=None, tries=2000):
+    """Seeded choice of ``n_react`` candidates whose net stoichiometry spans
+    the null space of the composition matrix (so every conserved-quantity
+    preserving direction can be reached)."""
+    S = comp.shape[1]
+    touch = set(range(S)) if must_touch is None else set(must_touch)
+    for _ in range(tries):
+        idx = rng.choice(len(cands), size=n_react, replace=False)
+        picks = [cands[i] for i in sorted(idx)]
+        used = set()
+        for a, b in picks:
+            used |= set(a) | set(b)
+        if not touch <= used:
+            continue
+        if _span_ok(comp, picks):
+            return picks
+    raise RuntimeError("could not draw a spanning reaction set")
+
+
+def _orient_and_draw(rng, picks, h_form, logA_of, b_rng, E_max, small_side_forward=True):
+    """Arrhenius parameters for each picked reaction.
+
+    The given ("forward") direction is the side with fewer species.  Its
+    barrier: the exothermic direction's barrier is drawn from U[0, E_max];
+    if the given direction is the endothermic one, its barrier is that draw
+    plus the reaction's energy change, so both directions have E >= 0."""
+    R = len(picks)
+    reac = np.full((R, 3), -1, np.int32)
+    prod = np.full((R, 3), -1, np.int32)
+    arr = np.zeros((R, 3))
+    for r, (a, b) in enumerate(picks):
+        reac[r] = _pad3(a)
+        prod[r] = _pad3(b)
+        dh = sum(h_form[s] for s in b) - sum(h_form[s] for s in a)   # forward energy change
+        e_exo = rng.uniform(0.0, E_max)
+        E = e_exo if dh <= 0.0 else e_exo + dh
+        arr[r] = (10.0 ** logA_of(len(a), rng), rng.uniform(*b_rng), E)
+    return reac, prod, arr
+
+
+# ----------------------------------------------------------------------------
+# the workload networks
+# ----------------------------------------------------------------------------
+
+def network_h_he(seed_index: int = 0) -> NetworkDesc:
+    """5 species H, H2, H+, e-, He over rows H, He and charge; 10 reversible
+    reactions with at most 3 species per side (astro H/He/e- chemistry)."""
+    rng = rng_for(seed_index, salt=1)
+    species = ["H", "H2", "H+", "e-", "He"]
+    rows = ["H", "He", "charge"]
+    comp = np.array([[1, 2, 1, 0, 0],
+                     [0, 0, 0, 0, 1],
+                     [0, 0, 1, -1, 0]], np.int32)
+    reservoir = np.array([0, 4, 3], np.int32)
+    cv = np.array([1.5, 2.5, 1.5, 1.5, 1.5])
+    h_form, s_form = _thermo(rng, comp, 2)
+    cands = enumerate_reactions(comp, 3, 3, max_common=1)
+    picks = _choose_reactions(rng, comp, cands, 10)
+    reac, prod, arr = _orient_and_draw(
+        rng, picks, h_form, lambda order, g: g.uniform(-12.0, -8.0), (-1.0, 1.0), 5e4)
+    return NetworkDesc("h_he_5sp", species, rows, 2, comp, reservoir, cv, h_form, s_form,
+                       reac, prod, arr, None, p_ref=ATM, T_min=1.0, T_max=1.0e6,
+                       meta={"config_index": 0})
+
+
+def network_h_o_n(seed_index: int = 1) -> NetworkDesc:
+    """9 species H2, O2, H, O, OH, H2O, HO2, H2O2, N2 over rows H, O, N;
+    24 reversible reactions with at most 2 species on one side and 3 on the
+    other; N2 only as a shared third body (combustion-shaped network)."""
+    rng = rng_for(seed_index, salt=1)
+    species = ["H2", "O2", "H", "O", "OH", "H2O", "HO2", "H2O2", "N2"]
+    rows = ["H", "O", "N"]
+    comp = np.array([[2, 0, 1, 0, 1, 2, 1, 2, 0],
+                     [0, 2, 0, 1, 1, 1, 2, 2, 0],
+                     [0, 0, 0, 0, 0, 0, 0, 0, 2]], np.int32)
+    reservoir = np.array([2, 3, 8], np.int32)
+    atoms = comp.sum(axis=0)
+    linear = [True, True, True, True, True, False, False, False, True]
+    cv = np.array([_heat_capacity(int(a), l) for a, l in zip(atoms, linear)])
+    h_form, s_form = _thermo(rng, comp, 3)
+    cands = enumerate_reactions(comp, 2, 3, max_common=1, spectator_only=(8,))
+    picks = _choose_reactions(rng, comp, cands, 24, must_touch=range(8))
+
+    def logA(order, g):
+        return g.uniform(6.0, 13.0) if order == 1 else g.uniform(-12.0, -9.0)
+    reac, prod, arr = _orient_and_draw(rng, picks, h_form, logA, (-1.0, 1.0), 3e4)
+    return NetworkDesc("h_o_n_9sp", species, rows, 3, comp, reservoir, cv, h_form, s_form,
+                       reac, prod, arr, None, p_ref=ATM, T_min=50.0, T_max=1.0e5,
+                       meta={"config_index": 1})
+
+
+# ----------------------------------------------------------------------------
+# cell states
+# ----------------------------------------------------------------------------
+
+@dataclass
+class CellStates:
+    n: np.ndarray      # float64 [S, n_cells]  (SoA, cm^-3)
+    T: np.ndarray      # float64 [n_cells]     (K)
+    rho: np.ndarray    # float64 [n_cells]     (g cm^-3, informational / floors)
+    dt: np.ndarray | None  # float64 [n_cells] or None when a scalar step applies
+    dt_scalar: float = 0.0
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.T.shape[0])
+
+
+_AMU = 1.66053906660e-24
+
+
+def _rho(net: NetworkDesc, n: np.ndarray) -> np.ndarray:
+    # mass from nucleon counts (1 amu per H, 4 He, 12 C, 14 N, 16 O)
+    amu = {"H": 1.0, "He": 4.0, "C": 12.0, "N": 14.0, "O": 16.0}
+    m = np.zeros(net.n_species)
+    for nu, row in enumerate(net.rows[:net.n_elem]):
+        m += amu.get(row, 1.0) * net.composition[nu]
+    return (m[:, None] * n).sum(axis=0) * _AMU
+
+
+def cells_h_he(net: NetworkDesc, n_cells: int, seed_index: int = 0) -> CellStates:
+    """T log-uniform [10, 1e4] K, hydrogen nuclei log-uniform [1, 1e6] cm^-3,
+    He = 0.1 n_H, hydrogen split H : 2 H2 : H+ by Dirichlet(1,1,1), n_e = n_H+.
+    The step is set later from the cells' fastest timescale."""
+    rng = rng_for(seed_index, salt=2)
+    T = 10.0 ** rng.uniform(1.0, 4.0, size=n_cells)
+    nH = 10.0 ** rng.uniform(0.0, 6.0, size=n_cells)
+    f = rng.dirichlet((1.0, 1.0, 1.0), size=n_cells)
+    n = np.zeros((5, n_cells))
+    n[0] = f[:, 0] * nH
+    n[1] = 0.5 * f[:, 1] * nH
+    n[2] = f[:, 2] * nH
+    n[3] = n[2]
+    n[4] = 0.1 * nH
+    return CellStates(n, T, _rho(net, n), None, 0.0)
+
+
+def cells_h_o_n(net: NetworkDesc, n_cells: int, seed_index: int = 1,
+                dt: float = 1e-4) -> CellStates:
+    """T ~ U[900, 2500] K at p = 1 atm; majors H2, O2, H2O, N2 ~
+    Dirichlet(2,1,1,4); radicals H, O, OH, HO2, H2O2 each 10^U[-12,-4];
+    renormalised mole fractions times n_tot = p / (k_B T)."""
+    rng = rng_for(seed_index, salt=2)
+    T = rng.uniform(900.0, 2500.0, size=n_cells)
+    ntot = ATM / (K_BOLTZ * T)
+    x = np.zeros((9, n_cells))
+    maj = rng.dirichlet((2.0, 1.0, 1.0, 4.0), size=n_cells)
+    for j, s in enumerate((0, 1, 5, 8)):
+        x[s] = maj[:, j]
+    for s in (2, 3, 4, 6, 7):
+        x[s] = 10.0 ** rng.uniform(-12.0, -4.0, size=n_cells)
+    x /= x.sum(axis=0, keepdims=True)
+    n = x * ntot[None, :]
+    return CellStates(n, T, _rho(net, n), None, dt)
+
+
+def network_for(config_index: int) -> NetworkDesc:
+    if config_index == 0:
+        return network_h_he(0)
+    if config_index == 1:
+        return network_h_o_n(1)
+    raise ValueError(f"no network for config {config_index}")
+
+
+def cells_for(config_index: int, net: NetworkDesc, n_cells: int) -> CellStates:
+    if config_index == 0:
+        return cells_h_he(net, n_cells, 0)
+    if config_index == 1:
+        return cells_h_o_n(net, n_cells, 1)
+    raise ValueError(f"no cells for config {config_index}")
