@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark: cell-steps/s of the implicit thermochemistry update on one GPU.
+
+Workload: 2^20 cells of the 9-species / 3-row / 24-reversible-reaction
+combustion-shaped network (energy equation, 10 unknowns per cell), T ~
+U[900, 2500] K at 1 atm, each cell integrated over dt = 1e-4 s with adaptive
+backward-Euler substeps at rtol 1e-6 (synthetic, seeded inputs).  A step is
+one kr_chem_integrate call over all cells from the same initial batch (the
+initial state is restored on the device before each step, a copy of ~100 MB
+that is <0.1% of a step).
+
+Prints one JSON line (the contract of this repository's driver), with a
+roofline object for the integrator kernel (FP64 VALU bound, algorithmic
+flops from the per-cell Newton/substep counts the kernel returns, timed with
+HIP events on the launch stream) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector, flop/s
+C_EXP = 27.0                 # FP64 exp / log counted as 27 flops each (range
+                             # reduction + degree-11 polynomial + scaling)
+
+
+def flops_per_unit(desc):
+    """Algorithmic FP64 flops of one Newton iteration and of one right-hand
+    side evaluation (the error estimate), from the network's structure.
+
+    Per direction d with m reactant slots: rate argument and coefficient
+    (4 + exp), slot products (m), d/dT (3), d/dn by the product rule
+    (m (m - 1) + m); per reaction: w and dw (1 + #columns), scatter into g
+    and J (2 flops per touched entry, energy row included).  Per iteration:
+    assembly 2 N^2 + residual 3 N, LU 2N^3/3, solve 2 N^2, update and
+    convergence 4 N.  Plus log T and 1/T."""
+    S = desc.n_species
+    N = S + 1
+    nu = desc.stoich()
+    f_eval = 2 * C_EXP
+    f_rhs = 2 * C_EXP
+    for r in range(desc.n_reactions):
+        cols = set()
+        for side in (desc.reac[r], desc.prod[r]):
+            sl = [s for s in side if s >= 0]
+            m = len(sl)
+            f_eval += 4 + C_EXP + m + 3 + m * (m - 1) + m
+            f_rhs += 4 + C_EXP + m
+            cols |= set(sl)
+        nnz = int(np.count_nonzero(nu[r])) + 1          # species rows + energy row
+        f_eval += 2 + len(cols) + 2 * nnz * (len(cols) + 1) + 2 * nnz
+        f_rhs += 1 + 2 * nnz
+    f_it = f_eval + 2 * N * N + 3 * N + (2.0 / 3.0) * N ** 3 + 2 * N * N + 4 * N
+    return f_it, f_rhs
+
+
+def cpu_baseline(desc, cs, dt_scalar, sample, seed=7):
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(cs.n.shape[1], size=sample, replace=False))
+    on = oracle.OracleNet(desc)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    on.integrate(cs.n[:, idx], cs.T[idx], cs.rho[idx], dt_scalar=dt_scalar, nthreads=cores)
+    el = time.perf_counter() - t0
+    return {"value": sample / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} cells drawn uniformly (seed {seed}) from the same {cs.n.shape[1]}-cell "
+                      f"batch, FP64 C oracle, OpenMP over {cores} threads, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cells", type=int, default=1 << 20)
+    ap.add_argument("--variants", default="fp64,fp32lu")
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the per-cell integration needs no communication, "
+              "and multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    desc = sy.network_h_o_n(1)
+    cs = sy.cells_h_o_n(desc, args.cells, 1)
+    dt_scalar = cs.dt_scalar
+    net = kr.Network(desc)
+    dev = torch.device("cuda", 0)
+    n0 = torch.tensor(cs.n, device=dev)
+    T0 = torch.tensor(cs.T, device=dev)
+    n = torch.empty_like(n0)
+    T = torch.empty_like(T0)
+    status = torch.empty(args.cells, dtype=torch.int32, device=dev)
+    stats = torch.empty((args.cells, 4), dtype=torch.int32, device=dev)
+    f_it, f_rhs = flops_per_unit(desc)
+    stream = torch.cuda.current_stream()
+
+    results = {}
+    for variant in args.variants.split(","):
+        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE}[variant]
+        opts = kr.default_options(precision=prec)
+
+        def step():
+            n.copy_(n0)
+            T.copy_(T0)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            kr.chem_integrate(net, n, T, dt_scalar=dt_scalar, rtol=1e-6, opts=opts,
+                              status=status, cell_stats=stats, stream=stream)
+            ev1.record(stream)
+            return ev0, ev1
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        events = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            events.append(step())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_s = np.mean([a.elapsed_time(b) for a, b in events]) * 1e-3
+        st = stats.cpu().numpy().astype(np.int64)
+        stat_codes = np.bincount(status.cpu().numpy(), minlength=3)
+        iters, acc, rej = st[:, 1].sum(), st[:, 0].sum(), st[:, 2].sum()
+        flops = iters * f_it + (acc + rej) * f_rhs
+        results[variant] = {
+            "ms_per_step": wall / args.steps * 1e3,
+            "value": args.cells * args.steps / wall,
+            "kernel_ms": kernel_s * 1e3,
+            "flops_per_launch": float(flops),
+            "achieved_tflops": flops / kernel_s / 1e12,
+            "newton_iters_per_cell": float(iters) / args.cells,
+            "substeps_per_cell": float(acc) / args.cells,
+            "status_counts": stat_codes.tolist(),
+        }
+        print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
+
+    head = results.get("fp64") or next(iter(results.values()))
+    out = {
+        "metric": "cell-steps/s implicit chem update @1e-6 rel: plain FP64 vs mixed+MLP, 1 GPU",
+        "value": head["value"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "h_o_n 9-species/24-reaction network + energy (10x10 LU), "
+                               f"{args.cells} cells, T~U[900,2500] K, 1 atm, dt=1e-4 s adaptive BE, rtol 1e-6",
+                   "cells": args.cells, "unknowns": desc.n_unknowns, "reactions": desc.n_reactions,
+                   "variant": "fp64" if "fp64" in results else args.variants},
+        "variants": results,
+        "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64,
+                     "traffic": None,
+                     "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
+                     "flops_per_error_estimate": f_rhs, "exp_log_flops": C_EXP},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc, cs, dt_scalar, min(args.cpu_sample, args.cells))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * kr.h -- C ABI of the per-cell implicit thermochemistry library (libkr.so).
+ *
+ * The library integrates, for every cell independently, the stiff
+ * thermochemical ODE system of the paper (Sec. 2.2, eq. method-ode-thermochem)
+ *
+ *     dn^i/dt = sum_r nu_ri w_r(n, T),      d eps/dt = Q(n, T),
+ *     eps = T * sum_s c_s n_s   (T = eps / c_V),
+ *
+ * over one step dt, starting from the state left by the preceding fluid step
+ * (Sec. 2.2.2).  w_r are mass-action rates with modified Arrhenius
+ * coefficients k = A T^b exp(-E/T) (Sec. 2.2.1, item 1); reverse coefficients
+ * follow from detailed balance; Q = sum_r qhat_r w_r is the chemical heat
+ * release.  Each substep is backward Euler solved by Newton iteration with the
+ * analytic Jacobian (Sec. 2.2.1, eq. method-jacobian) and a small dense LU
+ * factorisation (Sec. 2.3.2, Algorithm algo:lu-decomp); the substep size is
+ * adaptive.  Results are post-processed and failing cells are retried or
+ * reverted as in Sec. 2.2.3.  All compute runs in HIP kernels on the device.
+ *
+ * Conventions
+ *   - cgs units; energies divided by k_B (so in K).
+ *   - Every device pointer is caller-owned device memory (e.g. a torch
+ *     tensor's storage).  The library never frees caller memory.  Host
+ *     pointers are read during the call only.
+ *   - Return codes: KR_OK (0) or a negative KR_E* value.  No exception
+ *     crosses the ABI.  On error no output has been written unless stated.
+ *   - Calls are asynchronous on the given stream (NULL = the default stream)
+ *     unless a host-side output (stats, max_out) is requested, in which case
+ *     the call synchronises the stream before returning.
+ *   - A network handle is immutable after creation and may be shared by
+ *     calls on different streams, except that concurrent kr_chem_integrate
+ *     calls on one handle race on its work counter: serialise them per
+ *     handle (one stream per handle).
+ */
+#ifndef KR_H
+#define KR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *kr_stream_t; /* a hipStream_t; NULL selects the null stream */
+
+enum {
+  KR_OK = 0,
+  KR_EINVAL = -1,  /* bad argument (NULL pointer, size, non-conserving
+                      reaction, reservoir carrying other rows, ...) */
+  KR_EDEVICE = -2, /* a HIP runtime call failed */
+  KR_ENOMEM = -3,  /* host or device allocation failed */
+  KR_ECOMPILE = -4 /* the network's device code failed to compile */
+};
+
+/* ------------------------------------------------------------------------ */
+/* Network description and handle                                            */
+/* ------------------------------------------------------------------------ */
+
+/* A user-chosen set of species and reactions (the paper lets the user pick
+ * the species subset and reaction database in the input file, Sec. 2).
+ * All pointers are host memory, copied at creation.
+ *
+ *   composition [n_rows][n_species]  atoms of element row v in species s
+ *                                    (Sec. 2.1, N_{v,s}); rows at index
+ *                                    >= n_elem are charge rows (+1 per
+ *                                    positive charge, -1 for e-).
+ *   reservoir   [n_rows]             the species that absorbs each row's
+ *                                    post-processing correction (Sec. 2.2.3
+ *                                    "single-element species"); it must carry
+ *                                    only its own row.
+ *   cv          [n_species]          per-particle c_V / k_B.
+ *   h_form, s_form [n_species]       formation energy (K) and entropy (k_B)
+ *                                    at the standard-state pressure p_ref.
+ *   reac, prod  [n_reactions][3]     species of each side (multisets, -1
+ *                                    padded); every reaction must conserve
+ *                                    every row.
+ *   arr_f       [n_reactions][3]     forward (A, b, E): k = A T^b e^{-E/T}.
+ *   arr_r       [n_reactions][3]     explicit reverse (A, b, E), or NULL for
+ *                                    detailed balance: k_r = k_f / K_eq with
+ *                                    K_eq = (p_ref/(k_B T))^dnu exp(dS - dH/T).
+ *   T_min, T_max                     temperature limits applied to the input
+ *                                    state (Sec. 2.2.2).
+ * Limits: 1 <= n_species <= KR_MAX_SPECIES, 0 <= n_rows <= KR_MAX_ROWS,
+ * n_reactions >= 0. */
+#define KR_MAX_SPECIES 63
+#define KR_MAX_ROWS 8
+
+typedef struct {
+  int32_t n_species;
+  int32_t n_rows;
+  int32_t n_elem;
+  int32_t n_reactions;
+  const int32_t *composition;
+  const int32_t *reservoir;
+  const double *cv;
+  const double *h_form;
+  const double *s_form;
+  const int32_t *reac;
+  const int32_t *prod;
+  const double *arr_f;
+  const double *arr_r;
+  double p_ref;
+  double T_min;
+  double T_max;
+} kr_network_desc;
+
+typedef struct kr_network kr_network;
+
+/* Validates the description, derives reverse Arrhenius parameters, generates
+ * the network's device code and compiles it for the current device (gfx950)
+ * with hipRTC.  On success *out owns device memory until kr_network_destroy.
+ * Errors: KR_EINVAL (invalid description; *out = NULL), KR_ECOMPILE,
+ * KR_EDEVICE, KR_ENOMEM. */
+int kr_network_create(const kr_network_desc *desc, kr_network **out);
+void kr_network_destroy(kr_network *net);
+
+/* Number of unknowns per cell (n_species + 1: abundances and temperature). */
+int kr_network_unknowns(const kr_network *net);
+
+/* Derived Arrhenius table actually used: out[r][dir][3] = (A, b, E), dir 0
+ * forward, 1 reverse (host memory, n_reactions * 6 doubles). */
+int kr_network_arrhenius(const kr_network *net, double *out);
+
+/* Size of the generated device source (bytes incl. NUL) and a copy of it
+ * (truncated to buf_len - 1 bytes) when buf is not NULL. */
+int64_t kr_network_source(const kr_network *net, char *buf, int64_t buf_len);
+
+/* Validates a description and generates its device source without touching
+ * a device; with compile != 0 also compiles it with hipRTC for gfx950.  The
+ * source is copied to src_buf (truncated to src_len - 1 bytes) when src_buf
+ * is not NULL.  Returns KR_OK or the error kr_network_create would return
+ * for the same description. */
+int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
+                     int64_t src_len);
+
+/* ------------------------------------------------------------------------ */
+/* Integration                                                               */
+/* ------------------------------------------------------------------------ */
+
+enum { KR_FP64 = 0, KR_FP32LU_REFINE = 1 };  /* precision of the linear solve */
+enum { KR_ADAPTIVE = 0, KR_FIXED_STEP = 1 }; /* substep control */
+
+typedef struct {
+  int32_t precision;    /* KR_FP64 (default) or KR_FP32LU_REFINE: LU in FP32,
+                           residual, iterative refinement and the element
+                           projection in FP64 */
+  int32_t mode;         /* KR_ADAPTIVE (default) or KR_FIXED_STEP */
+  int32_t n_fixed;      /* substeps per cell in KR_FIXED_STEP (>= 1) */
+  int32_t max_newton;   /* Newton iterations per substep (default 10) */
+  int32_t max_substeps; /* substep attempts per cell and attempt (100000) */
+  int32_t reserved;
+  double floor;         /* absolute tolerance as a fraction of the nuclei
+                           density (default 1e-20) */
+  double newton_tol;    /* weighted max-norm bound on the Newton update
+                           (default 1e-3) */
+  double rho_floor;     /* density floor: cells with rho < rho_floor have
+                           their abundances scaled by rho_floor/rho
+                           (Sec. 2.2.2); default 0 = off */
+} kr_options;
+
+void kr_default_options(kr_options *opt);
+
+/* Advances every cell by its step.
+ *   states  device [n_species][ld] (SoA), in/out, cm^-3; ld >= n_cells
+ *   T       device [n_cells], in/out, K
+ *   rho     device [n_cells] g cm^-3 (used by the density floor) or NULL
+ *   dt      device [n_cells] s, or NULL to use dt_scalar for every cell
+ *   rtol    relative tolerance (> 0) of the substep error control and of
+ *           the Newton convergence test
+ *   opt     NULL for defaults
+ *   status  device [n_cells] or NULL: 0 ok, 1 ok after the retry with a
+ *           reduced first substep, 2 reverted (the cell's inputs are left
+ *           untouched: the paper's reversion to pre-evolution values)
+ *   cell_stats device [n_cells][4] int32 or NULL: accepted substeps, Newton
+ *           iterations, rejected substeps, Newton failures
+ * Errors: KR_EINVAL (NULL handle/arrays, n_cells < 0, ld < n_cells,
+ * rtol <= 0, bad options), KR_EDEVICE.  n_cells == 0 is a no-op. */
+int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
+                      int64_t ld, double *T, const double *rho,
+                      const double *dt, double dt_scalar, double rtol,
+                      const kr_options *opt, int32_t *status,
+                      int32_t *cell_stats, kr_stream_t stream);
+
+/* Per-cell conservation residual (the constant-element-abundance invariant,
+ * Sec. 2.1 eq. method-const-elem, taken per cell between two states):
+ *   resid[c] = max_v |sum_s N_vs (after - before)_s| / D_v,
+ *   D_v = sum_s |N_vs| before_s for element rows, the nuclei density for
+ *   charge rows.
+ *   before, after device [n_species][ld]; resid device [n_cells] or NULL;
+ *   max_out host pointer or NULL (then the call synchronises).
+ * Errors: KR_EINVAL, KR_EDEVICE, KR_ENOMEM. */
+int kr_element_residual(const kr_network *net, int64_t n_cells,
+                        const double *before, const double *after, int64_t ld,
+                        double *resid, double *max_out, kr_stream_t stream);
+
+/* Last error message of the calling thread (static storage). */
+const char *kr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,241 @@
+"""Python binding of libkr.so: per-cell implicit thermochemistry on MI355X.
+
+Argument marshalling only.  Every step of the integration runs in the
+library's HIP kernels; PyTorch provides device memory (tensors) and the
+stream.  The names mirror the C ABI in include/kr.h:
+
+    net = Network(desc)                       # kr_network_create
+    chem_integrate(net, states, T, ...)        # kr_chem_integrate
+    element_residual(net, before, after, ...)  # kr_element_residual
+
+``desc`` is any object with the network-description attributes
+(composition, reservoir, cv, h_form, s_form, reac, prod, arr_f, arr_r,
+n_elem, p_ref, T_min, T_max).  There is no CPU fallback: without the built
+library, or without a GPU, these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkr.so")
+
+KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
+KR_FP64, KR_FP32LU_REFINE = 0, 1
+KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
+
+EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns",
+            "kr_network_arrhenius", "kr_network_source", "kr_network_check",
+            "kr_default_options", "kr_chem_integrate", "kr_element_residual",
+            "kr_last_error")
+
+
+class KrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libkr error {code}: {msg}")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_rows", C.c_int32), ("n_elem", C.c_int32),
+                ("n_reactions", C.c_int32), ("composition", C.c_void_p),
+                ("reservoir", C.c_void_p), ("cv", C.c_void_p), ("h_form", C.c_void_p),
+                ("s_form", C.c_void_p), ("reac", C.c_void_p), ("prod", C.c_void_p),
+                ("arr_f", C.c_void_p), ("arr_r", C.c_void_p), ("p_ref", C.c_double),
+                ("T_min", C.c_double), ("T_max", C.c_double)]
+
+
+class Options(C.Structure):
+    """kr_options; defaults from kr_default_options."""
+    _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("n_fixed", C.c_int32),
+                ("max_newton", C.c_int32), ("max_substeps", C.c_int32), ("reserved", C.c_int32),
+                ("floor", C.c_double), ("newton_tol", C.c_double), ("rho_floor", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2504_04941_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        L.kr_network_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
+        L.kr_network_create.restype = C.c_int
+        L.kr_network_destroy.argtypes = [C.c_void_p]
+        L.kr_network_destroy.restype = None
+        L.kr_network_unknowns.argtypes = [C.c_void_p]
+        L.kr_network_arrhenius.argtypes = [C.c_void_p, C.c_void_p]
+        L.kr_network_source.argtypes = [C.c_void_p, C.c_char_p, C.c_int64]
+        L.kr_network_source.restype = C.c_int64
+        L.kr_network_check.argtypes = [C.POINTER(_Desc), C.c_int, C.c_char_p, C.c_int64]
+        L.kr_default_options.argtypes = [C.POINTER(Options)]
+        L.kr_default_options.restype = None
+        L.kr_chem_integrate.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                        C.POINTER(Options), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.kr_element_residual.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_int64, C.c_void_p, C.POINTER(C.c_double),
+                                          C.c_void_p]
+        L.kr_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != KR_OK:
+        raise KrError(rc, lib().kr_last_error().decode())
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().kr_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": KR_FP64, "fp32lu": KR_FP32LU_REFINE}[v]
+        if k == "mode" and isinstance(v, str):
+            v = {"adaptive": KR_ADAPTIVE, "fixed": KR_FIXED_STEP}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _pack_desc(desc):
+    keep = [np.ascontiguousarray(desc.composition, np.int32),
+            np.ascontiguousarray(desc.reservoir, np.int32),
+            np.ascontiguousarray(desc.cv, np.float64),
+            np.ascontiguousarray(desc.h_form, np.float64),
+            np.ascontiguousarray(desc.s_form, np.float64),
+            np.ascontiguousarray(desc.reac, np.int32).reshape(-1, 3),
+            np.ascontiguousarray(desc.prod, np.int32).reshape(-1, 3),
+            np.ascontiguousarray(desc.arr_f, np.float64).reshape(-1, 3)]
+    arr_r = None if desc.arr_r is None else np.ascontiguousarray(desc.arr_r, np.float64).reshape(-1, 3)
+    keep.append(arr_r)
+    d = _Desc()
+    d.n_rows, d.n_species = keep[0].shape if keep[0].ndim == 2 else (0, keep[2].shape[0])
+    d.n_elem = int(desc.n_elem)
+    d.n_reactions = keep[5].shape[0]
+    (d.composition, d.reservoir, d.cv, d.h_form, d.s_form, d.reac, d.prod,
+     d.arr_f) = (a.ctypes.data for a in keep[:8])
+    d.arr_r = None if arr_r is None else arr_r.ctypes.data
+    d.p_ref, d.T_min, d.T_max = float(desc.p_ref), float(desc.T_min), float(desc.T_max)
+    return d, keep
+
+
+def network_check(desc, compile: bool = False) -> str:
+    """Validates (and optionally compiles, without a device) a description;
+    returns the generated device source."""
+    d, keep = _pack_desc(desc)
+    buf = C.create_string_buffer(1 << 22)
+    _check(lib().kr_network_check(C.byref(d), int(bool(compile)), buf, len(buf)))
+    return buf.value.decode()
+
+
+class Network:
+    """A compiled network (kr_network_create / kr_network_destroy)."""
+
+    def __init__(self, desc):
+        d, keep = _pack_desc(desc)
+        h = C.c_void_p()
+        _check(lib().kr_network_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.n_species = d.n_species
+        self.n_reactions = d.n_reactions
+        self.n_unknowns = lib().kr_network_unknowns(h)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("network destroyed")
+        return self._h
+
+    def arrhenius(self) -> np.ndarray:
+        out = np.zeros((self.n_reactions, 2, 3))
+        _check(lib().kr_network_arrhenius(self.handle, out.ctypes.data))
+        return out
+
+    def source(self) -> str:
+        n = lib().kr_network_source(self.handle, None, 0)
+        buf = C.create_string_buffer(int(n))
+        lib().kr_network_source(self.handle, buf, n)
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kr_network_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
+                   rtol: float = 1e-6, opts: Options | None = None, status=None,
+                   cell_stats=None, stream=None) -> None:
+    """kr_chem_integrate on device tensors.
+
+    states: float64 [S, ld] with unit stride along cells (row stride = ld);
+    T, rho, dt: float64 [n_cells]; status: int32 [n_cells];
+    cell_stats: int32 [n_cells, 4].  Asynchronous on the stream."""
+    import torch
+    n_cells = int(T.numel())
+    if states.dim() != 2 or states.shape[0] != net.n_species or states.stride(1) != 1:
+        raise ValueError("states must be [n_species, ld] with unit stride along cells")
+    ld = int(states.stride(0))
+    if states.shape[1] < n_cells:
+        raise ValueError("states has fewer columns than cells")
+    if not T.is_contiguous() or (dt is not None and dt.numel() != n_cells):
+        raise ValueError("T must be contiguous; dt must have one entry per cell")
+    if cell_stats is not None and (cell_stats.numel() != 4 * n_cells or not cell_stats.is_contiguous()):
+        raise ValueError("cell_stats must be int32 [n_cells, 4]")
+    if status is not None and status.numel() != n_cells:
+        raise ValueError("status must have one entry per cell")
+    o = opts if opts is not None else default_options()
+    _check(lib().kr_chem_integrate(
+        net.handle, n_cells, _dev_ptr(states, torch.float64, "states"), ld,
+        _dev_ptr(T, torch.float64, "T"), _dev_ptr(rho, torch.float64, "rho"),
+        _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar), float(rtol), C.byref(o),
+        _dev_ptr(status, torch.int32, "status"), _dev_ptr(cell_stats, torch.int32, "cell_stats"),
+        _stream_ptr(stream)))
+
+
+def element_residual(net: Network, before, after, resid=None, want_max: bool = False,
+                     stream=None):
+    """kr_element_residual on device tensors [S, ld]; returns the host max
+    when want_max (the call then synchronises the stream)."""
+    import torch
+    n_cells = int(before.shape[1]) if resid is None else int(resid.numel())
+    if before.stride() != after.stride() or before.stride(1) != 1:
+        raise ValueError("before/after must share a [S, ld] layout with unit cell stride")
+    mx = C.c_double(0.0)
+    _check(lib().kr_element_residual(
+        net.handle, n_cells, _dev_ptr(before, torch.float64, "before"),
+        _dev_ptr(after, torch.float64, "after"), int(before.stride(0)),
+        _dev_ptr(resid, torch.float64, "resid"), C.byref(mx) if want_max else None,
+        _stream_ptr(stream)))
+    return mx.value if want_max else None

@@ -1,0 +1,745 @@
+/*
+ * kr_device.h -- device code of the per-cell implicit integrator (gfx950).
+ *
+ * This text is compiled together with the network-specific section that the
+ * network compiler generates (species count, conserved rows, heat
+ * capacities, and the straight-line rate/Jacobian function kr_eval).  The
+ * generated section defines:
+ *   KR_S, KR_NROWS, KR_NELEM            sizes
+ *   kr_comp[KR_NROWS][KR_S], kr_res[KR_NROWS], kr_cv[KR_S],
+ *   kr_atoms[KR_S], kr_T_min, kr_T_max  constant tables
+ *   kr_eval(y, g, J)                    g = (dn/dt, Q), J = dg/dy at
+ *                                       y = (n_1..n_S, T)
+ *
+ * Mapping to the hardware.  One cell per lane: the Newton matrix of a cell
+ * (N = S + 1 unknowns) lives in the lane's VGPRs, every index is a
+ * compile-time constant, and a wave advances 64 independent cells.  Lanes
+ * run a small state machine (fresh cell / start substep / Newton iteration /
+ * error check / restart) whose expensive part -- rate and Jacobian
+ * evaluation, assembly and the LU solve -- is the same code for every lane
+ * in every loop trip, so lanes at different substeps, Newton iterations or
+ * retry attempts never diverge in the heavy part.  A lane whose cell is
+ * finished claims the next cell from a global atomic counter (work
+ * stealing at lane granularity), so cells of very uneven stiffness keep all
+ * 64 lanes busy until the queue drains.
+ *
+ * The method (paper Sec. 2.2): backward Euler substeps
+ *   R_s = n_s - n_s^(n) - h f_s(y),  R_E = eps(y) - eps^(n) - h Q(y),
+ *   eps = T sum_s c_s n_s,
+ * solved by Newton iteration (M d = -R, M = dR/dy from the analytic
+ * Jacobian); adaptive step size from the local error estimate
+ * (h/2)|g(y_new) - g(y_old)|; pre-processing (Sec. 2.2.2: floors, density
+ * floor, temperature limits), post-processing (Sec. 2.2.3, three stages) and
+ * the retry-then-revert ladder (Sec. 2.2.3).
+ *
+ * Linear solve (paper Sec. 2.3.2 / Algorithm algo:lu-decomp computes an LU
+ * with implicit row scaling and partial pivoting).  Here the elimination is
+ * right-looking on the lane's registers with threshold partial pivoting: the
+ * diagonal is kept unless its scaled magnitude falls below KR_PIVOT_TAU of
+ * the best scaled candidate below it.  A row exchange is only executed
+ * (wave-uniformly, via predicated selects) when some lane of the wave needs
+ * one, since per-lane data-dependent register indexing does not exist.  The
+ * solution is the same vector as the paper's LU gives, up to rounding.
+ */
+
+#define KR_N (KR_S + 1)
+#ifndef KR_PIVOT_TAU
+#define KR_PIVOT_TAU 0.1
+#endif
+
+enum { KR_PH_NONE = 0, KR_PH_FRESH = 1, KR_PH_START = 2, KR_PH_NEWTON = 3,
+       KR_PH_CHECK = 4, KR_PH_RESTART = 5 };
+
+__device__ __forceinline__ bool kr_finite(double x) { return __builtin_isfinite(x); }
+
+__device__ __forceinline__ double kr_heat_capacity(const double (&y)[KR_N]) {
+  double c = 0.0;
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) c += kr_cv[s] * y[s];
+  return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* dense LU in registers                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Solves a x = b in place (b <- x) for one lane's matrix, by Gaussian
+ * elimination of the augmented system with threshold partial pivoting.
+ * Returns false for a zero row or a zero / non-finite pivot. */
+template <typename F>
+__device__ __forceinline__ bool kr_lu_solve(F (&a)[KR_N][KR_N], F (&b)[KR_N],
+                                            unsigned long long *swap_count) {
+  F sc[KR_N];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) {
+    F v = (F)0;
+#pragma unroll
+    for (int k = 0; k < KR_N; ++k) v = fmax(v, fabs(a[i][k]));
+    ok = ok && (v > (F)0) && kr_finite((double)v);
+    sc[i] = (F)1 / v;
+  }
+  F dinv[KR_N];
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+    F best = (F)0;
+    int bi = j;
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) {
+      F t = fabs(a[i][j]) * sc[i];
+      if (t > best) { best = t; bi = i; }
+    }
+    bool need = fabs(a[j][j]) * sc[j] < (F)KR_PIVOT_TAU * best;
+    unsigned long long mask = __ballot(need);
+    if (mask) {
+      if (swap_count && __lane_id() == (int)__builtin_ctzll(__ballot(1)))
+        atomicAdd(swap_count, (unsigned long long)__popcll(mask));
+#pragma unroll
+      for (int i = j + 1; i < KR_N; ++i) {
+        bool sw = need && bi == i;
+#pragma unroll
+        for (int k = j; k < KR_N; ++k) {
+          F u = a[j][k], w = a[i][k];
+          a[j][k] = sw ? w : u;
+          a[i][k] = sw ? u : w;
+        }
+        F u = b[j], w = b[i];
+        b[j] = sw ? w : u;
+        b[i] = sw ? u : w;
+        F su = sc[j], sw2 = sc[i];
+        sc[j] = sw ? sw2 : su;
+        sc[i] = sw ? su : sw2;
+      }
+    }
+    F piv = a[j][j];
+    ok = ok && (piv != (F)0) && kr_finite((double)piv);
+    F d = (F)1 / piv;
+    dinv[j] = d;
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) {
+      F l = a[i][j] * d;
+#pragma unroll
+      for (int k = j + 1; k < KR_N; ++k) a[i][k] = fma(-l, a[j][k], a[i][k]);
+      b[i] = fma(-l, b[j], b[i]);
+    }
+  }
+#pragma unroll
+  for (int i = KR_N - 1; i >= 0; --i) {
+    F x = b[i];
+#pragma unroll
+    for (int k = i + 1; k < KR_N; ++k) x = fma(-a[i][k], b[k], x);
+    b[i] = x * dinv[i];
+  }
+  return ok;
+}
+
+/* FP32 factorisation kept for several right-hand sides: L (unit, below the
+ * diagonal), U (on and above, with reciprocal pivots in dinv) and the row
+ * exchange taken at each column in perm. */
+__device__ __forceinline__ bool kr_lu_factor32(float (&a)[KR_N][KR_N], float (&dinv)[KR_N],
+                                               int (&perm)[KR_N],
+                                               unsigned long long *swap_count) {
+  float sc[KR_N];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) {
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KR_N; ++k) v = fmaxf(v, fabsf(a[i][k]));
+    ok = ok && (v > 0.0f) && __builtin_isfinite(v);
+    sc[i] = 1.0f / v;
+  }
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+    float best = 0.0f;
+    int bi = j;
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) {
+      float t = fabsf(a[i][j]) * sc[i];
+      if (t > best) { best = t; bi = i; }
+    }
+    bool need = fabsf(a[j][j]) * sc[j] < (float)KR_PIVOT_TAU * best;
+    perm[j] = need ? bi : j;
+    unsigned long long mask = __ballot(need);
+    if (mask) {
+      if (swap_count && __lane_id() == (int)__builtin_ctzll(__ballot(1)))
+        atomicAdd(swap_count, (unsigned long long)__popcll(mask));
+#pragma unroll
+      for (int i = j + 1; i < KR_N; ++i) {
+        bool sw = need && bi == i;
+#pragma unroll
+        for (int k = 0; k < KR_N; ++k) {
+          float u = a[j][k], w = a[i][k];
+          a[j][k] = sw ? w : u;
+          a[i][k] = sw ? u : w;
+        }
+        float su = sc[j], sw2 = sc[i];
+        sc[j] = sw ? sw2 : su;
+        sc[i] = sw ? su : sw2;
+      }
+    }
+    float piv = a[j][j];
+    ok = ok && (piv != 0.0f) && __builtin_isfinite(piv);
+    float d = 1.0f / piv;
+    dinv[j] = d;
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) {
+      float l = a[i][j] * d;
+      a[i][j] = l;
+#pragma unroll
+      for (int k = j + 1; k < KR_N; ++k) a[i][k] = fmaf(-l, a[j][k], a[i][k]);
+    }
+  }
+  return ok;
+}
+
+__device__ __forceinline__ void kr_lu_apply32(const float (&a)[KR_N][KR_N], const float (&dinv)[KR_N],
+                                              const int (&perm)[KR_N], float (&b)[KR_N]) {
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) {
+      bool sw = perm[j] == i;
+      float u = b[j], w = b[i];
+      b[j] = sw ? w : u;
+      b[i] = sw ? u : w;
+    }
+#pragma unroll
+    for (int i = j + 1; i < KR_N; ++i) b[i] = fmaf(-a[i][j], b[j], b[i]);
+  }
+#pragma unroll
+  for (int i = KR_N - 1; i >= 0; --i) {
+    float x = b[i];
+#pragma unroll
+    for (int k = i + 1; k < KR_N; ++k) x = fmaf(-a[i][k], b[k], x);
+    b[i] = x * dinv[i];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* conservation, pre- and post-processing                                    */
+/* ------------------------------------------------------------------------ */
+
+__device__ __forceinline__ double kr_nuclei(const double (&y)[KR_N]) {
+  double t = 0.0;
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) t += kr_atoms[s] * y[s];
+  return t;
+}
+
+/* Loads the cell's input and applies the pre-processing of Sec. 2.2.2:
+ * negative abundances to zero, optional density-floor rescaling, T limits.
+ * Returns false for a non-finite input (the cell is then left untouched). */
+__device__ __forceinline__ bool kr_load_input(const KrParams &p, long long c, double (&y0)[KR_N],
+                                              double &dt) {
+  bool ok = true;
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) {
+    double v = p.states[(long long)s * p.ld + c];
+    ok = ok && kr_finite(v);
+    y0[s] = v > 0.0 ? v : 0.0;
+  }
+  double T = p.T[c];
+  dt = p.dt ? p.dt[c] : p.dt_scalar;
+  ok = ok && kr_finite(T) && kr_finite(dt) && dt >= 0.0;
+  if (p.rho_floor > 0.0 && p.rho) {
+    double rho = p.rho[c];
+    if (rho > 0.0 && rho < p.rho_floor) {
+      double f = p.rho_floor / rho;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) y0[s] *= f;
+    }
+  }
+  y0[KR_S] = fmin(fmax(T, kr_T_min), kr_T_max);
+  return ok;
+}
+
+__device__ __forceinline__ double kr_element_resid(const double (&y0)[KR_N], const double (&y)[KR_N]) {
+  const double nn = kr_nuclei(y0);
+  double worst = 0.0;
+#pragma unroll
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double diff = 0.0, D = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) {
+      if (kr_comp[v][s] == 0) continue;
+      diff += kr_comp[v][s] * (y[s] - y0[s]);
+      D += (kr_comp[v][s] > 0 ? kr_comp[v][s] : -kr_comp[v][s]) * y0[s];
+    }
+    if (v >= KR_NELEM) D = nn;
+    double e = fabs(diff) / fmax(D, 1e-300);
+    if (!(e <= worst)) worst = e;
+  }
+  return worst;
+}
+
+/* Post-processing of Sec. 2.2.3: (1) negatives to zero; (2) each conserved
+ * row's reservoir absorbs the difference to the initial totals E0; (3) a
+ * reservoir left negative is refilled by breaking up the most abundant
+ * species carrying that row (with the reservoir's sign) into the reservoirs
+ * of all its rows, just enough.  All indexing is static: data-dependent
+ * choices are applied through predicated updates. */
+__device__ __forceinline__ void kr_postprocess(const double (&E0)[KR_NROWS > 0 ? KR_NROWS : 1],
+                                               double (&y)[KR_N]) {
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) y[s] = y[s] < 0.0 ? 0.0 : y[s];
+#pragma unroll
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double E = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s)
+      if (kr_comp[v][s] != 0) E += kr_comp[v][s] * y[s];
+    y[kr_res[v]] += (E0[v] - E) / kr_comp[v][kr_res[v]];
+  }
+#pragma unroll
+  for (int v = 0; v < KR_NROWS; ++v) {
+    const int rs = kr_res[v];
+    const int sr = kr_comp[v][rs] > 0 ? 1 : -1;
+    unsigned long long used = 0ull;
+    for (int it = 0; it < KR_S && y[rs] < 0.0; ++it) {
+      int best = -1;
+      double bval = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) {
+        const int a = kr_comp[v][s];
+        if (s == rs || a == 0 || (a > 0 ? 1 : -1) != sr) continue;
+        bool cand = !((used >> s) & 1ull) && y[s] > 0.0 && (best < 0 || y[s] > bval);
+        best = cand ? s : best;
+        bval = cand ? y[s] : bval;
+      }
+      if (best < 0) break;
+      used |= 1ull << best;
+      double na = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) na = (s == best) ? (double)kr_comp[v][s] : na;
+      const double need = -y[rs] * kr_comp[v][rs] / na;
+      const double x = need < bval ? need : bval;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s)
+        if (s == best) y[s] -= x;
+#pragma unroll
+      for (int u = 0; u < KR_NROWS; ++u) {
+        double au = 0.0;
+#pragma unroll
+        for (int s = 0; s < KR_S; ++s) au = (s == best) ? (double)kr_comp[u][s] : au;
+        y[kr_res[u]] += x * au / kr_comp[u][kr_res[u]];
+      }
+      if (x == need) y[rs] = 0.0;
+    }
+  }
+}
+
+/* Weighted element projection of a Newton update (FP32 form): removes the
+ * part of d_S that changes conserved-row totals, d <- d - W N^T (N W N^T)^-1
+ * N d with W = diag(max(|y_s|, atol)).  The exact Newton update of a
+ * conserving network already satisfies N d = 0; this restores it after the
+ * FP32 factorisation.  (The paper's projector P = V V^T is the W = I case.) */
+__device__ __forceinline__ void kr_project(const double (&y)[KR_N], double atol, double (&d)[KR_N]) {
+  if (KR_NROWS == 0) return;
+  constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
+  double W[KR_S];
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) W[s] = fmax(fabs(y[s]), atol);
+  double G[V][V], r[V];
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s)
+      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * d[s];
+    r[a] = t;
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      double g = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s)
+        if (kr_comp[a][s] != 0 && kr_comp[b][s] != 0) g += (double)(kr_comp[a][s] * kr_comp[b][s]) * W[s];
+      G[a][b] = g;
+    }
+  }
+  /* Cholesky of the SPD row Gram matrix */
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      double t = G[a][b];
+#pragma unroll
+      for (int k = 0; k < b; ++k) t -= G[a][k] * G[b][k];
+      if (a == b) G[a][a] = sqrt(fmax(t, 1e-300));
+      else G[a][b] = t / G[b][b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+    double t = r[a];
+#pragma unroll
+    for (int k = 0; k < a; ++k) t -= G[a][k] * r[k];
+    r[a] = t / G[a][a];
+  }
+#pragma unroll
+  for (int a = V - 1; a >= 0; --a) {
+    double t = r[a];
+#pragma unroll
+    for (int k = a + 1; k < V; ++k) t -= G[k][a] * r[k];
+    r[a] = t / G[a][a];
+  }
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) {
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a < V; ++a)
+      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * r[a];
+    d[s] -= W[s] * t;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* the integrator                                                            */
+/* ------------------------------------------------------------------------ */
+
+struct KrLane {
+  long long cell;
+  double y[KR_N], yn[KR_N], gn[KR_N];
+  double h, t, dt, atol, eps_n, prev, safety, growth;
+  int phase, attempt, k, grow, attempts, fin;
+  int acc, iters, rej, nfail;
+};
+
+__device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLane &L, const double (&y0)[KR_N]) {
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) { L.y[i] = y0[i]; L.yn[i] = y0[i]; }
+  L.eps_n = y0[KR_S] * kr_heat_capacity(y0);
+  L.t = 0.0;
+  if (p.mode == 1) {
+    L.h = L.dt / (double)p.n_fixed;
+  } else if (L.attempt == 0) {
+    L.h = L.dt; L.safety = 0.9; L.growth = 5.0;
+  } else {
+    L.h = L.dt / 100.0; L.safety = 0.5; L.growth = 2.0;
+  }
+  L.attempts = 0;
+  L.fin = 0;
+  L.phase = KR_PH_FRESH;
+}
+
+__device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLane &L, int code) {
+  if (p.status) p.status[L.cell] = code;
+  if (p.cell_stats) {
+    int *st = p.cell_stats + 4 * L.cell;
+    st[0] = L.acc; st[1] = L.iters; st[2] = L.rej; st[3] = L.nfail;
+  }
+}
+
+/* The attempt failed: retry once with a reduced first substep and tighter
+ * step control, else revert (inputs untouched, status 2). */
+__device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) {
+  if (L.attempt == 0 && p.mode == 0) {
+    double y0[KR_N], dt;
+    kr_load_input(p, L.cell, y0, dt);
+    L.attempt = 1;
+    kr_start_attempt(p, L, y0);
+  } else {
+    kr_write_outcome(p, L, 2);
+    L.phase = KR_PH_NONE;
+  }
+}
+
+__device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
+  double y0[KR_N], dt;
+  kr_load_input(p, L.cell, y0, dt);
+  const double nn = kr_nuclei(y0);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) ok = ok && kr_finite(L.y[i]);
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) ok = ok && !(L.y[s] < -1e-10 * nn);
+  ok = ok && kr_element_resid(y0, L.y) <= 1e-10;
+  if (!ok) { kr_attempt_failed(p, L); return; }
+  double E0[KR_NROWS > 0 ? KR_NROWS : 1];
+#pragma unroll
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s)
+      if (kr_comp[v][s] != 0) t += kr_comp[v][s] * y0[s];
+    E0[v] = t;
+  }
+  kr_postprocess(E0, L.y);
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = L.y[s];
+  p.T[L.cell] = L.y[KR_S];
+  kr_write_outcome(p, L, L.attempt);
+  L.phase = KR_PH_NONE;
+}
+
+/* Takes the next cell for an idle lane.  Returns false when none is left. */
+__device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
+  const unsigned long long c = atomicAdd(p.counter, 1ull);
+  if (c >= (unsigned long long)p.n_cells) return false;
+  L.cell = (long long)c;
+  L.acc = L.iters = L.rej = L.nfail = 0;
+  L.attempt = 0;
+  double y0[KR_N], dt;
+  if (!kr_load_input(p, L.cell, y0, dt)) {        /* non-finite input: revert */
+    kr_write_outcome(p, L, 2);
+    L.phase = KR_PH_NONE;
+    return true;
+  }
+  L.dt = dt;
+  if (dt == 0.0) {                                  /* nothing to integrate */
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = y0[s];
+    p.T[L.cell] = y0[KR_S];
+    kr_write_outcome(p, L, 0);
+    L.phase = KR_PH_NONE;
+    return true;
+  }
+  L.atol = p.floor * kr_nuclei(y0);
+  kr_start_attempt(p, L, y0);
+  return true;
+}
+
+__device__ __forceinline__ double kr_weight(const KrParams &p, const KrLane &L, int i, double yi) {
+  const double a = i < KR_S ? L.atol : 0.0;
+  return a + p.rtol * fmax(fabs(L.yn[i]), fabs(yi));
+}
+
+/* Newton failure: quarter the substep and restart it from y_n (adaptive);
+ * a fixed substep sequence cannot shrink, so the attempt fails. */
+__device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
+  L.nfail++;
+  if (p.mode == 1) { kr_attempt_failed(p, L); return; }
+  L.h *= 0.25;
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) L.y[i] = L.yn[i];
+  L.phase = KR_PH_RESTART;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
+  KrLane L;
+  L.cell = -1;
+  L.phase = KR_PH_NONE;
+  bool exhausted = false;
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) { L.y[i] = 1.0; L.yn[i] = 1.0; L.gn[i] = 0.0; }
+  L.h = L.t = L.dt = L.atol = L.eps_n = L.prev = 0.0;
+  L.safety = 0.9; L.growth = 5.0;
+  L.attempt = L.k = L.grow = L.attempts = L.fin = 0;
+  L.acc = L.iters = L.rej = L.nfail = 0;
+
+  for (;;) {
+    if (L.phase == KR_PH_NONE && !exhausted) exhausted = !kr_claim(p, L);
+    const bool active = L.phase != KR_PH_NONE;
+    if (!__any(active)) {
+      if (__all(exhausted)) break;
+      continue;
+    }
+    if (!active) continue;
+
+    /* rates and Jacobian at the lane's current point */
+    double g[KR_N], J[KR_N][KR_N];
+    kr_eval(L.y, g, J);
+    const double cv = kr_heat_capacity(L.y);
+    const int ph = L.phase;
+
+    if (ph == KR_PH_CHECK) {
+      if (p.mode == 1) {                              /* fixed sequence */
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) L.yn[i] = L.y[i];
+        L.eps_n = L.y[KR_S] * cv;
+        L.acc++;
+        if (L.acc >= p.n_fixed) kr_finish_cell(p, L);
+        else L.phase = KR_PH_START;
+      } else {
+        double err = 0.0;
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) {
+          const double gi = i < KR_S ? g[i] : g[KR_S] / cv;
+          const double e = fabs(0.5 * L.h * (gi - L.gn[i])) / kr_weight(p, L, i, L.y[i]);
+          err = e > err ? e : err;
+        }
+        if (!kr_finite(err)) {
+          L.rej++;
+          L.h *= 0.2;
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) L.y[i] = L.yn[i];
+          L.phase = KR_PH_RESTART;
+        } else if (err <= 1.0) {
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) {
+            L.yn[i] = L.y[i];
+            L.gn[i] = i < KR_S ? g[i] : g[KR_S] / cv;
+          }
+          L.eps_n = L.y[KR_S] * cv;
+          L.acc++;
+          if (L.fin) {
+            kr_finish_cell(p, L);
+          } else {
+            L.t += L.h;
+            L.h *= fmin(L.growth, fmax(0.2, L.safety / sqrt(fmax(err, 1e-10))));
+            L.phase = KR_PH_START;
+          }
+        } else {
+          L.rej++;
+          L.h *= fmax(0.2, L.safety / sqrt(err));
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) L.y[i] = L.yn[i];
+          L.phase = KR_PH_RESTART;
+        }
+      }
+    } else if (ph == KR_PH_FRESH) {
+#pragma unroll
+      for (int i = 0; i < KR_N; ++i) L.gn[i] = i < KR_S ? g[i] : g[KR_S] / cv;
+      L.phase = KR_PH_START;
+    }
+
+    if (L.phase == KR_PH_START) {                     /* y == y_n here */
+      bool go = true;
+      if (p.mode == 0) {
+        if (L.attempts >= p.max_substeps) {
+          go = false;
+        } else {
+          L.fin = 0;
+          if (L.h >= L.dt - L.t) { L.h = L.dt - L.t; L.fin = 1; }
+          else if (L.h < 1e-12 * L.dt) go = false;
+        }
+      }
+      if (go) {
+        L.attempts++;
+        L.k = 0;
+        L.grow = 0;
+        L.prev = __builtin_inf();
+        L.phase = KR_PH_NEWTON;
+      } else {
+        kr_attempt_failed(p, L);
+      }
+    }
+
+    if (L.phase == KR_PH_NEWTON) {
+      /* residual and Newton matrix M = dR/dy, assembled over J in place */
+      const double h = L.h;
+      double b[KR_N];
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) b[s] = -(L.y[s] - L.yn[s] - h * g[s]);
+      b[KR_S] = -(L.y[KR_S] * cv - L.eps_n - h * g[KR_S]);
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s)
+#pragma unroll
+        for (int m = 0; m < KR_N; ++m) J[s][m] = (s == m ? 1.0 : 0.0) - h * J[s][m];
+#pragma unroll
+      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = kr_cv[m] * L.y[KR_S] - h * J[KR_S][m];
+      J[KR_S][KR_S] = cv - h * J[KR_S][KR_S];
+      L.iters++;
+
+      bool ok;
+      if (!MIXED) {
+        ok = kr_lu_solve<double>(J, b, p.pivot_swaps);
+      } else {
+        /* FP32 LU of the row-equilibrated matrix; FP64 residual and
+         * iterative refinement against the FP64 matrix; FP64 projection */
+        float a32[KR_N][KR_N], dinv[KR_N];
+        int perm[KR_N];
+        double rs[KR_N];
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < KR_N; ++k) v = fmax(v, fabs(J[i][k]));
+          rs[i] = v > 0.0 ? 1.0 / v : 0.0;
+#pragma unroll
+          for (int k = 0; k < KR_N; ++k) a32[i][k] = (float)(J[i][k] * rs[i]);
+        }
+        ok = kr_lu_factor32(a32, dinv, perm, p.pivot_swaps);
+        double d[KR_N];
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) d[i] = 0.0;
+        double r[KR_N];
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) r[i] = b[i];
+        bool conv = false;
+#pragma unroll 1
+        for (int sweep = 0; sweep < 4 && ok; ++sweep) {
+          float c32[KR_N];
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) c32[i] = (float)(r[i] * rs[i]);
+          kr_lu_apply32(a32, dinv, perm, c32);
+          double cn = 0.0;
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) {
+            const double c = (double)c32[i];
+            d[i] += c;
+            const double e = fabs(c) / kr_weight(p, L, i, L.y[i]);
+            cn = e > cn ? e : cn;
+          }
+          if (!kr_finite(cn)) { ok = false; break; }
+          if (sweep > 0 && cn <= 1e-6) { conv = true; break; }
+          /* r = b - M d in FP64 */
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) {
+            double t = b[i];
+#pragma unroll
+            for (int k = 0; k < KR_N; ++k) t = fma(-J[i][k], d[k], t);
+            r[i] = t;
+          }
+        }
+        if (__any(ok && !conv)) {
+          /* refinement did not contract: FP64 LU for those lanes */
+          if (ok && !conv) {
+            ok = kr_lu_solve<double>(J, b, p.pivot_swaps);
+#pragma unroll
+            for (int i = 0; i < KR_N; ++i) d[i] = b[i];
+          }
+        }
+        kr_project(L.y, L.atol, d);
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) b[i] = d[i];
+      }
+
+      if (!ok) {
+        kr_newton_failed(p, L);
+      } else {
+        bool fin = true;
+        double norm = 0.0;
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) {
+          L.y[i] += b[i];
+          fin = fin && kr_finite(b[i]) && kr_finite(L.y[i]);
+        }
+        if (!fin || !(L.y[KR_S] > 0.0)) {
+          kr_newton_failed(p, L);
+        } else {
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) {
+            const double e = fabs(b[i]) / kr_weight(p, L, i, L.y[i]);
+            norm = e > norm ? e : norm;
+          }
+          if (norm <= p.newton_tol) {
+            L.phase = KR_PH_CHECK;
+          } else {
+            bool failed = false;
+            if (norm > L.prev) { if (++L.grow >= 2) failed = true; }
+            else L.grow = 0;
+            L.prev = norm;
+            if (!failed && ++L.k >= p.max_newton) failed = true;
+            if (failed) kr_newton_failed(p, L);
+          }
+        }
+      }
+    }
+
+    if (L.phase == KR_PH_RESTART) L.phase = KR_PH_START;
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(64) kr_integrate_fp64(KrParams p) {
+  kr_integrate_body<false>(p);
+}
+
+extern "C" __global__ void __launch_bounds__(64) kr_integrate_fp32lu(KrParams p) {
+  kr_integrate_body<true>(p);
+}
+
+extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}

@@ -1,0 +1,548 @@
+/*
+ * kr_lib.hip -- host runtime and C ABI of libkr.so (see include/kr.h).
+ *
+ *   network compiler  validates a network description (conservation of every
+ *                     element/charge row, reservoir rows), derives reverse
+ *                     Arrhenius parameters by detailed balance, and generates
+ *                     straight-line device code for the network's rates and
+ *                     analytic Jacobian (paper Sec. 2.2.1, eq.
+ *                     method-jacobian); the generated code plus the
+ *                     integrator template (kr_device.h) is compiled for gfx950
+ *                     with hipRTC, so every matrix index is a compile-time
+ *                     constant and a cell's Newton matrix stays in registers.
+ *   integrate         launches the persistent per-lane integrator over all
+ *                     cells (work claimed through an atomic counter).
+ *   element residual  an ahead-of-time kernel for the per-cell conservation
+ *                     check (Sec. 2.1, eq. method-const-elem).
+ */
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/kr.h"
+#include "kr_params.h"
+
+static const char *kDeviceSource =
+#include "kr_device_src.inc"
+    ;
+static const char *kParamsSource =
+#include "kr_params_src.inc"
+    ;
+
+static const double kBoltzmann = 1.380649e-16; /* erg / K */
+
+/* ------------------------------------------------------------------------ */
+/* errors                                                                    */
+/* ------------------------------------------------------------------------ */
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+extern "C" const char *kr_last_error(void) { return g_err.c_str(); }
+
+/* ------------------------------------------------------------------------ */
+/* network                                                                   */
+/* ------------------------------------------------------------------------ */
+
+struct kr_network {
+  int S = 0, n_rows = 0, n_elem = 0, R = 0;
+  std::vector<int32_t> comp, res, reac, prod;
+  std::vector<double> cv, h, s, par; /* par: [R][2][3] */
+  double p_ref = 0.0, T_min = 0.0, T_max = 0.0;
+  std::string source;
+  hipModule_t module = nullptr;
+  hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
+  int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
+  unsigned long long *d_counter = nullptr;
+  unsigned long long *d_max = nullptr;
+  int32_t *d_comp = nullptr;
+};
+
+static std::string hexd(double v) {
+  char b[64];
+  snprintf(b, sizeof b, "%a", v);
+  return b;
+}
+
+/* Validates and copies the description; derives the reverse parameters. */
+static int build_tables(const kr_network_desc *d, kr_network *n) {
+  if (!d) return fail(KR_EINVAL, "null description");
+  const int S = d->n_species, V = d->n_rows, R = d->n_reactions;
+  if (S < 1 || S > KR_MAX_SPECIES) return fail(KR_EINVAL, "n_species %d out of [1, %d]", S, KR_MAX_SPECIES);
+  if (V < 0 || V > KR_MAX_ROWS) return fail(KR_EINVAL, "n_rows %d out of [0, %d]", V, KR_MAX_ROWS);
+  if (d->n_elem < 0 || d->n_elem > V) return fail(KR_EINVAL, "n_elem %d out of [0, n_rows]", d->n_elem);
+  if (R < 0) return fail(KR_EINVAL, "n_reactions < 0");
+  if ((V && (!d->composition || !d->reservoir)) || !d->cv || !d->h_form || !d->s_form ||
+      (R && (!d->reac || !d->prod || !d->arr_f)))
+    return fail(KR_EINVAL, "null table in description");
+  if (!(d->p_ref > 0.0) || !std::isfinite(d->p_ref)) return fail(KR_EINVAL, "p_ref must be > 0");
+  if (!(d->T_min > 0.0) || !(d->T_max >= d->T_min) || !std::isfinite(d->T_max))
+    return fail(KR_EINVAL, "bad temperature limits");
+  n->S = S; n->n_rows = V; n->n_elem = d->n_elem; n->R = R;
+  n->p_ref = d->p_ref; n->T_min = d->T_min; n->T_max = d->T_max;
+  n->comp.assign(d->composition, d->composition + (size_t)V * S);
+  n->res.assign(d->reservoir, d->reservoir + V);
+  n->cv.assign(d->cv, d->cv + S);
+  n->h.assign(d->h_form, d->h_form + S);
+  n->s.assign(d->s_form, d->s_form + S);
+  n->reac.assign(d->reac, d->reac + 3 * (size_t)R);
+  n->prod.assign(d->prod, d->prod + 3 * (size_t)R);
+  for (int i = 0; i < S; ++i)
+    if (!std::isfinite(n->cv[i]) || n->cv[i] < 0.0 || !std::isfinite(n->h[i]) || !std::isfinite(n->s[i]))
+      return fail(KR_EINVAL, "species %d: non-finite or negative thermodynamic data", i);
+  for (int v = 0; v < V; ++v) {
+    const int rs = n->res[v];
+    if (rs < 0 || rs >= S || n->comp[(size_t)v * S + rs] == 0)
+      return fail(KR_EINVAL, "row %d: reservoir %d does not carry the row", v, rs);
+    for (int u = 0; u < V; ++u)
+      if (u != v && n->comp[(size_t)u * S + rs] != 0)
+        return fail(KR_EINVAL, "row %d: reservoir %d also carries row %d", v, rs, u);
+  }
+  n->par.assign(6 * (size_t)R, 0.0);
+  for (int r = 0; r < R; ++r) {
+    std::vector<int> nu(S, 0);
+    for (int k = 0; k < 3; ++k) {
+      const int a = n->reac[3 * r + k], b = n->prod[3 * r + k];
+      if (a < -1 || a >= S || b < -1 || b >= S) return fail(KR_EINVAL, "reaction %d: species index out of range", r);
+      if (a >= 0) nu[a] -= 1;
+      if (b >= 0) nu[b] += 1;
+    }
+    for (int v = 0; v < V; ++v) {
+      long t = 0;
+      for (int sp = 0; sp < S; ++sp) t += (long)n->comp[(size_t)v * S + sp] * nu[sp];
+      if (t != 0) return fail(KR_EINVAL, "reaction %d does not conserve row %d", r, v);
+    }
+    double dH = 0.0, dS = 0.0;
+    int dnu = 0;
+    for (int sp = 0; sp < S; ++sp) {
+      dH += nu[sp] * n->h[sp];
+      dS += nu[sp] * n->s[sp];
+      dnu += nu[sp];
+    }
+    double *pf = &n->par[6 * (size_t)r], *pr = pf + 3;
+    for (int k = 0; k < 3; ++k) pf[k] = d->arr_f[3 * r + k];
+    if (d->arr_r) {
+      for (int k = 0; k < 3; ++k) pr[k] = d->arr_r[3 * r + k];
+    } else {
+      /* k_r = k_f / K_eq, K_eq = (p_ref / (k_B T))^dnu exp(dS - dH/T) */
+      pr[0] = pf[0] * std::pow(kBoltzmann / n->p_ref, dnu) * std::exp(-dS);
+      pr[1] = pf[1] + dnu;
+      pr[2] = pf[2] - dH;
+    }
+    for (int k = 0; k < 6; ++k)
+      if (!std::isfinite(pf[k])) return fail(KR_EINVAL, "reaction %d: non-finite Arrhenius parameter", r);
+    if (pf[0] < 0.0 || pr[0] < 0.0) return fail(KR_EINVAL, "reaction %d: negative pre-factor", r);
+  }
+  return KR_OK;
+}
+
+/* One side's rate and its derivatives, as source text.  slots: species of
+ * the side (multiset). */
+struct SideCode {
+  std::string q;                        /* q = k * prod y[slot] */
+  std::vector<std::pair<int, std::string>> dq; /* (m, dq/dy_m) */
+};
+
+static SideCode side_code(const std::string &k, const int *slots) {
+  SideCode c;
+  std::vector<int> sl;
+  for (int i = 0; i < 3; ++i)
+    if (slots[i] >= 0) sl.push_back(slots[i]);
+  c.q = k;
+  for (int m : sl) c.q += " * y[" + std::to_string(m) + "]";
+  std::vector<int> distinct;
+  for (int m : sl)
+    if (std::find(distinct.begin(), distinct.end(), m) == distinct.end()) distinct.push_back(m);
+  for (int m : distinct) {
+    /* product rule over the slots holding m */
+    std::string sum;
+    for (size_t i = 0; i < sl.size(); ++i) {
+      if (sl[i] != m) continue;
+      std::string t = k;
+      for (size_t j = 0; j < sl.size(); ++j)
+        if (j != i) t += " * y[" + std::to_string(sl[j]) + "]";
+      sum += sum.empty() ? t : " + " + t;
+    }
+    c.dq.push_back({m, "(" + sum + ")"});
+  }
+  return c;
+}
+
+static std::string coef(int nu) {
+  if (nu == 1) return "";
+  if (nu == -1) return "-";
+  return std::to_string(nu) + ".0 * ";
+}
+
+/* The network-specific section of the device source. */
+static std::string generate_network(const kr_network *n) {
+  const int S = n->S, V = n->n_rows;
+  std::string o;
+  o += "/* generated network section: " + std::to_string(S) + " species, " + std::to_string(V) +
+       " conserved rows, " + std::to_string(n->R) + " reactions */\n";
+  o += "#define KR_S " + std::to_string(S) + "\n";
+  o += "#define KR_NROWS " + std::to_string(V) + "\n";
+  o += "#define KR_NELEM " + std::to_string(n->n_elem) + "\n";
+  const int VV = V > 0 ? V : 1;
+  o += "__device__ static constexpr int kr_comp[" + std::to_string(VV) + "][" + std::to_string(S) + "] = {";
+  for (int v = 0; v < VV; ++v) {
+    o += "{";
+    for (int s = 0; s < S; ++s) o += std::to_string(V ? n->comp[(size_t)v * S + s] : 0) + (s + 1 < S ? "," : "");
+    o += "}";
+    o += v + 1 < VV ? "," : "";
+  }
+  o += "};\n__device__ static constexpr int kr_res[" + std::to_string(VV) + "] = {";
+  for (int v = 0; v < VV; ++v) o += std::to_string(V ? n->res[v] : 0) + (v + 1 < VV ? "," : "");
+  o += "};\n__device__ static constexpr double kr_cv[" + std::to_string(S) + "] = {";
+  for (int s = 0; s < S; ++s) o += hexd(n->cv[s]) + (s + 1 < S ? "," : "");
+  o += "};\n__device__ static constexpr double kr_atoms[" + std::to_string(S) + "] = {";
+  for (int s = 0; s < S; ++s) {
+    int a = 0;
+    for (int v = 0; v < n->n_elem; ++v) a += n->comp[(size_t)v * S + s];
+    o += std::to_string(a) + ".0" + (s + 1 < S ? "," : "");
+  }
+  o += "};\n";
+  o += "__device__ static constexpr double kr_T_min = " + hexd(n->T_min) + ";\n";
+  o += "__device__ static constexpr double kr_T_max = " + hexd(n->T_max) + ";\n";
+
+  /* rates and analytic Jacobian, one block per reaction */
+  o += "__device__ __forceinline__ void kr_eval(const double (&y)[KR_S + 1], double (&g)[KR_S + 1],\n"
+       "                                        double (&J)[KR_S + 1][KR_S + 1]) {\n"
+       "#pragma unroll\n  for (int i = 0; i <= KR_S; ++i) {\n    g[i] = 0.0;\n"
+       "#pragma unroll\n    for (int j = 0; j <= KR_S; ++j) J[i][j] = 0.0;\n  }\n"
+       "  const double T = y[KR_S];\n  const double lnT = log(T);\n  const double iT = 1.0 / T;\n";
+  const std::string ST = std::to_string(S);
+  for (int r = 0; r < n->R; ++r) {
+    const double *pf = &n->par[6 * (size_t)r], *pr = pf + 3;
+    std::vector<int> nu(S, 0);
+    for (int k = 0; k < 3; ++k) {
+      if (n->reac[3 * r + k] >= 0) nu[n->reac[3 * r + k]] -= 1;
+      if (n->prod[3 * r + k] >= 0) nu[n->prod[3 * r + k]] += 1;
+    }
+    double dH = 0.0;
+    for (int s = 0; s < S; ++s) dH += nu[s] * n->h[s];
+    const double qhat = -dH;
+    o += "  { /* reaction " + std::to_string(r) + " */\n";
+    std::vector<std::pair<int, std::string>> dw; /* dw/dy_m terms */
+    std::string w, dwdT;
+    for (int dir = 0; dir < 2; ++dir) {
+      const double *pp = dir ? pr : pf;
+      if (pp[0] == 0.0) continue;
+      const std::string k = dir ? "kr" : "kf";
+      o += "    const double " + k + " = " + hexd(pp[0]) + " * exp(" + hexd(pp[1]) + " * lnT - " +
+           hexd(pp[2]) + " * iT);\n";
+      SideCode c = side_code(k, dir ? &n->prod[3 * r] : &n->reac[3 * r]);
+      const std::string q = dir ? "qr" : "qf";
+      o += "    const double " + q + " = " + c.q + ";\n";
+      o += "    const double " + q + "T = " + q + " * (" + hexd(pp[1]) + " + " + hexd(pp[2]) + " * iT) * iT;\n";
+      w += (dir ? " - " : (w.empty() ? "" : " + ")) + q;
+      dwdT += (dir ? " - " : (dwdT.empty() ? "" : " + ")) + q + "T";
+      for (auto &t : c.dq) {
+        auto it = std::find_if(dw.begin(), dw.end(), [&](const std::pair<int, std::string> &e) { return e.first == t.first; });
+        const std::string term = (dir ? " - " : " + ") + t.second;
+        if (it == dw.end()) dw.push_back({t.first, term});
+        else it->second += term;
+      }
+    }
+    if (w.empty()) { o += "  }\n"; continue; }
+    if (w[0] == ' ') w = "0.0" + w;
+    if (dwdT[0] == ' ') dwdT = "0.0" + dwdT;
+    o += "    const double w = " + w + ";\n";
+    o += "    const double wT = " + dwdT + ";\n";
+    for (auto &t : dw) o += "    const double w" + std::to_string(t.first) + " = 0.0" + t.second + ";\n";
+    for (int s = 0; s < S; ++s) {
+      if (!nu[s]) continue;
+      const std::string c = coef(nu[s]), ss = std::to_string(s);
+      o += "    g[" + ss + "] += " + c + "w;\n";
+      for (auto &t : dw) o += "    J[" + ss + "][" + std::to_string(t.first) + "] += " + c + "w" + std::to_string(t.first) + ";\n";
+      o += "    J[" + ss + "][" + ST + "] += " + c + "wT;\n";
+    }
+    if (qhat != 0.0) {
+      const std::string qh = hexd(qhat);
+      o += "    g[" + ST + "] += " + qh + " * w;\n";
+      for (auto &t : dw) o += "    J[" + ST + "][" + std::to_string(t.first) + "] += " + qh + " * w" + std::to_string(t.first) + ";\n";
+      o += "    J[" + ST + "][" + ST + "] += " + qh + " * wT;\n";
+    }
+    o += "  }\n";
+  }
+  o += "}\n";
+  return o;
+}
+
+static int compile_source(const std::string &src, std::vector<char> &code, std::string &log) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "kr_network.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return fail(KR_ECOMPILE, "hiprtcCreateProgram failed");
+  const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  size_t ls = 0;
+  hiprtcGetProgramLogSize(prog, &ls);
+  log.assign(ls + 1, '\0');
+  if (ls) hiprtcGetProgramLog(prog, &log[0]);
+  if (rc != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return fail(KR_ECOMPILE, "hipRTC compile failed: %.900s", log.c_str());
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code.resize(cs);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  return KR_OK;
+}
+
+static std::string full_source(const kr_network *n) {
+  return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
+         kParamsSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
+}
+
+static void release(kr_network *n) {
+  if (!n) return;
+  if (n->d_counter) (void)hipFree(n->d_counter);
+  if (n->d_max) (void)hipFree(n->d_max);
+  if (n->d_comp) (void)hipFree(n->d_comp);
+  if (n->module) (void)hipModuleUnload(n->module);
+  delete n;
+}
+
+extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) {
+  if (!out) return fail(KR_EINVAL, "null output handle");
+  *out = nullptr;
+  kr_network *n = new (std::nothrow) kr_network;
+  if (!n) return fail(KR_ENOMEM, "out of host memory");
+  int rc = build_tables(desc, n);
+  if (rc != KR_OK) { delete n; return rc; }
+  n->source = full_source(n);
+  std::vector<char> code;
+  std::string log;
+  rc = compile_source(n->source, code, log);
+  if (rc != KR_OK) { delete n; return rc; }
+  hipError_t e;
+#define CREATE_TRY(expr)                                                              \
+  do {                                                                                \
+    e = (expr);                                                                       \
+    if (e != hipSuccess) {                                                            \
+      rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                   \
+      release(n);                                                                     \
+      return rc;                                                                      \
+    }                                                                                 \
+  } while (0)
+  CREATE_TRY(hipGetDevice(&n->device));
+  CREATE_TRY(hipDeviceGetAttribute(&n->cu_count, hipDeviceAttributeMultiprocessorCount, n->device));
+  CREATE_TRY(hipModuleLoadData(&n->module, code.data()));
+  CREATE_TRY(hipModuleGetFunction(&n->f_fp64, n->module, "kr_integrate_fp64"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_fp32, n->module, "kr_integrate_fp32lu"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_reset, n->module, "kr_reset_counter"));
+  CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
+  CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
+  CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
+  CREATE_TRY(hipMalloc(&n->d_max, sizeof(unsigned long long)));
+  const size_t cb = sizeof(int32_t) * (n->comp.size() ? n->comp.size() : 1);
+  CREATE_TRY(hipMalloc(&n->d_comp, cb));
+  if (!n->comp.empty())
+    CREATE_TRY(hipMemcpy(n->d_comp, n->comp.data(), sizeof(int32_t) * n->comp.size(), hipMemcpyHostToDevice));
+#undef CREATE_TRY
+  *out = n;
+  return KR_OK;
+}
+
+extern "C" void kr_network_destroy(kr_network *net) { release(net); }
+
+extern "C" int kr_network_unknowns(const kr_network *net) { return net ? net->S + 1 : KR_EINVAL; }
+
+extern "C" int kr_network_arrhenius(const kr_network *net, double *out) {
+  if (!net || !out) return fail(KR_EINVAL, "null argument");
+  std::memcpy(out, net->par.data(), sizeof(double) * net->par.size());
+  return KR_OK;
+}
+
+extern "C" int64_t kr_network_source(const kr_network *net, char *buf, int64_t buf_len) {
+  if (!net) return fail(KR_EINVAL, "null network");
+  const int64_t need = (int64_t)net->source.size() + 1;
+  if (buf && buf_len > 0) {
+    const int64_t m = buf_len < need ? buf_len - 1 : need - 1;
+    std::memcpy(buf, net->source.data(), (size_t)m);
+    buf[m] = '\0';
+  }
+  return need;
+}
+
+/* Validation and code generation (and optionally the hipRTC compile) of a
+ * description without touching a device: used by build checks and tests on
+ * hosts without a GPU.  Returns KR_OK or the error create would return. */
+extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
+                                int64_t src_len) {
+  kr_network n;
+  int rc = build_tables(desc, &n);
+  if (rc != KR_OK) return rc;
+  const std::string src = full_source(&n);
+  if (src_buf && src_len > 0) {
+    const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
+    std::memcpy(src_buf, src.data(), m);
+    src_buf[m] = '\0';
+  }
+  if (!compile) return KR_OK;
+  std::vector<char> code;
+  std::string log;
+  return compile_source(src, code, log);
+}
+
+/* ------------------------------------------------------------------------ */
+/* integration                                                               */
+/* ------------------------------------------------------------------------ */
+
+extern "C" void kr_default_options(kr_options *o) {
+  if (!o) return;
+  o->precision = KR_FP64;
+  o->mode = KR_ADAPTIVE;
+  o->n_fixed = 1;
+  o->max_newton = 10;
+  o->max_substeps = 100000;
+  o->reserved = 0;
+  o->floor = 1e-20;
+  o->newton_tol = 1e-3;
+  o->rho_floor = 0.0;
+}
+
+extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states, int64_t ld,
+                                 double *T, const double *rho, const double *dt, double dt_scalar,
+                                 double rtol, const kr_options *opt, int32_t *status,
+                                 int32_t *cell_stats, kr_stream_t stream) {
+  if (!net) return fail(KR_EINVAL, "null network");
+  if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
+  kr_options o;
+  kr_default_options(&o);
+  if (opt) o = *opt;
+  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+      (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
+      o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
+      !(o.rho_floor >= 0.0))
+    return fail(KR_EINVAL, "bad options");
+  if (n_cells == 0) return KR_OK;
+  if (!states || !T) return fail(KR_EINVAL, "null state arrays");
+  if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+  HIP_TRY(hipSetDevice(net->device));
+  hipStream_t st = (hipStream_t)stream;
+
+  KrParams p;
+  p.n_cells = n_cells; p.states = states; p.ld = ld; p.T = T; p.rho = rho; p.dt = dt;
+  p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
+  p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
+  p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
+  p.counter = net->d_counter; p.pivot_swaps = nullptr;
+
+  unsigned long long *cnt = net->d_counter;
+  void *rargs[] = {&cnt};
+  HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
+  hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
+  const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
+  long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
+  const long long need = (n_cells + 63) / 64;
+  if (blocks > need) blocks = need;
+  if (blocks < 1) blocks = 1;
+  void *args[] = {&p};
+  HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
+  return KR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* element residual (ahead-of-time kernel)                                   */
+/* ------------------------------------------------------------------------ */
+
+__global__ void __launch_bounds__(256) kr_element_residual_kernel(
+    int S, int nrows, int nelem, const int32_t *__restrict__ comp, long long n,
+    const double *__restrict__ before, const double *__restrict__ after, long long ld,
+    double *__restrict__ resid, unsigned long long *__restrict__ maxbits) {
+  double local = 0.0;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    double nn = 0.0;
+    for (int s = 0; s < S; ++s) {
+      int a = 0;
+      for (int v = 0; v < nelem; ++v) a += comp[v * S + s];
+      nn += a * before[s * ld + c];
+    }
+    double worst = 0.0;
+    for (int v = 0; v < nrows; ++v) {
+      double diff = 0.0, D = 0.0;
+      for (int s = 0; s < S; ++s) {
+        const int a = comp[v * S + s];
+        if (!a) continue;
+        const double b = before[s * ld + c];
+        diff += a * (after[s * ld + c] - b);
+        D += (a > 0 ? a : -a) * b;
+      }
+      if (v >= nelem) D = nn;
+      const double e = fabs(diff) / fmax(D, 1e-300);
+      if (!(e <= worst)) worst = e;
+    }
+    if (resid) resid[c] = worst;
+    if (!(worst <= local)) local = worst;
+  }
+  if (!maxbits) return;
+  /* non-negative doubles (and NaN) order like their bit patterns */
+  unsigned long long bits = __double_as_longlong(local);
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(bits, off);
+    bits = o > bits ? o : bits;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(maxbits, bits);
+}
+
+__global__ void kr_zero_u64(unsigned long long *p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const double *before,
+                                   const double *after, int64_t ld, double *resid, double *max_out,
+                                   kr_stream_t stream) {
+  if (!net) return fail(KR_EINVAL, "null network");
+  if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld");
+  if (n_cells > 0 && (!before || !after)) return fail(KR_EINVAL, "null state arrays");
+  HIP_TRY(hipSetDevice(net->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (max_out) {
+    hipLaunchKernelGGL(kr_zero_u64, dim3(1), dim3(64), 0, st, net->d_max);
+    HIP_TRY(hipGetLastError());
+  }
+  if (n_cells > 0) {
+    long long blocks = (n_cells + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(kr_element_residual_kernel, dim3((unsigned)blocks), dim3(256), 0, st, net->S,
+                       net->n_rows, net->n_elem, net->d_comp, (long long)n_cells, before, after,
+                       (long long)ld, resid, max_out ? net->d_max : nullptr);
+    HIP_TRY(hipGetLastError());
+  }
+  if (max_out) {
+    unsigned long long bits = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, net->d_max, sizeof bits, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(max_out, &bits, sizeof bits);
+  }
+  return KR_OK;
+}

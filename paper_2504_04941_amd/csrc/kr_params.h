@@ -1,0 +1,31 @@
+/*
+ * kr_params.h -- launch parameters shared by the host runtime and the
+ * device code of the per-cell integrator (the device source is compiled at
+ * network creation, so this struct is the one contract between the two).
+ */
+#ifndef KR_PARAMS_H
+#define KR_PARAMS_H
+
+struct KrParams {
+  long long n_cells;
+  double *states;        /* [S][ld] in/out */
+  long long ld;
+  double *T;             /* [n_cells] in/out */
+  const double *rho;     /* [n_cells] or null */
+  const double *dt;      /* [n_cells] or null */
+  double dt_scalar;
+  double rtol;
+  double floor;          /* atol = floor * nuclei density */
+  double newton_tol;
+  double rho_floor;
+  int max_newton;
+  int max_substeps;
+  int mode;              /* 0 adaptive, 1 fixed */
+  int n_fixed;
+  int *status;           /* [n_cells] or null */
+  int *cell_stats;       /* [n_cells][4] or null */
+  unsigned long long *counter; /* next unclaimed cell */
+  unsigned long long *pivot_swaps; /* diagnostic: row exchanges taken, or null */
+};
+
+#endif
