@@ -52,6 +52,24 @@ enum { KR_PH_NONE = 0, KR_PH_FRESH = 1, KR_PH_START = 2, KR_PH_NEWTON = 3,
 
 __device__ __forceinline__ bool kr_finite(double x) { return __builtin_isfinite(x); }
 
+/* 1/x from the hardware estimate refined by two Newton steps (within an ulp
+ * or so; not correctly rounded).  Used where a value feeds a comparison or a
+ * scaling, never for results that are compared bit-for-bit. */
+__device__ __forceinline__ double kr_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+/* A lane's slot in a per-wave LDS array laid out [index][lane], so that a
+ * wave's 64 accesses to one index hit 64 consecutive doubles. */
+struct KrSlot {
+  double *base;
+  __device__ __forceinline__ double &operator[](int i) const { return base[i * 64]; }
+};
+
 __device__ __forceinline__ double kr_heat_capacity(const double (&y)[KR_N]) {
   double c = 0.0;
 #pragma unroll
@@ -66,30 +84,29 @@ __device__ __forceinline__ double kr_heat_capacity(const double (&y)[KR_N]) {
 /* Solves a x = b in place (b <- x) for one lane's matrix, by Gaussian
  * elimination of the augmented system with threshold partial pivoting.
  * Returns false for a zero row or a zero / non-finite pivot. */
-template <typename F>
-__device__ __forceinline__ bool kr_lu_solve(F (&a)[KR_N][KR_N], F (&b)[KR_N],
+__device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)[KR_N],
                                             unsigned long long *swap_count) {
-  F sc[KR_N];
+  /* inverse row scales only steer the pivot choice: FP32 is plenty */
+  float sc[KR_N];
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) {
-    F v = (F)0;
+    double v = 0.0;
 #pragma unroll
     for (int k = 0; k < KR_N; ++k) v = fmax(v, fabs(a[i][k]));
-    ok = ok && (v > (F)0) && kr_finite((double)v);
-    sc[i] = (F)1 / v;
+    ok = ok && (v > 0.0) && kr_finite(v);
+    sc[i] = __builtin_amdgcn_rcpf((float)v);
   }
-  F dinv[KR_N];
 #pragma unroll
   for (int j = 0; j < KR_N; ++j) {
-    F best = (F)0;
+    float best = 0.0f;
     int bi = j;
 #pragma unroll
     for (int i = j + 1; i < KR_N; ++i) {
-      F t = fabs(a[i][j]) * sc[i];
+      float t = (float)fabs(a[i][j]) * sc[i];
       if (t > best) { best = t; bi = i; }
     }
-    bool need = fabs(a[j][j]) * sc[j] < (F)KR_PIVOT_TAU * best;
+    bool need = (float)fabs(a[j][j]) * sc[j] < (float)KR_PIVOT_TAU * best;
     unsigned long long mask = __ballot(need);
     if (mask) {
       if (swap_count && __lane_id() == (int)__builtin_ctzll(__ballot(1)))
@@ -99,25 +116,25 @@ __device__ __forceinline__ bool kr_lu_solve(F (&a)[KR_N][KR_N], F (&b)[KR_N],
         bool sw = need && bi == i;
 #pragma unroll
         for (int k = j; k < KR_N; ++k) {
-          F u = a[j][k], w = a[i][k];
+          double u = a[j][k], w = a[i][k];
           a[j][k] = sw ? w : u;
           a[i][k] = sw ? u : w;
         }
-        F u = b[j], w = b[i];
+        double u = b[j], w = b[i];
         b[j] = sw ? w : u;
         b[i] = sw ? u : w;
-        F su = sc[j], sw2 = sc[i];
+        float su = sc[j], sw2 = sc[i];
         sc[j] = sw ? sw2 : su;
         sc[i] = sw ? su : sw2;
       }
     }
-    F piv = a[j][j];
-    ok = ok && (piv != (F)0) && kr_finite((double)piv);
-    F d = (F)1 / piv;
-    dinv[j] = d;
+    const double piv = a[j][j];
+    ok = ok && (piv != 0.0) && kr_finite(piv);
+    const double d = kr_rcp(piv);
+    a[j][j] = d;                      /* reciprocal pivot kept on the diagonal */
 #pragma unroll
     for (int i = j + 1; i < KR_N; ++i) {
-      F l = a[i][j] * d;
+      const double l = a[i][j] * d;
 #pragma unroll
       for (int k = j + 1; k < KR_N; ++k) a[i][k] = fma(-l, a[j][k], a[i][k]);
       b[i] = fma(-l, b[j], b[i]);
@@ -125,10 +142,10 @@ __device__ __forceinline__ bool kr_lu_solve(F (&a)[KR_N][KR_N], F (&b)[KR_N],
   }
 #pragma unroll
   for (int i = KR_N - 1; i >= 0; --i) {
-    F x = b[i];
+    double x = b[i];
 #pragma unroll
     for (int k = i + 1; k < KR_N; ++k) x = fma(-a[i][k], b[k], x);
-    b[i] = x * dinv[i];
+    b[i] = x * a[i][i];
   }
   return ok;
 }
@@ -399,7 +416,7 @@ __device__ __forceinline__ void kr_project(const double (&y)[KR_N], double atol,
 
 struct KrLane {
   long long cell;
-  double y[KR_N], yn[KR_N], gn[KR_N];
+  KrSlot y, yn, gn;             /* iterate, substep start and its rates: LDS */
   double h, t, dt, atol, eps_n, prev, safety, growth;
   int phase, attempt, k, grow, attempts, fin;
   int acc, iters, rej, nfail;
@@ -445,15 +462,17 @@ __device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) 
 }
 
 __device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
-  double y0[KR_N], dt;
+  double y0[KR_N], dt, y[KR_N];
   kr_load_input(p, L.cell, y0, dt);
+#pragma unroll
+  for (int i = 0; i < KR_N; ++i) y[i] = L.y[i];
   const double nn = kr_nuclei(y0);
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < KR_N; ++i) ok = ok && kr_finite(L.y[i]);
+  for (int i = 0; i < KR_N; ++i) ok = ok && kr_finite(y[i]);
 #pragma unroll
-  for (int s = 0; s < KR_S; ++s) ok = ok && !(L.y[s] < -1e-10 * nn);
-  ok = ok && kr_element_resid(y0, L.y) <= 1e-10;
+  for (int s = 0; s < KR_S; ++s) ok = ok && !(y[s] < -1e-10 * nn);
+  ok = ok && kr_element_resid(y0, y) <= 1e-10;
   if (!ok) { kr_attempt_failed(p, L); return; }
   double E0[KR_NROWS > 0 ? KR_NROWS : 1];
 #pragma unroll
@@ -464,10 +483,10 @@ __device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
       if (kr_comp[v][s] != 0) t += kr_comp[v][s] * y0[s];
     E0[v] = t;
   }
-  kr_postprocess(E0, L.y);
+  kr_postprocess(E0, y);
 #pragma unroll
-  for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = L.y[s];
-  p.T[L.cell] = L.y[KR_S];
+  for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = y[s];
+  p.T[L.cell] = y[KR_S];
   kr_write_outcome(p, L, L.attempt);
   L.phase = KR_PH_NONE;
 }
@@ -517,9 +536,13 @@ __device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
 
 template <bool MIXED>
 __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
+  __shared__ double s_y[KR_N * 64], s_yn[KR_N * 64], s_gn[KR_N * 64];
   KrLane L;
   L.cell = -1;
   L.phase = KR_PH_NONE;
+  L.y.base = s_y + threadIdx.x;
+  L.yn.base = s_yn + threadIdx.x;
+  L.gn.base = s_gn + threadIdx.x;
   bool exhausted = false;
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) { L.y[i] = 1.0; L.yn[i] = 1.0; L.gn[i] = 0.0; }
@@ -538,16 +561,19 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
     if (!active) continue;
 
     /* rates and Jacobian at the lane's current point */
-    double g[KR_N], J[KR_N][KR_N];
-    kr_eval(L.y, g, J);
-    const double cv = kr_heat_capacity(L.y);
+    double g[KR_N], J[KR_N][KR_N], yv[KR_N];
+#pragma unroll
+    for (int i = 0; i < KR_N; ++i) yv[i] = L.y[i];
+    kr_eval(yv, g, J);
+    const double cv = kr_heat_capacity(yv);
+    const double icv = kr_rcp(cv);
     const int ph = L.phase;
 
     if (ph == KR_PH_CHECK) {
       if (p.mode == 1) {                              /* fixed sequence */
 #pragma unroll
-        for (int i = 0; i < KR_N; ++i) L.yn[i] = L.y[i];
-        L.eps_n = L.y[KR_S] * cv;
+        for (int i = 0; i < KR_N; ++i) L.yn[i] = yv[i];
+        L.eps_n = yv[KR_S] * cv;
         L.acc++;
         if (L.acc >= p.n_fixed) kr_finish_cell(p, L);
         else L.phase = KR_PH_START;
@@ -555,8 +581,8 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         double err = 0.0;
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) {
-          const double gi = i < KR_S ? g[i] : g[KR_S] / cv;
-          const double e = fabs(0.5 * L.h * (gi - L.gn[i])) / kr_weight(p, L, i, L.y[i]);
+          const double gi = i < KR_S ? g[i] : g[KR_S] * icv;
+          const double e = fabs(0.5 * L.h * (gi - L.gn[i])) * kr_rcp(kr_weight(p, L, i, yv[i]));
           err = e > err ? e : err;
         }
         if (!kr_finite(err)) {
@@ -568,10 +594,10 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         } else if (err <= 1.0) {
 #pragma unroll
           for (int i = 0; i < KR_N; ++i) {
-            L.yn[i] = L.y[i];
-            L.gn[i] = i < KR_S ? g[i] : g[KR_S] / cv;
+            L.yn[i] = yv[i];
+            L.gn[i] = i < KR_S ? g[i] : g[KR_S] * icv;
           }
-          L.eps_n = L.y[KR_S] * cv;
+          L.eps_n = yv[KR_S] * cv;
           L.acc++;
           if (L.fin) {
             kr_finish_cell(p, L);
@@ -590,7 +616,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       }
     } else if (ph == KR_PH_FRESH) {
 #pragma unroll
-      for (int i = 0; i < KR_N; ++i) L.gn[i] = i < KR_S ? g[i] : g[KR_S] / cv;
+      for (int i = 0; i < KR_N; ++i) L.gn[i] = i < KR_S ? g[i] : g[KR_S] * icv;
       L.phase = KR_PH_START;
     }
 
@@ -621,20 +647,20 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       const double h = L.h;
       double b[KR_N];
 #pragma unroll
-      for (int s = 0; s < KR_S; ++s) b[s] = -(L.y[s] - L.yn[s] - h * g[s]);
-      b[KR_S] = -(L.y[KR_S] * cv - L.eps_n - h * g[KR_S]);
+      for (int s = 0; s < KR_S; ++s) b[s] = -(yv[s] - L.yn[s] - h * g[s]);
+      b[KR_S] = -(yv[KR_S] * cv - L.eps_n - h * g[KR_S]);
 #pragma unroll
       for (int s = 0; s < KR_S; ++s)
 #pragma unroll
         for (int m = 0; m < KR_N; ++m) J[s][m] = (s == m ? 1.0 : 0.0) - h * J[s][m];
 #pragma unroll
-      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = kr_cv[m] * L.y[KR_S] - h * J[KR_S][m];
+      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = kr_cv[m] * yv[KR_S] - h * J[KR_S][m];
       J[KR_S][KR_S] = cv - h * J[KR_S][KR_S];
       L.iters++;
 
       bool ok;
       if (!MIXED) {
-        ok = kr_lu_solve<double>(J, b, p.pivot_swaps);
+        ok = kr_lu_solve(J, b, p.pivot_swaps);
       } else {
         /* FP32 LU of the row-equilibrated matrix; FP64 residual and
          * iterative refinement against the FP64 matrix; FP64 projection */
@@ -669,7 +695,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
           for (int i = 0; i < KR_N; ++i) {
             const double c = (double)c32[i];
             d[i] += c;
-            const double e = fabs(c) / kr_weight(p, L, i, L.y[i]);
+            const double e = fabs(c) * kr_rcp(kr_weight(p, L, i, L.y[i]));
             cn = e > cn ? e : cn;
           }
           if (!kr_finite(cn)) { ok = false; break; }
@@ -686,12 +712,15 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         if (__any(ok && !conv)) {
           /* refinement did not contract: FP64 LU for those lanes */
           if (ok && !conv) {
-            ok = kr_lu_solve<double>(J, b, p.pivot_swaps);
+            ok = kr_lu_solve(J, b, p.pivot_swaps);
 #pragma unroll
             for (int i = 0; i < KR_N; ++i) d[i] = b[i];
           }
         }
-        kr_project(L.y, L.atol, d);
+        double yc[KR_N];
+#pragma unroll
+        for (int i = 0; i < KR_N; ++i) yc[i] = L.y[i];
+        kr_project(yc, L.atol, d);
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) b[i] = d[i];
       }
@@ -703,17 +732,15 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         double norm = 0.0;
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) {
-          L.y[i] += b[i];
-          fin = fin && kr_finite(b[i]) && kr_finite(L.y[i]);
+          const double yi = L.y[i] + b[i];
+          L.y[i] = yi;
+          fin = fin && kr_finite(b[i]) && kr_finite(yi);
+          const double e = fabs(b[i]) * kr_rcp(kr_weight(p, L, i, yi));
+          norm = e > norm ? e : norm;
         }
         if (!fin || !(L.y[KR_S] > 0.0)) {
           kr_newton_failed(p, L);
         } else {
-#pragma unroll
-          for (int i = 0; i < KR_N; ++i) {
-            const double e = fabs(b[i]) / kr_weight(p, L, i, L.y[i]);
-            norm = e > norm ? e : norm;
-          }
           if (norm <= p.newton_tol) {
             L.phase = KR_PH_CHECK;
           } else {
@@ -732,11 +759,15 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
   }
 }
 
-extern "C" __global__ void __launch_bounds__(64) kr_integrate_fp64(KrParams p) {
+#ifndef KR_WAVES_PER_EU
+#define KR_WAVES_PER_EU 1
+#endif
+
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp64(KrParams p) {
   kr_integrate_body<false>(p);
 }
 
-extern "C" __global__ void __launch_bounds__(64) kr_integrate_fp32lu(KrParams p) {
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp32lu(KrParams p) {
   kr_integrate_body<true>(p);
 }
 

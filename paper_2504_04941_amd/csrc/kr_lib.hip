@@ -296,8 +296,12 @@ static int compile_source(const std::string &src, std::vector<char> &code, std::
   hiprtcProgram prog;
   if (hiprtcCreateProgram(&prog, src.c_str(), "kr_network.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
     return fail(KR_ECOMPILE, "hiprtcCreateProgram failed");
+  /* Machine-level loop-invariant code motion is off: it would hoist every
+   * FP64 constant of the rate and exp/log code out of the persistent loop
+   * and spill them (hundreds of registers for a 10-unknown network). */
   const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-mllvm", "-disable-machine-licm"};
   hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
   size_t ls = 0;
   hiprtcGetProgramLogSize(prog, &ls);
@@ -315,9 +319,25 @@ static int compile_source(const std::string &src, std::vector<char> &code, std::
   return KR_OK;
 }
 
+/* Occupancy target of the integrator kernels (waves per SIMD the compiler
+ * budgets registers for).  One wave: from ~8 unknowns the lane's FP64
+ * Newton matrix alone needs most of 256 VGPRs, and even at 6 unknowns a
+ * two-wave budget forces scratch spills that cost more than the extra wave
+ * hides (measured: 390 vs 490 ms on 2^18 five-species cells).
+ * KR_WAVES_PER_EU in the environment overrides (tuning experiments). */
+static int waves_per_eu(const kr_network *n) {
+  if (const char *e = getenv("KR_WAVES_PER_EU")) {
+    const int w = atoi(e);
+    if (w >= 1 && w <= 8) return w;
+  }
+  (void)n;
+  return 1;
+}
+
 static std::string full_source(const kr_network *n) {
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         kParamsSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
+         "#define KR_WAVES_PER_EU " + std::to_string(waves_per_eu(n)) + "\n" + kParamsSource + "\n" +
+         generate_network(n) + "\n" + kDeviceSource;
 }
 
 static void release(kr_network *n) {
