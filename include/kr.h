@@ -156,6 +156,16 @@ typedef struct {
   double rho_floor;     /* density floor: cells with rho < rho_floor have
                            their abundances scaled by rho_floor/rho
                            (Sec. 2.2.2); default 0 = off */
+  const double *guess;  /* device [n_species + 1][guess_ld] or NULL: Newton
+                           starting point for each cell's first substep of
+                           its first attempt (e.g. from kr_guess_predict);
+                           if Newton fails from it, the same substep is
+                           redone from the plain starting point (the
+                           substep's initial state) before any step cut */
+  int64_t guess_ld;
+  unsigned long long *counters; /* device [4] or NULL, accumulated: substeps
+                           started from a guess, guess fallbacks, row
+                           exchanges taken by the LU, reserved */
 } kr_options;
 
 void kr_default_options(kr_options *opt);
@@ -192,6 +202,88 @@ int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
 int kr_element_residual(const kr_network *net, int64_t n_cells,
                         const double *before, const double *after, int64_t ld,
                         double *resid, double *max_out, kr_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned Newton guess                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* A small MLP that maps (log10 of each abundance over the nuclei density,
+ * floored at 1e-20; log10 T; log10 h) to the change of those logarithms
+ * (species and T) over one backward-Euler substep of length h.  Its output
+ * is only a Newton starting point (kr_options.guess); the Newton residual
+ * of the method decides the result.  The paper names a learned solver as
+ * the direction for acceleration (Sec. 5, DeepODE).
+ *
+ * Architecture: (S + 2) inputs -> `layers` x [Linear(hidden) + GELU(tanh)]
+ * -> Linear(S + 1).  BF16 weights and activations in every product (MFMA),
+ * FP32 accumulation, FP32 biases, gradients and Adam master weights.
+ * Inputs and targets are standardised by per-column mean and standard
+ * deviation (normalisation block: mu_in[16], sd_in[16], mu_out[16],
+ * sd_out[16]).  Parameter layout (FP32, flat): for each linear layer l,
+ * W_l [fan_out][fan_in] row-major, then b_l [fan_out].
+ * Supports networks of at most 14 species. */
+typedef struct kr_guess kr_guess;
+
+typedef struct {
+  int64_t steps;   /* Adam steps in this call */
+  int32_t batch;   /* rows per step, drawn uniformly with replacement */
+  int32_t reserved;
+  float lr, lr_min;        /* cosine decay from lr to lr_min over the call */
+  float beta1, beta2, eps; /* Adam */
+  uint64_t seed;           /* batch sampling stream; 0 = consecutive blocks
+                              of rows (deterministic) */
+} kr_train_opts;
+
+/* Allocates the model on the network's device, initialised uniformly in
+ * +-1/sqrt(fan_in) from a splitmix64 stream of `seed`.  Errors: KR_EINVAL
+ * (sizes, more than 14 species), KR_EDEVICE. */
+int kr_guess_create(const kr_network *net, int32_t hidden, int32_t layers,
+                    uint64_t seed, kr_guess **out);
+void kr_guess_destroy(kr_guess *g);
+int64_t kr_guess_num_params(const kr_guess *g);
+/* FP32 master parameters to / from host memory (kr_guess_num_params floats;
+ * set also re-rounds the BF16 copies).  Synchronous. */
+int kr_guess_get_params(const kr_guess *g, float *host);
+int kr_guess_set_params(kr_guess *g, const float *host);
+/* Normalisation block (64 floats, host).  Synchronous. */
+int kr_guess_get_normalization(const kr_guess *g, float *norm64);
+int kr_guess_set_normalization(kr_guess *g, const float *norm64);
+
+/* Raw features X [n][S+2] (device FP32) of n cells (states SoA [S][ld],
+ * T [n], step dt [n] or dt_scalar). */
+int kr_guess_features(const kr_guess *g, int64_t n, const double *states,
+                      int64_t ld, const double *T, const double *dt,
+                      double dt_scalar, float *X, kr_stream_t stream);
+/* Raw targets Y [n][S+1] (device FP32): change of the logarithms between
+ * two states of the same cells (same layout and ld). */
+int kr_guess_targets(const kr_guess *g, int64_t n, const double *before,
+                     const double *T_before, const double *after,
+                     const double *T_after, int64_t ld, float *Y,
+                     kr_stream_t stream);
+/* Sets the normalisation from the column means and standard deviations of
+ * X and Y (n >= 2 rows, device). */
+int kr_guess_fit_normalization(kr_guess *g, int64_t n, const float *X,
+                               const float *Y, kr_stream_t stream);
+/* Loss and gradient (FP32, device, kr_guess_num_params floats, may be NULL)
+ * of the first B rows of X, Y without updating; *loss (host, may be NULL)
+ * is the mean squared error in standardised units (synchronises). */
+int kr_guess_gradients(kr_guess *g, int32_t B, const float *X, const float *Y,
+                       float *grads, double *loss, kr_stream_t stream);
+/* opts->steps Adam steps on batches drawn from the n rows of X, Y; *loss
+ * (host, may be NULL) is the last batch's loss (synchronises). */
+int kr_guess_train(kr_guess *g, int64_t n, const float *X, const float *Y,
+                   const kr_train_opts *opts, double *last_loss,
+                   kr_stream_t stream);
+/* Standardised outputs out [n][S+1] (device FP32) for raw features X. */
+int kr_guess_forward(kr_guess *g, int64_t n, const float *X, float *out,
+                     kr_stream_t stream);
+/* The Newton starting point for one substep of length dt of each cell:
+ * guess [S+1][guess_ld] (device FP64; species rows then T).  X_scratch:
+ * device FP32 [n][S+2] workspace (caller-owned). */
+int kr_guess_predict(kr_guess *g, int64_t n, const double *states, int64_t ld,
+                     const double *T, const double *dt, double dt_scalar,
+                     float *X_scratch, double *guess, int64_t guess_ld,
+                     kr_stream_t stream);
 
 /* Last error message of the calling thread (static storage). */
 const char *kr_last_error(void);

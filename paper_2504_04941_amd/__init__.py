@@ -30,7 +30,11 @@ KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check",
             "kr_default_options", "kr_chem_integrate", "kr_element_residual",
-            "kr_last_error")
+            "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
+            "kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
+            "kr_guess_set_normalization", "kr_guess_features", "kr_guess_targets",
+            "kr_guess_fit_normalization", "kr_guess_gradients", "kr_guess_train",
+            "kr_guess_forward", "kr_guess_predict")
 
 
 class KrError(RuntimeError):
@@ -52,7 +56,15 @@ class Options(C.Structure):
     """kr_options; defaults from kr_default_options."""
     _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("n_fixed", C.c_int32),
                 ("max_newton", C.c_int32), ("max_substeps", C.c_int32), ("reserved", C.c_int32),
-                ("floor", C.c_double), ("newton_tol", C.c_double), ("rho_floor", C.c_double)]
+                ("floor", C.c_double), ("newton_tol", C.c_double), ("rho_floor", C.c_double),
+                ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p)]
+
+
+class TrainOpts(C.Structure):
+    """kr_train_opts."""
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int32), ("reserved", C.c_int32),
+                ("lr", C.c_float), ("lr_min", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -84,6 +96,22 @@ def lib():
                                           C.c_int64, C.c_void_p, C.POINTER(C.c_double),
                                           C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
+        vp, i64 = C.c_void_p, C.c_int64
+        L.kr_guess_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(vp)]
+        L.kr_guess_destroy.argtypes = [vp]
+        L.kr_guess_destroy.restype = None
+        L.kr_guess_num_params.argtypes = [vp]
+        L.kr_guess_num_params.restype = i64
+        for name in ("kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
+                     "kr_guess_set_normalization"):
+            getattr(L, name).argtypes = [vp, vp]
+        L.kr_guess_features.argtypes = [vp, i64, vp, i64, vp, vp, C.c_double, vp, vp]
+        L.kr_guess_targets.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp]
+        L.kr_guess_fit_normalization.argtypes = [vp, i64, vp, vp, vp]
+        L.kr_guess_gradients.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(C.c_double), vp]
+        L.kr_guess_train.argtypes = [vp, i64, vp, vp, C.POINTER(TrainOpts), C.POINTER(C.c_double), vp]
+        L.kr_guess_forward.argtypes = [vp, i64, vp, vp, vp]
+        L.kr_guess_predict.argtypes = [vp, i64, vp, i64, vp, vp, C.c_double, vp, vp, i64, vp]
         _lib = L
     return _lib
 
@@ -239,3 +267,150 @@ def element_residual(net: Network, before, after, resid=None, want_max: bool = F
         _dev_ptr(resid, torch.float64, "resid"), C.byref(mx) if want_max else None,
         _stream_ptr(stream)))
     return mx.value if want_max else None
+
+
+class GuessModel:
+    """The learned Newton guess (kr_guess_*): an MLP with BF16-MFMA training
+    and inference kernels.  Tensors are device tensors; features X are
+    float32 [n, S+2], targets Y float32 [n, S+1]."""
+
+    def __init__(self, net: Network, hidden: int = 256, layers: int = 3, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().kr_guess_create(net.handle, int(hidden), int(layers), int(seed), C.byref(h)))
+        self._h = h
+        self.S = net.n_species
+        self.n_in, self.n_out = self.S + 2, self.S + 1
+        self.hidden, self.layers = hidden, layers
+        self.n_params = int(lib().kr_guess_num_params(h))
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("guess model destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kr_guess_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        _check(lib().kr_guess_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, w) -> None:
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.size == self.n_params
+        _check(lib().kr_guess_set_params(self.handle, w.ctypes.data))
+
+    def get_normalization(self) -> np.ndarray:
+        out = np.zeros(64, np.float32)
+        _check(lib().kr_guess_get_normalization(self.handle, out.ctypes.data))
+        return out
+
+    def set_normalization(self, norm64) -> None:
+        norm64 = np.ascontiguousarray(norm64, np.float32)
+        _check(lib().kr_guess_set_normalization(self.handle, norm64.ctypes.data))
+
+    def layer_slices(self):
+        """[(W slice, b slice, fan_out, fan_in)] of the flat parameter vector."""
+        out, off = [], 0
+        for l in range(self.layers + 1):
+            fi = self.n_in if l == 0 else self.hidden
+            fo = self.n_out if l == self.layers else self.hidden
+            out.append((slice(off, off + fi * fo), slice(off + fi * fo, off + fi * fo + fo), fo, fi))
+            off += fi * fo + fo
+        return out
+
+    def features(self, states, T, dt=None, dt_scalar=0.0, X=None, stream=None):
+        import torch
+        n = int(T.numel())
+        if X is None:
+            X = torch.empty((n, self.n_in), dtype=torch.float32, device=T.device)
+        _check(lib().kr_guess_features(self.handle, n, _dev_ptr(states, torch.float64, "states"),
+                                       int(states.stride(0)), _dev_ptr(T, torch.float64, "T"),
+                                       _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar),
+                                       _dev_ptr(X, torch.float32, "X"), _stream_ptr(stream)))
+        return X
+
+    def targets(self, before, T_before, after, T_after, Y=None, stream=None):
+        import torch
+        n = int(T_before.numel())
+        if Y is None:
+            Y = torch.empty((n, self.n_out), dtype=torch.float32, device=T_before.device)
+        assert before.stride() == after.stride()
+        _check(lib().kr_guess_targets(self.handle, n, _dev_ptr(before, torch.float64, "before"),
+                                      _dev_ptr(T_before, torch.float64, "T_before"),
+                                      _dev_ptr(after, torch.float64, "after"),
+                                      _dev_ptr(T_after, torch.float64, "T_after"),
+                                      int(before.stride(0)), _dev_ptr(Y, torch.float32, "Y"),
+                                      _stream_ptr(stream)))
+        return Y
+
+    def fit_normalization(self, X, Y, stream=None):
+        import torch
+        _check(lib().kr_guess_fit_normalization(self.handle, int(X.shape[0]),
+                                                _dev_ptr(X, torch.float32, "X"),
+                                                _dev_ptr(Y, torch.float32, "Y"), _stream_ptr(stream)))
+
+    def gradients(self, X, Y, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        loss = C.c_double(0.0)
+        _check(lib().kr_guess_gradients(self.handle, int(X.shape[0]), _dev_ptr(X, torch.float32, "X"),
+                                        _dev_ptr(Y, torch.float32, "Y"), _dev_ptr(g, torch.float32, "g"),
+                                        C.byref(loss), _stream_ptr(stream)))
+        return g, loss.value
+
+    def train(self, X, Y, steps, batch=4096, lr=1e-3, lr_min=1e-5, seed=1, beta1=0.9,
+              beta2=0.999, eps=1e-8, stream=None) -> float:
+        import torch
+        o = TrainOpts(int(steps), int(batch), 0, float(lr), float(lr_min), float(beta1),
+                      float(beta2), float(eps), int(seed))
+        loss = C.c_double(0.0)
+        _check(lib().kr_guess_train(self.handle, int(X.shape[0]), _dev_ptr(X, torch.float32, "X"),
+                                    _dev_ptr(Y, torch.float32, "Y"), C.byref(o), C.byref(loss),
+                                    _stream_ptr(stream)))
+        return loss.value
+
+    def forward(self, X, stream=None):
+        import torch
+        out = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        _check(lib().kr_guess_forward(self.handle, int(X.shape[0]), _dev_ptr(X, torch.float32, "X"),
+                                      _dev_ptr(out, torch.float32, "out"), _stream_ptr(stream)))
+        return out
+
+    def predict(self, states, T, dt=None, dt_scalar=0.0, guess=None, X_scratch=None, stream=None):
+        """Newton starting points [S+1, n] (float64) for one substep of
+        length dt of each cell."""
+        import torch
+        n = int(T.numel())
+        if guess is None:
+            guess = torch.empty((self.S + 1, n), dtype=torch.float64, device=T.device)
+        if X_scratch is None:
+            X_scratch = torch.empty((n, self.n_in), dtype=torch.float32, device=T.device)
+        _check(lib().kr_guess_predict(self.handle, n, _dev_ptr(states, torch.float64, "states"),
+                                      int(states.stride(0)), _dev_ptr(T, torch.float64, "T"),
+                                      _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar),
+                                      _dev_ptr(X_scratch, torch.float32, "X"),
+                                      _dev_ptr(guess, torch.float64, "guess"), int(guess.stride(0)),
+                                      _stream_ptr(stream)))
+        return guess
+
+
+def guess_options(guess, counters=None, **kw) -> Options:
+    """Options that start each cell's first substep from `guess` [S+1, ld]."""
+    import torch
+    o = default_options(**kw)
+    o.guess = _dev_ptr(guess, torch.float64, "guess")
+    o.guess_ld = int(guess.stride(0))
+    if counters is not None:
+        o.counters = counters.data_ptr()
+    return o

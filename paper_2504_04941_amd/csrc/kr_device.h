@@ -48,7 +48,7 @@
 #endif
 
 enum { KR_PH_NONE = 0, KR_PH_FRESH = 1, KR_PH_START = 2, KR_PH_NEWTON = 3,
-       KR_PH_CHECK = 4, KR_PH_RESTART = 5 };
+       KR_PH_CHECK = 4, KR_PH_RESTART = 5, KR_PH_GUESS = 6 };
 
 __device__ __forceinline__ bool kr_finite(double x) { return __builtin_isfinite(x); }
 
@@ -419,6 +419,7 @@ struct KrLane {
   KrSlot y, yn, gn;             /* iterate, substep start and its rates: LDS */
   double h, t, dt, atol, eps_n, prev, safety, growth;
   int phase, attempt, k, grow, attempts, fin;
+  int gstate;                   /* 1 guess pending, 2 Newton running from it */
   int acc, iters, rej, nfail;
 };
 
@@ -454,6 +455,7 @@ __device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) 
     double y0[KR_N], dt;
     kr_load_input(p, L.cell, y0, dt);
     L.attempt = 1;
+    L.gstate = 0;
     kr_start_attempt(p, L, y0);
   } else {
     kr_write_outcome(p, L, 2);
@@ -498,6 +500,7 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
   L.cell = (long long)c;
   L.acc = L.iters = L.rej = L.nfail = 0;
   L.attempt = 0;
+  L.gstate = p.guess ? 1 : 0;
   double y0[KR_N], dt;
   if (!kr_load_input(p, L.cell, y0, dt)) {        /* non-finite input: revert */
     kr_write_outcome(p, L, 2);
@@ -526,6 +529,17 @@ __device__ __forceinline__ double kr_weight(const KrParams &p, const KrLane &L, 
 /* Newton failure: quarter the substep and restart it from y_n (adaptive);
  * a fixed substep sequence cannot shrink, so the attempt fails. */
 __device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
+  if (L.gstate == 2) {
+    /* Newton failed from the learned guess: redo the same substep from
+     * the plain starting point, without cutting the step */
+    L.gstate = 0;
+    if (p.counters) atomicAdd(&p.counters[1], 1ull);
+#pragma unroll
+    for (int i = 0; i < KR_N; ++i) L.y[i] = L.yn[i];
+    L.attempts--;
+    L.phase = KR_PH_RESTART;
+    return;
+  }
   L.nfail++;
   if (p.mode == 1) { kr_attempt_failed(p, L); return; }
   L.h *= 0.25;
@@ -548,8 +562,9 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
   for (int i = 0; i < KR_N; ++i) { L.y[i] = 1.0; L.yn[i] = 1.0; L.gn[i] = 0.0; }
   L.h = L.t = L.dt = L.atol = L.eps_n = L.prev = 0.0;
   L.safety = 0.9; L.growth = 5.0;
-  L.attempt = L.k = L.grow = L.attempts = L.fin = 0;
+  L.attempt = L.k = L.grow = L.attempts = L.fin = L.gstate = 0;
   L.acc = L.iters = L.rej = L.nfail = 0;
+  unsigned long long *swaps = p.counters ? &p.counters[2] : nullptr;
 
   for (;;) {
     if (L.phase == KR_PH_NONE && !exhausted) exhausted = !kr_claim(p, L);
@@ -637,9 +652,20 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         L.grow = 0;
         L.prev = __builtin_inf();
         L.phase = KR_PH_NEWTON;
+        if (L.gstate == 1) {
+          /* first substep: start Newton from the learned guess (evaluated
+           * on the next trip) */
+#pragma unroll
+          for (int i = 0; i < KR_N; ++i) L.y[i] = p.guess[(long long)i * p.guess_ld + L.cell];
+          L.gstate = 2;
+          L.phase = KR_PH_GUESS;
+          if (p.counters) atomicAdd(&p.counters[0], 1ull);
+        }
       } else {
         kr_attempt_failed(p, L);
       }
+    } else if (ph == KR_PH_GUESS) {
+      L.phase = KR_PH_NEWTON;
     }
 
     if (L.phase == KR_PH_NEWTON) {
@@ -660,7 +686,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 
       bool ok;
       if (!MIXED) {
-        ok = kr_lu_solve(J, b, p.pivot_swaps);
+        ok = kr_lu_solve(J, b, swaps);
       } else {
         /* FP32 LU of the row-equilibrated matrix; FP64 residual and
          * iterative refinement against the FP64 matrix; FP64 projection */
@@ -676,7 +702,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
           for (int k = 0; k < KR_N; ++k) a32[i][k] = (float)(J[i][k] * rs[i]);
         }
-        ok = kr_lu_factor32(a32, dinv, perm, p.pivot_swaps);
+        ok = kr_lu_factor32(a32, dinv, perm, swaps);
         double d[KR_N];
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) d[i] = 0.0;
@@ -712,7 +738,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         if (__any(ok && !conv)) {
           /* refinement did not contract: FP64 LU for those lanes */
           if (ok && !conv) {
-            ok = kr_lu_solve(J, b, p.pivot_swaps);
+            ok = kr_lu_solve(J, b, swaps);
 #pragma unroll
             for (int i = 0; i < KR_N; ++i) d[i] = b[i];
           }
@@ -743,6 +769,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         } else {
           if (norm <= p.newton_tol) {
             L.phase = KR_PH_CHECK;
+            L.gstate = 0;
           } else {
             bool failed = false;
             if (norm > L.prev) { if (++L.grow >= 2) failed = true; }

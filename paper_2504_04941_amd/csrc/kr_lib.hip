@@ -446,6 +446,9 @@ extern "C" void kr_default_options(kr_options *o) {
   o->floor = 1e-20;
   o->newton_tol = 1e-3;
   o->rho_floor = 0.0;
+  o->guess = nullptr;
+  o->guess_ld = 0;
+  o->counters = nullptr;
 }
 
 extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states, int64_t ld,
@@ -474,7 +477,9 @@ extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double 
   p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
   p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
   p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
-  p.counter = net->d_counter; p.pivot_swaps = nullptr;
+  p.counter = net->d_counter;
+  if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
+  p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
 
   unsigned long long *cnt = net->d_counter;
   void *rargs[] = {&cnt};
@@ -538,6 +543,10 @@ __global__ void kr_zero_u64(unsigned long long *p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
 
+__global__ void kr_zero_doubles(double *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
 extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const double *before,
                                    const double *after, int64_t ld, double *resid, double *max_out,
                                    kr_stream_t stream) {
@@ -566,3 +575,8 @@ extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const
   }
   return KR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* learned Newton guess (BF16 MFMA MLP)                                      */
+/* ------------------------------------------------------------------------ */
+#include "kr_mlp.hip"

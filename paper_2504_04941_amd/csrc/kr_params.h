@@ -25,7 +25,10 @@ struct KrParams {
   int *status;           /* [n_cells] or null */
   int *cell_stats;       /* [n_cells][4] or null */
   unsigned long long *counter; /* next unclaimed cell */
-  unsigned long long *pivot_swaps; /* diagnostic: row exchanges taken, or null */
+  const double *guess;   /* [S+1][guess_ld] first-substep Newton guess, or null */
+  long long guess_ld;
+  unsigned long long *counters; /* [4] guess starts, guess fallbacks, row
+                                   exchanges, reserved; or null */
 };
 
 #endif

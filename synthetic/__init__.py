@@ -319,11 +319,12 @@ def cells_h_he(net: NetworkDesc, n_cells: int, seed_index: int = 0) -> CellState
 
 
 def cells_h_o_n(net: NetworkDesc, n_cells: int, seed_index: int = 1,
-                dt: float = 1e-4) -> CellStates:
+                dt: float = 1e-4, salt: int = 2) -> CellStates:
     """T ~ U[900, 2500] K at p = 1 atm; majors H2, O2, H2O, N2 ~
     Dirichlet(2,1,1,4); radicals H, O, OH, HO2, H2O2 each 10^U[-12,-4];
-    renormalised mole fractions times n_tot = p / (k_B T)."""
-    rng = rng_for(seed_index, salt=2)
+    renormalised mole fractions times n_tot = p / (k_B T).  Different salts
+    give independent sets (e.g. training and held-out cells)."""
+    rng = rng_for(seed_index, salt=salt)
     T = rng.uniform(900.0, 2500.0, size=n_cells)
     ntot = ATM / (K_BOLTZ * T)
     x = np.zeros((9, n_cells))
@@ -335,6 +336,12 @@ def cells_h_o_n(net: NetworkDesc, n_cells: int, seed_index: int = 1,
     x /= x.sum(axis=0, keepdims=True)
     n = x * ntot[None, :]
     return CellStates(n, T, _rho(net, n), None, dt)
+
+
+def log_uniform(n: int, lo: float, hi: float, config_index: int, salt: int) -> np.ndarray:
+    """n values log-uniform in [lo, hi] from the seeded stream (config, salt)."""
+    rng = rng_for(config_index, salt=salt)
+    return 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=n)
 
 
 def network_for(config_index: int) -> NetworkDesc:
