@@ -84,7 +84,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=1 << 20)
-    ap.add_argument("--variants", default="fp64,fp32lu")
+    ap.add_argument("--variants", default="fp64,fp32lu,fp32lu+mlp")
+    ap.add_argument("--train-pairs", type=int, default=1 << 22)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -112,13 +114,47 @@ def main():
     stream = torch.cuda.current_stream()
 
     results = {}
+    learned_info = None
+    model = None
+    if any("mlp" in v for v in args.variants.split(",")):
+        from paper_2504_04941_amd import learned
+        t0 = time.perf_counter()
+        model = kr.GuessModel(net, hidden=256, layers=3, seed=1)
+        X, Y, _ = learned.single_step_pairs(net, model, desc, args.train_pairs, salt=1000)
+        hist = learned.train(model, X, Y, steps=args.train_steps, batch=4096, lr=1e-3, lr_min=1e-5,
+                             log=lambda s: print("# " + s, file=sys.stderr, flush=True))
+        del X, Y
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        # held-out single substeps (h log-uniform in [1e-10, 1e-4] s): Newton
+        # iterations from the plain start and from the learned start
+        evals = {}
+        for use in (False, True):
+            r = learned.newton_counts(net, model if use else None, desc, 1 << 20, salt=99)
+            st_ = r["cell_stats"].cpu().numpy()
+            evals["guess" if use else "plain"] = {
+                "newton_per_cell": float(st_[:, 1].mean()),
+                "status_counts": np.bincount(r["status"].cpu().numpy(), minlength=3).tolist(),
+                "guess_starts_fallbacks": r["counters"].cpu().numpy()[:2].tolist()}
+        learned_info = {"training_pairs": args.train_pairs, "training_steps": args.train_steps,
+                        "final_batch_loss": hist[-1][1], "setup_s": train_s,
+                        "single_substep_eval_2^20_cells": evals}
+        print(f"# learned guess: {learned_info}", file=sys.stderr, flush=True)
+
+    guess = torch.empty((desc.n_unknowns, args.cells), dtype=torch.float64, device=dev)
+    xs = torch.empty((args.cells, desc.n_species + 2), dtype=torch.float32, device=dev)
     for variant in args.variants.split(","):
-        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE}[variant]
-        opts = kr.default_options(precision=prec)
+        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE,
+                "fp32lu+mlp": kr.KR_FP32LU_REFINE, "fp64+mlp": kr.KR_FP64}[variant]
+        use_guess = "mlp" in variant
+        opts = (kr.guess_options(guess, precision=prec) if use_guess
+                else kr.default_options(precision=prec))
 
         def step():
             n.copy_(n0)
             T.copy_(T0)
+            if use_guess:   # the inference pre-pass is part of the step
+                model.predict(n, T, dt_scalar=dt_scalar, guess=guess, X_scratch=xs, stream=stream)
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
             ev0.record(stream)
@@ -172,6 +208,7 @@ def main():
                    "cells": args.cells, "unknowns": desc.n_unknowns, "reactions": desc.n_reactions,
                    "variant": "fp64" if "fp64" in results else args.variants},
         "variants": results,
+        "learned_guess": learned_info,
         "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64,
                      "traffic": None,

@@ -675,6 +675,25 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
       for (int s = 0; s < KR_S; ++s) b[s] = -(yv[s] - L.yn[s] - h * g[s]);
       b[KR_S] = -(yv[KR_S] * cv - L.eps_n - h * g[KR_S]);
+      if (ph == KR_PH_GUESS && L.gstate == 2) {
+        /* residual gate: keep the learned starting point only if its BE
+         * residual is smaller (weighted max norm) than the plain start's,
+         * R(y_n) = -h (f(y_n), Q(y_n)) */
+        double rg = 0.0, rp = 0.0;
+#pragma unroll
+        for (int s = 0; s < KR_S; ++s) {
+          const double w = kr_rcp(L.atol + p.rtol * fabs(L.yn[s]));
+          rg = fmax(rg, fabs(b[s]) * w);
+          rp = fmax(rp, h * fabs(L.gn[s]) * w);
+        }
+        const double wE = kr_rcp(p.rtol * L.eps_n);
+        rg = fmax(rg, fabs(b[KR_S]) * wE);
+        rp = fmax(rp, h * fabs(L.gn[KR_S] * L.eps_n / L.yn[KR_S]) * wE);
+        if (!(rg < rp)) {
+          kr_newton_failed(p, L);   /* falls back to the plain start */
+          goto kr_trip_end;
+        }
+      }
 #pragma unroll
       for (int s = 0; s < KR_S; ++s)
 #pragma unroll
@@ -782,6 +801,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       }
     }
 
+  kr_trip_end:
     if (L.phase == KR_PH_RESTART) L.phase = KR_PH_START;
   }
 }

@@ -361,12 +361,13 @@ static int guess_reserve(kr_guess *q, int B) {
   if (B <= q->bcap) return KR_OK;
   guess_free_buffers(q);
   const size_t H = (size_t)q->hidden;
+  const size_t HD = std::max<size_t>(H, (size_t)q->nout); /* gradient rows hold either width */
   HIP_TRY(hipMalloc(&q->a_in, sizeof(kr_bf16) * B * q->nin));
   HIP_TRY(hipMalloc(&q->out, sizeof(float) * B * q->nout));
   HIP_TRY(hipMalloc(&q->tgt, sizeof(float) * B * q->nout));
   for (int k = 0; k < 2; ++k) {
-    HIP_TRY(hipMalloc(&q->dzf[k], sizeof(float) * B * H));
-    HIP_TRY(hipMalloc(&q->dzb[k], sizeof(kr_bf16) * B * H));
+    HIP_TRY(hipMalloc(&q->dzf[k], sizeof(float) * B * HD));
+    HIP_TRY(hipMalloc(&q->dzb[k], sizeof(kr_bf16) * B * HD));
   }
   q->zl.assign(q->layers, nullptr);
   q->al.assign(q->layers, nullptr);
