@@ -114,6 +114,23 @@ typedef struct kr_network kr_network;
 int kr_network_create(const kr_network_desc *desc, kr_network **out);
 void kr_network_destroy(kr_network *net);
 
+/* Compile-time tuning of the generated kernels (chosen by the autotuner):
+ *   waves_per_eu  occupancy the register allocator budgets for (1..8; the
+ *                 lane's Newton matrix lives in VGPRs, so more waves means
+ *                 fewer registers per lane and possibly scratch spills)
+ *   pivot_tau     threshold of the LU's partial pivoting, (0, 1]: the
+ *                 diagonal is kept unless its scaled magnitude is below
+ *                 pivot_tau times the best candidate's. */
+typedef struct {
+  int32_t waves_per_eu;
+  float pivot_tau;
+} kr_build_opts;
+
+void kr_default_build_options(kr_build_opts *opt);
+/* kr_network_create with explicit build options (NULL = defaults). */
+int kr_network_create_ex(const kr_network_desc *desc, const kr_build_opts *opt,
+                         kr_network **out);
+
 /* Number of unknowns per cell (n_species + 1: abundances and temperature). */
 int kr_network_unknowns(const kr_network *net);
 
@@ -202,6 +219,56 @@ int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
 int kr_element_residual(const kr_network *net, int64_t n_cells,
                         const double *before, const double *after, int64_t ld,
                         double *resid, double *max_out, kr_stream_t stream);
+
+/* Fastest self-coupling timescale of each cell at its (pre-processed) input
+ * state, out[c] = 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s
+ * (device arrays; used to express steps in units of the cell's stiffness). */
+int kr_fastest_timescale(const kr_network *net, int64_t n_cells,
+                         const double *states, int64_t ld, const double *T,
+                         double *out, kr_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Several networks in one launch                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Up to 4 networks compiled into one module whose persistent kernel drains
+ * each network's cell queue in turn (each wave works on one network at a
+ * time, so lanes never diverge across networks; waves start on different
+ * networks so the queues drain together).  The networks must outlive the
+ * handle. */
+typedef struct kr_multi kr_multi;
+
+/* One network's cells for kr_chem_integrate_multi: the arrays and their
+ * meaning are those of kr_chem_integrate. */
+typedef struct {
+  int64_t n_cells;
+  double *states;
+  int64_t ld;
+  double *T;
+  const double *rho;
+  const double *dt;
+  double dt_scalar;
+  int32_t *status;
+  int32_t *cell_stats;
+} kr_batch;
+
+int kr_multi_create(const kr_network *const *nets, int32_t n_nets,
+                    const kr_build_opts *opt, kr_multi **out);
+void kr_multi_destroy(kr_multi *m);
+/* Integrates batches[k] with network k, all in one persistent launch.
+ * use_graph != 0: the launch ([reset work counters] -> [integrate]) is
+ * captured into a hipGraph on first use and replayed on later calls with
+ * the same arguments (re-captured when they change).  Options apply to all
+ * batches; the learned guess is not supported here (KR_EINVAL).  Calls on
+ * one handle must be serialised. */
+int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, double rtol,
+                            const kr_options *opt, int32_t use_graph,
+                            kr_stream_t stream);
+/* Graph replays so far (return value) and captures (*captures if not NULL). */
+int64_t kr_multi_graph_stats(const kr_multi *m, int64_t *captures);
+/* kr_network_check for a set of descriptions compiled into one module. */
+int kr_multi_check(const kr_network_desc *const *descs, int32_t n_nets,
+                   int compile, char *src_buf, int64_t src_len);
 
 /* ------------------------------------------------------------------------ */
 /* Learned Newton guess                                                      */

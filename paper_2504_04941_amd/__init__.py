@@ -60,6 +60,18 @@ class Options(C.Structure):
                 ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p)]
 
 
+class BuildOpts(C.Structure):
+    """kr_build_opts: compile-time tuning of the generated kernels."""
+    _fields_ = [("waves_per_eu", C.c_int32), ("pivot_tau", C.c_float)]
+
+
+class Batch(C.Structure):
+    """kr_batch: one network's cells in a multi-network launch."""
+    _fields_ = [("n_cells", C.c_int64), ("states", C.c_void_p), ("ld", C.c_int64),
+                ("T", C.c_void_p), ("rho", C.c_void_p), ("dt", C.c_void_p),
+                ("dt_scalar", C.c_double), ("status", C.c_void_p), ("cell_stats", C.c_void_p)]
+
+
 class TrainOpts(C.Structure):
     """kr_train_opts."""
     _fields_ = [("steps", C.c_int64), ("batch", C.c_int32), ("reserved", C.c_int32),
@@ -97,6 +109,18 @@ def lib():
                                           C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
         vp, i64 = C.c_void_p, C.c_int64
+        L.kr_default_build_options.argtypes = [C.POINTER(BuildOpts)]
+        L.kr_default_build_options.restype = None
+        L.kr_network_create_ex.argtypes = [C.POINTER(_Desc), C.POINTER(BuildOpts), C.POINTER(vp)]
+        L.kr_fastest_timescale.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+        L.kr_multi_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(BuildOpts), C.POINTER(vp)]
+        L.kr_multi_destroy.argtypes = [vp]
+        L.kr_multi_destroy.restype = None
+        L.kr_chem_integrate_multi.argtypes = [vp, C.POINTER(Batch), C.c_double, C.POINTER(Options),
+                                              C.c_int32, vp]
+        L.kr_multi_graph_stats.argtypes = [vp, C.POINTER(i64)]
+        L.kr_multi_graph_stats.restype = i64
+        L.kr_multi_check.argtypes = [C.POINTER(C.POINTER(_Desc)), C.c_int32, C.c_int, C.c_char_p, i64]
         L.kr_guess_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(vp)]
         L.kr_guess_destroy.argtypes = [vp]
         L.kr_guess_destroy.restype = None
@@ -164,13 +188,30 @@ def network_check(desc, compile: bool = False) -> str:
     return buf.value.decode()
 
 
-class Network:
-    """A compiled network (kr_network_create / kr_network_destroy)."""
+def build_options(**kw) -> BuildOpts:
+    o = BuildOpts()
+    lib().kr_default_build_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
 
-    def __init__(self, desc):
+
+def multi_check(descs, compile: bool = False) -> str:
+    packed = [_pack_desc(d) for d in descs]
+    arr = (C.POINTER(_Desc) * len(descs))(*[C.pointer(p[0]) for p in packed])
+    buf = C.create_string_buffer(1 << 23)
+    _check(lib().kr_multi_check(arr, len(descs), int(bool(compile)), buf, len(buf)))
+    return buf.value.decode()
+
+
+class Network:
+    """A compiled network (kr_network_create_ex / kr_network_destroy)."""
+
+    def __init__(self, desc, build: BuildOpts | None = None):
         d, keep = _pack_desc(desc)
         h = C.c_void_p()
-        _check(lib().kr_network_create(C.byref(d), C.byref(h)))
+        _check(lib().kr_network_create_ex(C.byref(d), None if build is None else C.byref(build),
+                                          C.byref(h)))
         self._h = h
         self.n_species = d.n_species
         self.n_reactions = d.n_reactions
@@ -250,6 +291,67 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
         _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar), float(rtol), C.byref(o),
         _dev_ptr(status, torch.int32, "status"), _dev_ptr(cell_stats, torch.int32, "cell_stats"),
         _stream_ptr(stream)))
+
+
+def fastest_timescale(net: Network, states, T, out=None, stream=None):
+    """kr_fastest_timescale: per-cell fastest self-coupling timescale (s)."""
+    import torch
+    n = int(T.numel())
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=T.device)
+    _check(lib().kr_fastest_timescale(net.handle, n, _dev_ptr(states, torch.float64, "states"),
+                                      int(states.stride(0)), _dev_ptr(T, torch.float64, "T"),
+                                      _dev_ptr(out, torch.float64, "out"), _stream_ptr(stream)))
+    return out
+
+
+class Multi:
+    """Several networks in one persistent launch (kr_multi_*)."""
+
+    def __init__(self, nets, build: BuildOpts | None = None):
+        self.nets = list(nets)   # keep the networks alive
+        arr = (C.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
+        h = C.c_void_p()
+        _check(lib().kr_multi_create(arr, len(self.nets), None if build is None else C.byref(build),
+                                     C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kr_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def graph_stats(self):
+        cap = C.c_int64(0)
+        launches = lib().kr_multi_graph_stats(self._h, C.byref(cap))
+        return int(launches), int(cap.value)
+
+    def integrate(self, batches, rtol=1e-6, opts: Options | None = None, use_graph=False,
+                  stream=None):
+        """batches: list of dicts with states [S_k, ld], T, and optional
+        rho, dt, dt_scalar, status, cell_stats (device tensors)."""
+        import torch
+        arr = (Batch * len(batches))()
+        for k, b in enumerate(batches):
+            st = b["states"]
+            n = int(b["T"].numel())
+            if st.stride(1) != 1 or st.shape[0] != self.nets[k].n_species:
+                raise ValueError(f"batch {k}: states must be [n_species, ld] with unit cell stride")
+            arr[k] = Batch(n, _dev_ptr(st, torch.float64, "states"), int(st.stride(0)),
+                           _dev_ptr(b["T"], torch.float64, "T"),
+                           _dev_ptr(b.get("rho"), torch.float64, "rho"),
+                           _dev_ptr(b.get("dt"), torch.float64, "dt"), float(b.get("dt_scalar", 0.0)),
+                           _dev_ptr(b.get("status"), torch.int32, "status"),
+                           _dev_ptr(b.get("cell_stats"), torch.int32, "cell_stats"))
+        o = opts if opts is not None else default_options()
+        _check(lib().kr_chem_integrate_multi(self._h, arr, float(rtol), C.byref(o),
+                                             int(bool(use_graph)), _stream_ptr(stream)))
 
 
 def element_residual(net: Network, before, after, resid=None, want_max: bool = False,

@@ -1,0 +1,116 @@
+"""Autotuner for the generated integrator kernels.
+
+Tunables (compile-time, `kr_build_opts`): the occupancy target the register
+allocator budgets for (waves per SIMD; the lane's Newton matrix lives in
+VGPRs, so a higher target trades registers for scratch spills) and the
+threshold of the LU's partial pivoting (a smaller threshold takes fewer row
+exchanges, which execute wave-wide when any lane needs one).  Each candidate
+is compiled, run on a sample of the caller's own cells (fresh copies per
+timing) and timed with HIP events on the launch stream; the fastest wins.
+Choices are cached in a JSON file keyed by the generated source (which
+encodes the network and the kernel template), the device name and the
+precision, so a network is tuned once per machine.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+from . import BuildOpts, Multi, Network, build_options, default_options, multi_check, network_check
+
+CACHE = os.environ.get("KR_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "kr_autotune.json"))
+CANDIDATES = [(1, 0.1), (1, 0.01), (2, 0.1)]
+
+
+def _key(sources, precision):
+    import torch
+    h = hashlib.sha256()
+    for s in sources:
+        h.update(s.encode())
+    h.update(torch.cuda.get_device_name(0).encode())
+    h.update(str(precision).encode())
+    return h.hexdigest()[:32]
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def _time_call(fn, reps):
+    import torch
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        prep = fn(None)           # copies the inputs (not timed)
+        ev0.record(stream)
+        fn(prep)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, ev0.elapsed_time(ev1))
+    return best
+
+
+def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, reps=2,
+               use_cache=True, log=None):
+    """Best build options for a set of networks integrated together.
+
+    batches: list of dicts as for Multi.integrate (a sample of the cells;
+    they are copied before every timed run and left untouched).  Returns
+    (BuildOpts, report)."""
+    import torch
+    key = _key([multi_check(descs)], precision)
+    db = _load() if use_cache else {}
+    if key in db:
+        w, tau = db[key]["best"]
+        return build_options(waves_per_eu=int(w), pivot_tau=float(tau)), db[key]
+    nets_cache = {}
+    report = {"candidates": [], "sample_cells": [int(b["T"].numel()) for b in batches]}
+    opts = default_options(precision=precision)
+    best, best_t = None, float("inf")
+    for w, tau in candidates:
+        bo = build_options(waves_per_eu=w, pivot_tau=tau)
+        t0 = time.time()
+        nets = [Network(d, bo) for d in descs]
+        multi = Multi(nets, bo)
+        compile_s = time.time() - t0
+
+        def run(prep):
+            if prep is None:
+                return [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in b.items()}
+                        for b in batches]
+            multi.integrate(prep, rtol=rtol, opts=opts)
+            return None
+
+        ms = _time_call(run, reps)
+        report["candidates"].append({"waves_per_eu": w, "pivot_tau": tau, "ms": ms,
+                                     "compile_s": compile_s})
+        if log:
+            log(f"autotune waves_per_eu={w} pivot_tau={tau}: {ms:.1f} ms (compile {compile_s:.1f} s)")
+        if ms < best_t:
+            best, best_t = (w, tau), ms
+        multi.close()
+        for n in nets:
+            n.close()
+        nets_cache.clear()
+    report["best"] = list(best)
+    if use_cache:
+        db = _load()
+        db[key] = report
+        _store(db)
+    return build_options(waves_per_eu=best[0], pivot_tau=best[1]), report

@@ -810,6 +810,30 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #define KR_WAVES_PER_EU 1
 #endif
 
+/* Fastest self-coupling timescale of each cell at its input state:
+ * 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s (workload set-up:
+ * steps expressed in units of it). */
+__device__ __forceinline__ void kr_timescale_body(const KrParams &p, double *out) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < p.n_cells;
+       c += (long long)gridDim.x * blockDim.x) {
+    double y[KR_N], g[KR_N], J[KR_N][KR_N], dt;
+    kr_load_input(p, c, y, dt);
+    kr_eval(y, g, J);
+    double m = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) m = fmax(m, fabs(J[s][s]));
+    const double cv = kr_heat_capacity(y);
+    if (cv > 0.0) m = fmax(m, fabs(J[KR_S][KR_S]) / cv);
+    double tau = (m > 0.0 && kr_finite(m)) ? 1.0 / m : 1e7;
+    out[c] = (kr_finite(tau) && tau < 1e7) ? tau : 1e7;
+  }
+}
+
+#ifndef KR_NO_KERNELS
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_timescale(KrParams p, double *out) {
+  kr_timescale_body(p, out);
+}
+
 extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp64(KrParams p) {
   kr_integrate_body<false>(p);
 }
@@ -821,3 +845,4 @@ extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_f
 extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
 }
+#endif /* KR_NO_KERNELS */

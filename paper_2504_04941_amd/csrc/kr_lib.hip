@@ -74,8 +74,9 @@ struct kr_network {
   double p_ref = 0.0, T_min = 0.0, T_max = 0.0;
   std::string source;
   hipModule_t module = nullptr;
-  hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
+  hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
+  kr_build_opts build{1, 0.1f};
   unsigned long long *d_counter = nullptr;
   unsigned long long *d_max = nullptr;
   int32_t *d_comp = nullptr;
@@ -325,19 +326,36 @@ static int compile_source(const std::string &src, std::vector<char> &code, std::
  * two-wave budget forces scratch spills that cost more than the extra wave
  * hides (measured: 390 vs 490 ms on 2^18 five-species cells).
  * KR_WAVES_PER_EU in the environment overrides (tuning experiments). */
-static int waves_per_eu(const kr_network *n) {
+static int default_waves_per_eu() {
   if (const char *e = getenv("KR_WAVES_PER_EU")) {
     const int w = atoi(e);
     if (w >= 1 && w <= 8) return w;
   }
-  (void)n;
   return 1;
 }
 
-static std::string full_source(const kr_network *n) {
+extern "C" void kr_default_build_options(kr_build_opts *o) {
+  if (!o) return;
+  o->waves_per_eu = default_waves_per_eu();
+  o->pivot_tau = 0.1f;
+}
+
+static int check_build_options(const kr_build_opts *o) {
+  if (o->waves_per_eu < 1 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [1, 8]");
+  if (!(o->pivot_tau > 0.0f && o->pivot_tau <= 1.0f)) return fail(KR_EINVAL, "pivot_tau out of (0, 1]");
+  return KR_OK;
+}
+
+static std::string build_prefix(const kr_build_opts &o) {
+  char b[160];
+  snprintf(b, sizeof b, "#define KR_WAVES_PER_EU %d\n#define KR_PIVOT_TAU %a\n", o.waves_per_eu,
+           (double)o.pivot_tau);
+  return b;
+}
+
+static std::string full_source(const kr_network *n, const kr_build_opts &o) {
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         "#define KR_WAVES_PER_EU " + std::to_string(waves_per_eu(n)) + "\n" + kParamsSource + "\n" +
-         generate_network(n) + "\n" + kDeviceSource;
+         build_prefix(o) + kParamsSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
 }
 
 static void release(kr_network *n) {
@@ -349,14 +367,21 @@ static void release(kr_network *n) {
   delete n;
 }
 
-extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) {
+extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_opts *bopt,
+                                    kr_network **out) {
   if (!out) return fail(KR_EINVAL, "null output handle");
   *out = nullptr;
+  kr_build_opts bo;
+  kr_default_build_options(&bo);
+  if (bopt) bo = *bopt;
+  int rc = check_build_options(&bo);
+  if (rc != KR_OK) return rc;
   kr_network *n = new (std::nothrow) kr_network;
   if (!n) return fail(KR_ENOMEM, "out of host memory");
-  int rc = build_tables(desc, n);
+  rc = build_tables(desc, n);
   if (rc != KR_OK) { delete n; return rc; }
-  n->source = full_source(n);
+  n->build = bo;
+  n->source = full_source(n, bo);
   std::vector<char> code;
   std::string log;
   rc = compile_source(n->source, code, log);
@@ -377,6 +402,7 @@ extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) 
   CREATE_TRY(hipModuleGetFunction(&n->f_fp64, n->module, "kr_integrate_fp64"));
   CREATE_TRY(hipModuleGetFunction(&n->f_fp32, n->module, "kr_integrate_fp32lu"));
   CREATE_TRY(hipModuleGetFunction(&n->f_reset, n->module, "kr_reset_counter"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_tau, n->module, "kr_timescale"));
   CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
   CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
   CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
@@ -388,6 +414,10 @@ extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) 
 #undef CREATE_TRY
   *out = n;
   return KR_OK;
+}
+
+extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) {
+  return kr_network_create_ex(desc, nullptr, out);
 }
 
 extern "C" void kr_network_destroy(kr_network *net) { release(net); }
@@ -419,7 +449,9 @@ extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *
   kr_network n;
   int rc = build_tables(desc, &n);
   if (rc != KR_OK) return rc;
-  const std::string src = full_source(&n);
+  kr_build_opts bo;
+  kr_default_build_options(&bo);
+  const std::string src = full_source(&n, bo);
   if (src_buf && src_len > 0) {
     const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
     std::memcpy(src_buf, src.data(), m);
@@ -573,6 +605,255 @@ extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const
     HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(max_out, &bits, sizeof bits);
   }
+  return KR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* fastest timescale (workload set-up)                                       */
+/* ------------------------------------------------------------------------ */
+
+extern "C" int kr_fastest_timescale(const kr_network *net, int64_t n_cells, const double *states,
+                                    int64_t ld, const double *T, double *out, kr_stream_t stream) {
+  if (!net || n_cells < 0 || ld < n_cells || (n_cells && (!states || !T || !out)))
+    return fail(KR_EINVAL, "bad timescale arguments");
+  if (!n_cells) return KR_OK;
+  HIP_TRY(hipSetDevice(net->device));
+  KrParams p{};
+  p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.dt_scalar = 1.0;
+  long long blocks = std::min<long long>((n_cells + 63) / 64, (long long)net->cu_count * 16);
+  void *args[] = {&p, &out};
+  HIP_TRY(hipModuleLaunchKernel(net->f_tau, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
+                                nullptr));
+  return KR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* several networks in one persistent launch                                 */
+/* ------------------------------------------------------------------------ */
+
+#define KR_MAX_NETS 4
+
+struct KrMultiHost {          /* mirrors the device struct KrMulti */
+  KrParams net[KR_MAX_NETS];
+  int n_nets;
+};
+
+struct kr_multi {
+  std::vector<const kr_network *> nets;
+  kr_build_opts build{1, 0.1f};
+  std::string source;
+  hipModule_t module = nullptr;
+  hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
+  int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
+  unsigned long long *d_counters = nullptr; /* one per network */
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;      /* launch parameters the graph was captured with */
+  long long graph_launches = 0, graph_captures = 0;
+};
+
+static std::string multi_source(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
+  std::string s = "/* per-cell implicit thermochemistry: several networks in one launch */\n" +
+                  build_prefix(o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n";
+  for (size_t k = 0; k < nets.size(); ++k) {
+    s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" + kDeviceSource +
+         "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";
+  }
+  s += "struct KrMulti { KrParams net[" + std::to_string(KR_MAX_NETS) + "]; int n_nets; };\n";
+  for (int mixed = 0; mixed < 2; ++mixed) {
+    s += std::string("extern \"C\" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) ") +
+         (mixed ? "kr_integrate_multi_fp32lu" : "kr_integrate_multi_fp64") +
+         "(KrMulti m) {\n"
+         "  /* each wave drains one network's queue after another, starting at a\n"
+         "   * different network so that the queues drain together */\n"
+         "  for (int i = 0; i < m.n_nets; ++i) {\n"
+         "    const int k = (int)((blockIdx.x + i) % (unsigned)m.n_nets);\n"
+         "    switch (k) {\n";
+    for (size_t k = 0; k < nets.size(); ++k)
+      s += "      case " + std::to_string(k) + ": kr_m" + std::to_string(k) + "::kr_integrate_body<" +
+           (mixed ? "true" : "false") + ">(m.net[" + std::to_string(k) + "]); break;\n";
+    s += "      default: break;\n    }\n  }\n}\n";
+  }
+  s += "extern \"C\" __global__ void kr_reset_counters(unsigned long long *c, int n) {\n"
+       "  if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = 0ull;\n}\n";
+  return s;
+}
+
+static void release_multi(kr_multi *m) {
+  if (!m) return;
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->capture) (void)hipStreamDestroy(m->capture);
+  if (m->d_counters) (void)hipFree(m->d_counters);
+  if (m->module) (void)hipModuleUnload(m->module);
+  delete m;
+}
+
+extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, const kr_build_opts *bopt,
+                               kr_multi **out) {
+  if (!out) return fail(KR_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
+  for (int k = 0; k < n_nets; ++k)
+    if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
+  kr_build_opts bo;
+  kr_default_build_options(&bo);
+  if (bopt) bo = *bopt;
+  int rc = check_build_options(&bo);
+  if (rc != KR_OK) return rc;
+  kr_multi *m = new (std::nothrow) kr_multi;
+  if (!m) return fail(KR_ENOMEM, "out of host memory");
+  m->nets.assign(nets, nets + n_nets);
+  m->build = bo;
+  m->source = multi_source(m->nets, bo);
+  std::vector<char> code;
+  std::string log;
+  rc = compile_source(m->source, code, log);
+  if (rc != KR_OK) { delete m; return rc; }
+  hipError_t e;
+#define MULTI_TRY(expr)                                                              \
+  do {                                                                               \
+    e = (expr);                                                                      \
+    if (e != hipSuccess) {                                                           \
+      rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                  \
+      release_multi(m);                                                              \
+      return rc;                                                                     \
+    }                                                                                \
+  } while (0)
+  MULTI_TRY(hipGetDevice(&m->device));
+  MULTI_TRY(hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device));
+  MULTI_TRY(hipModuleLoadData(&m->module, code.data()));
+  MULTI_TRY(hipModuleGetFunction(&m->f_fp64, m->module, "kr_integrate_multi_fp64"));
+  MULTI_TRY(hipModuleGetFunction(&m->f_fp32, m->module, "kr_integrate_multi_fp32lu"));
+  MULTI_TRY(hipModuleGetFunction(&m->f_reset, m->module, "kr_reset_counters"));
+  MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64, m->f_fp64, 64, 0));
+  MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32, m->f_fp32, 64, 0));
+  MULTI_TRY(hipMalloc(&m->d_counters, sizeof(unsigned long long) * KR_MAX_NETS));
+  MULTI_TRY(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
+#undef MULTI_TRY
+  *out = m;
+  return KR_OK;
+}
+
+extern "C" void kr_multi_destroy(kr_multi *m) { release_multi(m); }
+
+extern "C" int kr_multi_check(const kr_network_desc *const *descs, int32_t n_nets, int compile, char *src_buf,
+                              int64_t src_len) {
+  if (!descs || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
+  std::vector<kr_network> tabs(n_nets);
+  std::vector<const kr_network *> ptrs;
+  for (int k = 0; k < n_nets; ++k) {
+    int rc = build_tables(descs[k], &tabs[k]);
+    if (rc != KR_OK) return rc;
+    ptrs.push_back(&tabs[k]);
+  }
+  kr_build_opts bo;
+  kr_default_build_options(&bo);
+  const std::string src = multi_source(ptrs, bo);
+  if (src_buf && src_len > 0) {
+    const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
+    std::memcpy(src_buf, src.data(), m);
+    src_buf[m] = '\0';
+  }
+  if (!compile) return KR_OK;
+  std::vector<char> code;
+  std::string log;
+  return compile_source(src, code, log);
+}
+
+extern "C" int64_t kr_multi_graph_stats(const kr_multi *m, int64_t *captures) {
+  if (!m) return fail(KR_EINVAL, "null handle");
+  if (captures) *captures = m->graph_captures;
+  return m->graph_launches;
+}
+
+static int fill_params(const kr_network *net, const kr_batch &b, double rtol, const kr_options &o,
+                       unsigned long long *counter, KrParams &p) {
+  if (b.n_cells < 0 || b.ld < b.n_cells) return fail(KR_EINVAL, "bad n_cells/ld in a batch");
+  if (b.n_cells && (!b.states || !b.T)) return fail(KR_EINVAL, "null state arrays in a batch");
+  if (!b.dt && !(b.dt_scalar >= 0.0 && std::isfinite(b.dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+  (void)net;
+  p = KrParams{};
+  p.n_cells = b.n_cells; p.states = b.states; p.ld = b.ld; p.T = b.T; p.rho = b.rho; p.dt = b.dt;
+  p.dt_scalar = b.dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
+  p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
+  p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = b.status; p.cell_stats = b.cell_stats;
+  p.counter = counter; p.guess = nullptr; p.guess_ld = 0; p.counters = o.counters;
+  return KR_OK;
+}
+
+static int validate_options(const kr_options &o) {
+  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+      (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
+      o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
+      !(o.rho_floor >= 0.0))
+    return fail(KR_EINVAL, "bad options");
+  return KR_OK;
+}
+
+extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, double rtol,
+                                       const kr_options *opt, int32_t use_graph, kr_stream_t stream) {
+  if (!m || !batches) return fail(KR_EINVAL, "null argument");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
+  kr_options o;
+  kr_default_options(&o);
+  if (opt) o = *opt;
+  int rc = validate_options(o);
+  if (rc) return rc;
+  if (o.guess) return fail(KR_EINVAL, "a learned guess is not supported in multi-network launches");
+  KrMultiHost h{};
+  long long total = 0;
+  h.n_nets = (int)m->nets.size();
+  for (int k = 0; k < h.n_nets; ++k) {
+    if ((rc = fill_params(m->nets[k], batches[k], rtol, o, m->d_counters + k, h.net[k]))) return rc;
+    total += batches[k].n_cells;
+  }
+  if (total == 0) return KR_OK;
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t st = (hipStream_t)stream;
+  hipFunction_t f = o.precision == KR_FP64 ? m->f_fp64 : m->f_fp32;
+  const int occ = o.precision == KR_FP64 ? m->occ_fp64 : m->occ_fp32;
+  long long blocks = (long long)m->cu_count * (occ > 0 ? occ : 1);
+  const long long need = (total + 63) / 64;
+  if (blocks > need) blocks = need;
+  if (blocks < 1) blocks = 1;
+  unsigned long long *cnt = m->d_counters;
+  int nn = h.n_nets;
+  void *rargs[] = {&cnt, &nn};
+  void *args[] = {&h};
+  if (!use_graph) {
+    HIP_TRY(hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
+    HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
+    return KR_OK;
+  }
+  /* graph of [reset the work counters] -> [persistent integrate], captured
+   * once per distinct launch configuration and replayed on the caller's
+   * stream (the counters are cleared by a kernel, not a memset node) */
+  std::vector<char> key(sizeof h + sizeof blocks + sizeof f);
+  std::memcpy(key.data(), &h, sizeof h);
+  std::memcpy(key.data() + sizeof h, &blocks, sizeof blocks);
+  std::memcpy(key.data() + sizeof h + sizeof blocks, &f, sizeof f);
+  if (!m->exec || key != m->key) {
+    if (m->exec) { (void)hipGraphExecDestroy(m->exec); m->exec = nullptr; }
+    if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
+    HIP_TRY(hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, m->capture, rargs, nullptr);
+    hipError_t e2 = hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, m->capture, args, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e3 = hipStreamEndCapture(m->capture, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(KR_EDEVICE, "graph capture failed: %s / %s / %s", hipGetErrorString(e1),
+                  hipGetErrorString(e2), hipGetErrorString(e3));
+    }
+    m->graph = g;
+    HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
+    m->key = key;
+    m->graph_captures++;
+  }
+  HIP_TRY(hipGraphLaunch(m->exec, st));
+  m->graph_launches++;
   return KR_OK;
 }
 

@@ -338,6 +338,61 @@ def cells_h_o_n(net: NetworkDesc, n_cells: int, seed_index: int = 1,
     return CellStates(n, T, _rho(net, n), None, dt)
 
 
+def network_astro23(seed_index: int = 2) -> NetworkDesc:
+    """23 species over rows H, He, C, O and charge (an astrochemistry-shaped
+    ion-molecule network); 64 reversible reactions with at most 3 species
+    per side, spanning the null space of the composition (dimension 18)."""
+    rng = rng_for(seed_index, salt=1)
+    # (name, H, He, C, O, charge)
+    table = [("H", 1, 0, 0, 0, 0), ("H2", 2, 0, 0, 0, 0), ("H+", 1, 0, 0, 0, 1),
+             ("H2+", 2, 0, 0, 0, 1), ("H3+", 3, 0, 0, 0, 1), ("e-", 0, 0, 0, 0, -1),
+             ("He", 0, 1, 0, 0, 0), ("He+", 0, 1, 0, 0, 1), ("C", 0, 0, 1, 0, 0),
+             ("C+", 0, 0, 1, 0, 1), ("CH", 1, 0, 1, 0, 0), ("CH+", 1, 0, 1, 0, 1),
+             ("CH2", 2, 0, 1, 0, 0), ("O", 0, 0, 0, 1, 0), ("O+", 0, 0, 0, 1, 1),
+             ("OH", 1, 0, 0, 1, 0), ("OH+", 1, 0, 0, 1, 1), ("H2O", 2, 0, 0, 1, 0),
+             ("H2O+", 2, 0, 0, 1, 1), ("H3O+", 3, 0, 0, 1, 1), ("CO", 0, 0, 1, 1, 0),
+             ("CO+", 0, 0, 1, 1, 1), ("O2", 0, 0, 0, 2, 0)]
+    species = [t[0] for t in table]
+    comp = np.array([[t[k] for t in table] for k in range(1, 6)], np.int32)
+    reservoir = np.array([0, 6, 8, 13, 5], np.int32)
+    atoms = comp[:4].sum(axis=0)
+    linear = {"H2", "H2+", "CH", "CH+", "OH", "OH+", "CO", "CO+", "O2"}
+    cv = np.array([1.5 if s == "e-" else _heat_capacity(int(a), s in linear)
+                   for s, a in zip(species, atoms)])
+    h_form, s_form = _thermo(rng, comp, 4)
+    cands = enumerate_reactions(comp, 3, 3, max_common=1)
+    picks = _choose_reactions(rng, comp, cands, 64)
+    reac, prod, arr = _orient_and_draw(
+        rng, picks, h_form, lambda order, g: g.uniform(-12.0, -8.0), (-1.0, 1.0), 5e4)
+    return NetworkDesc("astro_23sp", species, ["H", "He", "C", "O", "charge"], 4, comp,
+                       reservoir, cv, h_form, s_form, reac, prod, arr, None, p_ref=ATM,
+                       T_min=1.0, T_max=1.0e6, meta={"config_index": 2})
+
+
+def cells_astro23(net: NetworkDesc, n_cells: int, seed_index: int = 2, salt: int = 2) -> CellStates:
+    """T log-uniform [10, 3000] K, hydrogen nuclei log-uniform [1, 1e6]
+    cm^-3 split H : 2 H2 : H+ by Dirichlet(1,1,1) with n_e balancing the
+    charge, He = 0.1 n_H, C = 1e-4 n_H (as C+), O = 3e-4 n_H (as O),
+    other species 10^U[-12,-6] n_H."""
+    rng = rng_for(seed_index, salt=salt)
+    S = net.n_species
+    idx = {s: i for i, s in enumerate(net.species)}
+    T = 10.0 ** rng.uniform(1.0, np.log10(3000.0), size=n_cells)
+    nH = 10.0 ** rng.uniform(0.0, 6.0, size=n_cells)
+    f = rng.dirichlet((1.0, 1.0, 1.0), size=n_cells)
+    n = 10.0 ** rng.uniform(-12.0, -6.0, size=(S, n_cells)) * nH[None, :]
+    n[idx["H"]] = f[:, 0] * nH
+    n[idx["H2"]] = 0.5 * f[:, 1] * nH
+    n[idx["H+"]] = f[:, 2] * nH
+    n[idx["He"]] = 0.1 * nH
+    n[idx["C+"]] = 1e-4 * nH
+    n[idx["O"]] = 3e-4 * nH
+    charge = net.composition[4].astype(float)
+    n[idx["e-"]] = 0.0
+    n[idx["e-"]] = np.maximum(charge @ n, 0.0)
+    return CellStates(n, T, _rho(net, n), None, 0.0)
+
+
 def log_uniform(n: int, lo: float, hi: float, config_index: int, salt: int) -> np.ndarray:
     """n values log-uniform in [lo, hi] from the seeded stream (config, salt)."""
     rng = rng_for(config_index, salt=salt)
