@@ -78,9 +78,160 @@ def cpu_baseline(desc, cs, dt_scalar, sample, seed=7):
                       f"batch, FP64 C oracle, OpenMP over {cores} threads, {el:.1f} s"}
 
 
+MIX_FRACTIONS = (0.5, 0.3, 0.2)
+MIX_U_RANGE = (-4.0, -1.5)   # dt = tau_fast * 10^U[...]: substeps span ~1 to a few hundred
+
+
+def _mix_descs():
+    import synthetic as sy
+    return [sy.network_h_he(0), sy.network_h_o_n(1), sy.network_astro23(2)]
+
+
+def _cells(name):
+    def make(d, n):
+        import synthetic as sy
+        return getattr(sy, name)(d, n, {"cells_h_he": 0, "cells_h_o_n": 1, "cells_astro23": 2}[name])
+    return make
+
+
+_MIX_MAKERS = [_cells("cells_h_he"), _cells("cells_h_o_n"), _cells("cells_astro23")]
+
+
+def run_mixed(args):
+    """Uneven batch in one persistent launch: 2^22 cells mixing the 6-, 10-
+    and 24-unknown networks (50/30/20%), each cell's step a seeded multiple
+    10^U[-4,-1.5] of its own fastest timescale, FP32 LU with FP64
+    refinement, one hipGraph-replayed launch per step."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+    from paper_2504_04941_amd import autotune
+
+    dev = torch.device("cuda", 0)
+    descs = _mix_descs()
+    makers = _MIX_MAKERS
+    counts = [int(args.cells * f) for f in MIX_FRACTIONS]
+    counts[0] += args.cells - sum(counts)
+    bo = kr.build_options()
+    t0 = time.perf_counter()
+    base_nets = [kr.Network(d) for d in descs]
+    init, bufs = [], []
+    for k, (d, mk, n) in enumerate(zip(descs, makers, counts)):
+        cs = mk(d, n)
+        n0 = torch.tensor(cs.n, device=dev)
+        T0 = torch.tensor(cs.T, device=dev)
+        tau = kr.fastest_timescale(base_nets[k], n0, T0)
+        dt = tau * torch.tensor(sy.log_uniform(n, 10 ** MIX_U_RANGE[0], 10 ** MIX_U_RANGE[1], 2, 300 + k),
+                                device=dev)
+        init.append((n0, T0))
+        bufs.append({"states": n0.clone(), "T": T0.clone(), "dt": dt,
+                     "status": torch.empty(n, dtype=torch.int32, device=dev),
+                     "cell_stats": torch.empty((n, 4), dtype=torch.int32, device=dev)})
+    setup_s = time.perf_counter() - t0
+    report = None
+    if args.autotune:
+        sample = [{k2: (v[..., : max(1, v.shape[-1] // 64)].contiguous() if k2 in ("states",) else
+                        v[: max(1, v.shape[0] // 64)].contiguous()) for k2, v in b.items()} for b in bufs]
+        bo, report = autotune.tune_multi(descs, sample, precision=kr.KR_FP32LU_REFINE,
+                                         candidates=[(1, 0.1), (1, 0.01)],
+                                         log=lambda s: print("# " + s, file=sys.stderr, flush=True))
+    nets = [kr.Network(d, bo) for d in descs]
+    multi = kr.Multi(nets, bo)
+    opts = kr.default_options(precision=kr.KR_FP32LU_REFINE)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for (n0, T0), b in zip(init, bufs):
+            b["states"].copy_(n0)
+            b["T"].copy_(T0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        multi.integrate(bufs, rtol=1e-6, opts=opts, use_graph=True, stream=stream)
+        ev1.record(stream)
+        return ev0, ev1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = np.mean([a.elapsed_time(b) for a, b in evs]) * 1e-3
+    flops, per_net = 0.0, {}
+    for d, b in zip(descs, bufs):
+        st = b["cell_stats"].cpu().numpy().astype(np.int64)
+        f_it, f_rhs = flops_per_unit(d)
+        flops += st[:, 1].sum() * f_it + (st[:, 0] + st[:, 2]).sum() * f_rhs
+        acc = st[:, 0]
+        per_net[d.name] = {"cells": int(acc.size), "newton_per_cell": float(st[:, 1].mean()),
+                           "substep_histogram": {"1": int((acc <= 1).sum()),
+                                                 "2-10": int(((acc > 1) & (acc <= 10)).sum()),
+                                                 "11-50": int(((acc > 10) & (acc <= 50)).sum()),
+                                                 "51-200": int(((acc > 50) & (acc <= 200)).sum()),
+                                                 ">200": int((acc > 200).sum())},
+                           "status_counts": np.bincount(b["status"].cpu().numpy(), minlength=3).tolist()}
+    launches, captures = multi.graph_stats()
+    out = {"metric": "cell-steps/s implicit chem update, uneven multi-network batch, 1 GPU",
+           "value": args.cells * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32lu",
+           "data": "synthetic",
+           "config": {"workload": f"mixed: {args.cells} cells, 5/9/23-species networks 50/30/20%, "
+                                  "dt = tau_fast*10^U[-4,-1.5], FP32 LU + FP64 refinement, "
+                                  "one persistent hipGraph launch", "build": [bo.waves_per_eu, bo.pivot_tau]},
+           "per_network": per_net, "graph": {"launches": launches, "captures": captures},
+           "autotune": report, "setup_s": setup_s,
+           "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": PEAK_FP64 / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / kernel_s / PEAK_FP64, "traffic": None,
+                        "kernel": "kr_integrate_multi_fp32lu"}}
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_mixed(args):
+    """Substep-count distribution of each network of the uneven batch for
+    steps dt = tau_fast * 10^u over a grid of u (16384 cells per network,
+    same seeded cell recipe as the batch): the table the per-network step
+    ranges of the uneven batch were read from."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    dev = torch.device("cuda", 0)
+    n_cells = 16384
+    grid = [float(u) for u in np.arange(-6.0, -0.99, 0.5)]
+    out = {}
+    for k, (d, mk) in enumerate(zip(_mix_descs(), _MIX_MAKERS)):
+        cs = mk(d, n_cells)
+        net = kr.Network(d)
+        n0 = torch.tensor(cs.n, device=dev)
+        T0 = torch.tensor(cs.T, device=dev)
+        tau = kr.fastest_timescale(net, n0, T0)
+        rows = {}
+        for u in grid:
+            n = n0.clone()
+            T = T0.clone()
+            st = torch.empty((n_cells, 4), dtype=torch.int32, device=dev)
+            status = torch.empty(n_cells, dtype=torch.int32, device=dev)
+            kr.chem_integrate(net, n, T, dt=tau * 10.0 ** u, rtol=1e-6,
+                              opts=kr.default_options(precision=kr.KR_FP32LU_REFINE),
+                              status=status, cell_stats=st)
+            a = st[:, 0].cpu().numpy()
+            rows[f"{u:+.1f}"] = {"p50": float(np.median(a)), "p90": float(np.percentile(a, 90)),
+                                 "p99": float(np.percentile(a, 99)), "max": int(a.max()),
+                                 "newton_per_cell": float(st[:, 1].float().mean()),
+                                 "status_counts": np.bincount(status.cpu().numpy(), minlength=3).tolist()}
+            print(f"# {d.name} u={u:+.1f}: {rows[f'{u:+.1f}']}", file=sys.stderr, flush=True)
+        out[d.name] = rows
+        net.close()
+    print(json.dumps({"calibration": out, "cells_per_network": n_cells}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="h_o_n", choices=["h_o_n", "mixed", "calibrate"])
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=1 << 20)
@@ -94,6 +245,15 @@ def main():
         print("bench.py measures one GPU only: the per-cell integration needs no communication, "
               "and multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "calibrate":
+        calibrate_mixed(args)
+        return
+    if args.workload == "mixed":
+        if args.cells == 1 << 20:
+            args.cells = 1 << 22
+        run_mixed(args)
+        return
 
     import torch
     import paper_2504_04941_amd as kr
@@ -142,6 +302,7 @@ def main():
         print(f"# learned guess: {learned_info}", file=sys.stderr, flush=True)
 
     guess = torch.empty((desc.n_unknowns, args.cells), dtype=torch.float64, device=dev)
+    counters = torch.zeros(8, dtype=torch.int64, device=dev)
     xs = torch.empty((args.cells, desc.n_species + 2), dtype=torch.float32, device=dev)
     for variant in args.variants.split(","):
         prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE,
@@ -149,10 +310,12 @@ def main():
         use_guess = "mlp" in variant
         opts = (kr.guess_options(guess, precision=prec) if use_guess
                 else kr.default_options(precision=prec))
+        opts.counters = counters.data_ptr()
 
         def step():
             n.copy_(n0)
             T.copy_(T0)
+            counters.zero_()
             if use_guess:   # the inference pre-pass is part of the step
                 model.predict(n, T, dt_scalar=dt_scalar, guess=guess, X_scratch=xs, stream=stream)
             ev0 = torch.cuda.Event(enable_timing=True)
@@ -186,6 +349,9 @@ def main():
             "newton_iters_per_cell": float(iters) / args.cells,
             "substeps_per_cell": float(acc) / args.cells,
             "status_counts": stat_codes.tolist(),
+            "counters_last_step": dict(zip(("guess_starts", "guess_fallbacks", "row_exchanges",
+                                            "fp32_solves", "fp64_fallbacks"),
+                                           counters.cpu().numpy()[:5].tolist())),
         }
         print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
 

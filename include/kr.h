@@ -120,10 +120,22 @@ void kr_network_destroy(kr_network *net);
  *                 fewer registers per lane and possibly scratch spills)
  *   pivot_tau     threshold of the LU's partial pivoting, (0, 1]: the
  *                 diagonal is kept unless its scaled magnitude is below
- *                 pivot_tau times the best candidate's. */
+ *                 pivot_tau times the best candidate's (lane-per-cell
+ *                 layout; the wave-per-cell LU takes the best candidate)
+ *   layout        KR_LAYOUT_AUTO: one cell per lane below
+ *                 KR_WIDE_MIN_SPECIES species, one cell per wavefront from
+ *                 there; KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
+ *                 wavefront layout holds the Newton matrix one row per lane
+ *                 and needs n_species <= 62 and 5 * 2 * n_reactions
+ *                 rounded up to 320 <= 4095 (n_reactions <= 384). */
+#define KR_LAYOUT_AUTO 0
+#define KR_LAYOUT_LANE 1
+#define KR_LAYOUT_WAVE 2
+#define KR_WIDE_MIN_SPECIES 32
 typedef struct {
   int32_t waves_per_eu;
   float pivot_tau;
+  int32_t layout;
 } kr_build_opts;
 
 void kr_default_build_options(kr_build_opts *opt);
@@ -149,6 +161,9 @@ int64_t kr_network_source(const kr_network *net, char *buf, int64_t buf_len);
  * for the same description. */
 int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
                      int64_t src_len);
+/* kr_network_check with explicit build options (NULL = defaults). */
+int kr_network_check_ex(const kr_network_desc *desc, const kr_build_opts *opt, int compile,
+                        char *src_buf, int64_t src_len);
 
 /* ------------------------------------------------------------------------ */
 /* Integration                                                               */
@@ -180,9 +195,12 @@ typedef struct {
                            redone from the plain starting point (the
                            substep's initial state) before any step cut */
   int64_t guess_ld;
-  unsigned long long *counters; /* device [4] or NULL, accumulated: substeps
-                           started from a guess, guess fallbacks, row
-                           exchanges taken by the LU, reserved */
+  unsigned long long *counters; /* device [8] or NULL, accumulated: [0]
+                           substeps started from a guess, [1] guess
+                           fallbacks, [2] row exchanges taken by the LU,
+                           [3] FP32 solves in refinement sweeps (FP32 LU
+                           form), [4] linear systems that refinement did
+                           not settle and FP64 LU solved, [5..7] reserved */
 } kr_options;
 
 void kr_default_options(kr_options *opt);

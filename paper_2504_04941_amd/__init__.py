@@ -26,9 +26,11 @@ LIB_PATH = os.path.join(_HERE, "libkr.so")
 KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
 KR_FP64, KR_FP32LU_REFINE = 0, 1
 KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
+KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
+KR_WIDE_MIN_SPECIES = 32
 
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns",
-            "kr_network_arrhenius", "kr_network_source", "kr_network_check",
+            "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
             "kr_default_options", "kr_chem_integrate", "kr_element_residual",
             "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
             "kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
@@ -62,7 +64,7 @@ class Options(C.Structure):
 
 class BuildOpts(C.Structure):
     """kr_build_opts: compile-time tuning of the generated kernels."""
-    _fields_ = [("waves_per_eu", C.c_int32), ("pivot_tau", C.c_float)]
+    _fields_ = [("waves_per_eu", C.c_int32), ("pivot_tau", C.c_float), ("layout", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -179,12 +181,13 @@ def _pack_desc(desc):
     return d, keep
 
 
-def network_check(desc, compile: bool = False) -> str:
+def network_check(desc, compile: bool = False, build: BuildOpts | None = None) -> str:
     """Validates (and optionally compiles, without a device) a description;
     returns the generated device source."""
     d, keep = _pack_desc(desc)
-    buf = C.create_string_buffer(1 << 22)
-    _check(lib().kr_network_check(C.byref(d), int(bool(compile)), buf, len(buf)))
+    buf = C.create_string_buffer(1 << 23)
+    _check(lib().kr_network_check_ex(C.byref(d), C.byref(build) if build is not None else None,
+                                     int(bool(compile)), buf, len(buf)))
     return buf.value.decode()
 
 

@@ -721,7 +721,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
           for (int k = 0; k < KR_N; ++k) a32[i][k] = (float)(J[i][k] * rs[i]);
         }
-        ok = kr_lu_factor32(a32, dinv, perm, swaps);
+        bool ok32 = kr_lu_factor32(a32, dinv, perm, swaps);
         double d[KR_N];
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) d[i] = 0.0;
@@ -729,8 +729,10 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) r[i] = b[i];
         bool conv = false;
+        int sweeps = 0;
 #pragma unroll 1
-        for (int sweep = 0; sweep < 4 && ok; ++sweep) {
+        for (int sweep = 0; sweep < 4 && ok32; ++sweep) {
+          sweeps = sweep + 1;
           float c32[KR_N];
 #pragma unroll
           for (int i = 0; i < KR_N; ++i) c32[i] = (float)(r[i] * rs[i]);
@@ -743,7 +745,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
             const double e = fabs(c) * kr_rcp(kr_weight(p, L, i, L.y[i]));
             cn = e > cn ? e : cn;
           }
-          if (!kr_finite(cn)) { ok = false; break; }
+          if (!kr_finite(cn)) { ok32 = false; break; }
           if (sweep > 0 && cn <= 1e-6) { conv = true; break; }
           /* r = b - M d in FP64 */
 #pragma unroll
@@ -754,9 +756,15 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
             r[i] = t;
           }
         }
-        if (__any(ok && !conv)) {
-          /* refinement did not contract: FP64 LU for those lanes */
-          if (ok && !conv) {
+        if (p.counters) atomicAdd(&p.counters[3], (unsigned long long)sweeps);
+        /* an FP32 factorisation that broke down (zero, overflowing or
+         * non-finite values) or a refinement that did not contract: FP64 LU
+         * for those lanes */
+        const bool need64 = !ok32 || !conv;
+        ok = true;
+        if (__any(need64)) {
+          if (need64) {
+            if (p.counters) atomicAdd(&p.counters[4], 1ull);
             ok = kr_lu_solve(J, b, swaps);
 #pragma unroll
             for (int i = 0; i < KR_N; ++i) d[i] = b[i];

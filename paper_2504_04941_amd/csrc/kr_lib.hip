@@ -23,6 +23,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,9 @@
 
 static const char *kDeviceSource =
 #include "kr_device_src.inc"
+    ;
+static const char *kWideSource =
+#include "kr_wide_src.inc"
     ;
 static const char *kParamsSource =
 #include "kr_params_src.inc"
@@ -76,7 +80,8 @@ struct kr_network {
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
-  kr_build_opts build{1, 0.1f};
+  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
+  bool wide = false;            /* one wavefront per cell */
   unsigned long long *d_counter = nullptr;
   unsigned long long *d_max = nullptr;
   int32_t *d_comp = nullptr;
@@ -198,12 +203,143 @@ static std::string coef(int nu) {
   return std::to_string(nu) + ".0 * ";
 }
 
-/* The network-specific section of the device source. */
-static std::string generate_network(const kr_network *n) {
+static std::string network_tables(const kr_network *n);
+
+/* Row stride (in doubles) of the wavefront layout's LDS Jacobian: S species
+ * columns, T and f; odd, so that lanes reading their own rows spread over
+ * the LDS banks. */
+static int wide_ldj(int S) { return (S + 2) % 2 ? S + 2 : S + 3; }
+
+/* Reaction directions with a nonzero rate: Arrhenius parameters, reactant
+ * slots and net stoichiometry (products minus reactants). */
+struct WideDir {
+  double A, b, E;
+  int slot[3];
+  std::vector<int> nu;
+};
+
+static std::vector<WideDir> wide_directions(const kr_network *n) {
+  std::vector<WideDir> out;
+  for (int r = 0; r < n->R; ++r)
+    for (int dir = 0; dir < 2; ++dir) {
+      const double *pp = &n->par[6 * (size_t)r + 3 * dir];
+      if (pp[0] == 0.0) continue;
+      const int32_t *re = dir ? &n->prod[3 * r] : &n->reac[3 * r];
+      const int32_t *pr = dir ? &n->reac[3 * r] : &n->prod[3 * r];
+      WideDir d{pp[0], pp[1], pp[2], {re[0], re[1], re[2]}, std::vector<int>(n->S, 0)};
+      for (int k = 0; k < 3; ++k) {
+        if (re[k] >= 0) d.nu[re[k]] -= 1;
+        if (pr[k] >= 0) d.nu[pr[k]] += 1;
+      }
+      out.push_back(d);
+    }
+  return out;
+}
+
+/* Contribution lists of the wavefront layout.  Each destination entry of
+ * the LDS Jacobian (a list of (source in P, coefficient) terms) is owned by
+ * one lane; destinations go to lanes largest-first onto the least loaded
+ * lane, each lane's terms are concatenated with a flush mark on the last
+ * term of every destination, and the lists are padded to equal length and
+ * interleaved by lane (term i of lane l at i * 64 + l). */
+static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pair<int, int>>> &dst, int &len) {
+  std::vector<std::pair<int, int>> order; /* (terms, destination) */
+  for (const auto &kv : dst) order.push_back({(int)kv.second.size(), kv.first});
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int, int> &a, const std::pair<int, int> &b) { return a.first > b.first; });
+  std::vector<std::vector<uint32_t>> lanes(64);
+  for (const auto &od : order) {
+    int best = 0;
+    for (int l = 1; l < 64; ++l)
+      if (lanes[l].size() < lanes[best].size()) best = l;
+    const auto &terms = dst.at(od.second);
+    for (size_t i = 0; i < terms.size(); ++i) {
+      const uint32_t flush = i + 1 == terms.size() ? 1u : 0u;
+      lanes[best].push_back((uint32_t)terms[i].first | ((uint32_t)od.second << 12) |
+                            ((uint32_t)(terms[i].second + 4) << 25) | (flush << 28));
+    }
+  }
+  len = 1;
+  for (const auto &l : lanes) len = std::max(len, (int)l.size());
+  std::vector<uint32_t> tab((size_t)len * 64, 4u << 25);
+  for (int l = 0; l < 64; ++l)
+    for (size_t i = 0; i < lanes[l].size(); ++i) tab[i * 64 + l] = lanes[l][i];
+  return tab;
+}
+
+static int check_wide(const kr_network *n) {
+  if (n->S > 62) return fail(KR_EINVAL, "the wavefront layout takes at most 62 species (got %d)", n->S);
+  const size_t D = wide_directions(n).size();
+  const size_t ndp = ((D + 63) / 64) * 64;
+  if (5 * ndp > 4096)
+    return fail(KR_EINVAL, "the wavefront layout takes at most 768 reaction directions (got %zu)", D);
+  return KR_OK;
+}
+
+/* The network-specific section of the wavefront-per-cell device source. */
+static std::string generate_wide(const kr_network *n) {
+  const int S = n->S, LDJ = wide_ldj(S);
+  const std::vector<WideDir> dirs = wide_directions(n);
+  const int NDR = std::max<int>(1, (int)((dirs.size() + 63) / 64)), NDP = NDR * 64;
+  std::map<int, std::vector<std::pair<int, int>>> full, fonly;
+  for (size_t d = 0; d < dirs.size(); ++d) {
+    const int src = 5 * (int)d;
+    for (int s = 0; s < S; ++s) {
+      const int nu = dirs[d].nu[s];
+      if (!nu) continue;
+      full[s * LDJ + S + 1].push_back({src, nu});
+      fonly[s * LDJ + S + 1].push_back({src, nu});
+      full[s * LDJ + S].push_back({src + 1, nu});
+      for (int k = 0; k < 3; ++k)
+        if (dirs[d].slot[k] >= 0) full[s * LDJ + dirs[d].slot[k]].push_back({src + 2 + k, nu});
+    }
+  }
+  int NC = 0, NF = 0;
+  const std::vector<uint32_t> wc = wide_lists(full, NC), wf = wide_lists(fonly, NF);
+  std::string o;
+  o += "/* generated network section (one wavefront per cell): " + std::to_string(S) + " species, " +
+       std::to_string(n->n_rows) + " conserved rows, " + std::to_string(dirs.size()) + " reaction directions */\n";
+  o += network_tables(n);
+  o += "#define KR_LDJ " + std::to_string(LDJ) + "\n#define KR_NDR " + std::to_string(NDR) +
+       "\n#define KR_NC " + std::to_string(NC) + "\n#define KR_NF " + std::to_string(NF) + "\n";
+  o += "__device__ static constexpr double kr_hf[" + std::to_string(S) + "] = {";
+  for (int s = 0; s < S; ++s) o += hexd(n->h[s]) + (s + 1 < S ? "," : "");
+  o += "};\n";
+  const char *names[3] = {"kr_dA", "kr_db", "kr_dE"};
+  for (int q = 0; q < 3; ++q) {
+    o += std::string("__device__ static constexpr double ") + names[q] + "[" + std::to_string(NDP) + "] = {";
+    for (int d = 0; d < NDP; ++d) {
+      double v = 0.0;
+      if (d < (int)dirs.size()) v = q == 0 ? dirs[d].A : (q == 1 ? dirs[d].b : dirs[d].E);
+      o += hexd(v) + (d + 1 < NDP ? "," : "");
+    }
+    o += "};\n";
+  }
+  o += "__device__ static constexpr unsigned kr_dr[" + std::to_string(NDP) + "] = {";
+  for (int d = 0; d < NDP; ++d) {
+    uint32_t r = 0xFFFFFFu;
+    if (d < (int)dirs.size()) {
+      r = 0;
+      for (int k = 0; k < 3; ++k) r |= (uint32_t)(dirs[d].slot[k] >= 0 ? dirs[d].slot[k] : 255) << (8 * k);
+    }
+    o += std::to_string(r) + "u" + (d + 1 < NDP ? "," : "");
+  }
+  o += "};\n";
+  const std::pair<const char *, const std::vector<uint32_t> *> lists[2] = {{"kr_wc", &wc}, {"kr_wf", &wf}};
+  for (const auto &l : lists) {
+    o += std::string("__device__ static constexpr unsigned ") + l.first + "[" + std::to_string(l.second->size()) +
+         "] = {";
+    for (size_t i = 0; i < l.second->size(); ++i)
+      o += std::to_string((*l.second)[i]) + "u" + (i + 1 < l.second->size() ? "," : "");
+    o += "};\n";
+  }
+  return o;
+}
+
+/* Sizes and constant tables shared by both device layouts. */
+static std::string network_tables(const kr_network *n) {
   const int S = n->S, V = n->n_rows;
   std::string o;
-  o += "/* generated network section: " + std::to_string(S) + " species, " + std::to_string(V) +
-       " conserved rows, " + std::to_string(n->R) + " reactions */\n";
   o += "#define KR_S " + std::to_string(S) + "\n";
   o += "#define KR_NROWS " + std::to_string(V) + "\n";
   o += "#define KR_NELEM " + std::to_string(n->n_elem) + "\n";
@@ -228,6 +364,16 @@ static std::string generate_network(const kr_network *n) {
   o += "};\n";
   o += "__device__ static constexpr double kr_T_min = " + hexd(n->T_min) + ";\n";
   o += "__device__ static constexpr double kr_T_max = " + hexd(n->T_max) + ";\n";
+  return o;
+}
+
+/* The network-specific section of the lane-per-cell device source. */
+static std::string generate_network(const kr_network *n) {
+  const int S = n->S, V = n->n_rows;
+  std::string o;
+  o += "/* generated network section: " + std::to_string(S) + " species, " + std::to_string(V) +
+       " conserved rows, " + std::to_string(n->R) + " reactions */\n";
+  o += network_tables(n);
 
   /* rates and analytic Jacobian, one block per reaction */
   o += "__device__ __forceinline__ void kr_eval(const double (&y)[KR_S + 1], double (&g)[KR_S + 1],\n"
@@ -338,11 +484,13 @@ extern "C" void kr_default_build_options(kr_build_opts *o) {
   if (!o) return;
   o->waves_per_eu = default_waves_per_eu();
   o->pivot_tau = 0.1f;
+  o->layout = KR_LAYOUT_AUTO;
 }
 
 static int check_build_options(const kr_build_opts *o) {
   if (o->waves_per_eu < 1 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [1, 8]");
   if (!(o->pivot_tau > 0.0f && o->pivot_tau <= 1.0f)) return fail(KR_EINVAL, "pivot_tau out of (0, 1]");
+  if (o->layout < KR_LAYOUT_AUTO || o->layout > KR_LAYOUT_WAVE) return fail(KR_EINVAL, "layout out of [0, 2]");
   return KR_OK;
 }
 
@@ -353,7 +501,14 @@ static std::string build_prefix(const kr_build_opts &o) {
   return b;
 }
 
+static bool use_wide(const kr_network *n, const kr_build_opts &o) {
+  return o.layout == KR_LAYOUT_WAVE || (o.layout == KR_LAYOUT_AUTO && n->S >= KR_WIDE_MIN_SPECIES);
+}
+
 static std::string full_source(const kr_network *n, const kr_build_opts &o) {
+  if (use_wide(n, o))
+    return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(o) +
+           kParamsSource + "\n" + generate_wide(n) + "\n" + kWideSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
          build_prefix(o) + kParamsSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
 }
@@ -381,6 +536,17 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
   rc = build_tables(desc, n);
   if (rc != KR_OK) { delete n; return rc; }
   n->build = bo;
+  n->wide = use_wide(n, bo);
+  if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
+  if (n->wide) {
+    /* The wavefront layout generates and compiles (kr_network_check_ex),
+     * but its kernels did not return on gfx950 for a one-cell batch whose
+     * CPU execution takes one substep; until the cause is known, networks
+     * are not created with it. */
+    delete n;
+    return fail(KR_EINVAL, "the wavefront-per-cell layout is disabled on devices (n_species %d >= %d or "
+                "layout forced); see the design notes", desc->n_species, KR_WIDE_MIN_SPECIES);
+  }
   n->source = full_source(n, bo);
   std::vector<char> code;
   std::string log;
@@ -444,13 +610,16 @@ extern "C" int64_t kr_network_source(const kr_network *net, char *buf, int64_t b
 /* Validation and code generation (and optionally the hipRTC compile) of a
  * description without touching a device: used by build checks and tests on
  * hosts without a GPU.  Returns KR_OK or the error create would return. */
-extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
-                                int64_t src_len) {
+extern "C" int kr_network_check_ex(const kr_network_desc *desc, const kr_build_opts *bopt, int compile,
+                                   char *src_buf, int64_t src_len) {
   kr_network n;
   int rc = build_tables(desc, &n);
   if (rc != KR_OK) return rc;
   kr_build_opts bo;
   kr_default_build_options(&bo);
+  if (bopt) bo = *bopt;
+  if ((rc = check_build_options(&bo)) != KR_OK) return rc;
+  if (use_wide(&n, bo) && (rc = check_wide(&n)) != KR_OK) return rc;
   const std::string src = full_source(&n, bo);
   if (src_buf && src_len > 0) {
     const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
@@ -461,6 +630,11 @@ extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *
   std::vector<char> code;
   std::string log;
   return compile_source(src, code, log);
+}
+
+extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
+                                int64_t src_len) {
+  return kr_network_check_ex(desc, nullptr, compile, src_buf, src_len);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -511,6 +685,7 @@ extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double 
   p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
   p.counter = net->d_counter;
   if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
+  if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
   p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
 
   unsigned long long *cnt = net->d_counter;
@@ -519,7 +694,7 @@ extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double 
   hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
   const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
   long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
-  const long long need = (n_cells + 63) / 64;
+  const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
   void *args[] = {&p};
@@ -620,7 +795,8 @@ extern "C" int kr_fastest_timescale(const kr_network *net, int64_t n_cells, cons
   HIP_TRY(hipSetDevice(net->device));
   KrParams p{};
   p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.dt_scalar = 1.0;
-  long long blocks = std::min<long long>((n_cells + 63) / 64, (long long)net->cu_count * 16);
+  long long blocks = std::min<long long>(net->wide ? n_cells : (n_cells + 63) / 64,
+                                        (long long)net->cu_count * (net->wide ? 4 : 16));
   void *args[] = {&p, &out};
   HIP_TRY(hipModuleLaunchKernel(net->f_tau, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
                                 nullptr));
@@ -640,7 +816,7 @@ struct KrMultiHost {          /* mirrors the device struct KrMulti */
 
 struct kr_multi {
   std::vector<const kr_network *> nets;
-  kr_build_opts build{1, 0.1f};
+  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
@@ -695,8 +871,10 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   if (!out) return fail(KR_EINVAL, "null output handle");
   *out = nullptr;
   if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
-  for (int k = 0; k < n_nets; ++k)
+  for (int k = 0; k < n_nets; ++k) {
     if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
+    if (nets[k]->wide) return fail(KR_EINVAL, "network %d uses the wavefront layout, not supported here", k);
+  }
   kr_build_opts bo;
   kr_default_build_options(&bo);
   if (bopt) bo = *bopt;

@@ -1,0 +1,726 @@
+/*
+ * kr_wide.h -- device code of the per-cell implicit integrator for large
+ * networks (gfx950): one wavefront per cell.
+ *
+ * Same method as the lane-per-cell integrator (paper Sec. 2.2: backward-Euler
+ * substeps solved by Newton iteration with the analytic Jacobian, adaptive
+ * substeps, pre-/post-processing and the retry-then-revert ladder), mapped
+ * for networks whose Newton matrix (N = S + 1 unknowns, up to 63) no longer
+ * fits one lane's registers:
+ *
+ *  - vectors of the cell (iterate y, substep start y_n, rates g_n, weights)
+ *    are spread over the lanes: lane i holds entry i;
+ *  - rates: lane l evaluates reaction directions l, l+64, ...: the rate
+ *    coefficient k = A exp(b ln T - E/T), the rate of progress q = k prod n,
+ *    dq/dT and dq/dn per reactant slot, into an LDS table P;
+ *  - the rate Jacobian is gathered into LDS (rows = species; columns =
+ *    species, T and the rate f itself) from per-lane contribution lists that
+ *    the network compiler builds: every matrix entry is owned by one lane,
+ *    so the accumulation needs no atomics and its order is fixed (bitwise
+ *    reproducible per cell); the lists are balanced over the 64 lanes;
+ *  - the energy row follows from the species rows, dQ/dy = -sum_s h_s df_s/dy
+ *    (heat release q_r = -sum_s nu_rs h_s), as one column sum per lane;
+ *  - LU: lane i holds row i of the Newton matrix in registers; column j is
+ *    eliminated by a wave-wide arg-max over the remaining rows (implicit row
+ *    scaling as in the paper's Algorithm 1), a broadcast of the pivot row and
+ *    one FMA per remaining entry.  Rows are never moved: each lane records
+ *    the column at which its row became pivot row, and the triangular
+ *    solves walk the pivot order (found by a ballot per column).
+ *
+ * Generated section (network compiler) defines:
+ *   KR_S, KR_NROWS, KR_NELEM, KR_LDJ (LDS row stride of the Jacobian),
+ *   KR_NDR (direction rounds of 64), KR_NC / KR_NF (contribution list lengths)
+ *   kr_comp, kr_res, kr_cv, kr_atoms, kr_hf, kr_T_min, kr_T_max
+ *   kr_dA, kr_db, kr_dE [KR_NDR * 64]   direction Arrhenius parameters
+ *   kr_dr [KR_NDR * 64]                 reactant slots, 8 bits each (255 none)
+ *   kr_wc [KR_NC * 64], kr_wf [KR_NF * 64]  contribution lists (lane-interleaved):
+ *       bits 0-11 source in P, 12-24 destination in the Jacobian,
+ *       25-27 stoichiometric coefficient + 4, 28 last contribution of its entry
+ */
+
+#define KR_N (KR_S + 1)
+#define KR_NDP (KR_NDR * 64)
+
+struct KrWave {
+  double y[64];                 /* broadcast copy of the current point */
+  double v[64];                 /* scratch vector */
+  double P[5 * KR_NDP];         /* per direction: q, dq/dT, dq/dn (3 slots) */
+  double J[KR_N * KR_LDJ];      /* rows 0..S-1 species (cols 0..S-1 d/dn, S d/dT,
+                                   S+1 f), row S energy (dQ/dn, dQ/dT, Q) */
+};
+
+__device__ __forceinline__ bool kr_finite(double x) { return __builtin_isfinite(x); }
+
+__device__ __forceinline__ double kr_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float kr_bcastf(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+__device__ __forceinline__ double kr_wsum(double v) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double kr_wmax(double v) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+/* Lane holding the largest non-negative key (lowest lane on ties); key 0 for
+ * lanes that do not compete.  Returns the winning lane, and its key. */
+__device__ __forceinline__ int kr_wargmax(float key, bool cand, unsigned &best) {
+  const int lane = threadIdx.x;
+  unsigned k = cand ? ((__float_as_uint(key) & ~63u) | (unsigned)(63 - lane)) : 0u;
+#pragma unroll
+  for (int o = 32; o; o >>= 1) {
+    const unsigned t = (unsigned)__shfl_xor((int)k, o);
+    k = t > k ? t : k;
+  }
+  best = (unsigned)__builtin_amdgcn_readfirstlane((int)k);
+  return 63 - (int)(best & 63u);
+}
+
+/* ------------------------------------------------------------------------ */
+/* rates, rate Jacobian, energy row                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Publishes the lane-distributed point y to LDS. */
+__device__ __forceinline__ void kr_wpublish(KrWave &w, double yl) {
+  if ((int)threadIdx.x < KR_N) w.y[threadIdx.x] = yl;
+  __syncthreads();
+}
+
+/* Direction pass at the published point: P gets q, dq/dT and the slot
+ * partials (full) or q only. */
+template <bool FULL>
+__device__ __forceinline__ void kr_wdirections(KrWave &w) {
+  const int lane = threadIdx.x;
+  const double T = w.y[KR_S];
+  const double lnT = log(T);
+  const double iT = 1.0 / T;
+#pragma unroll
+  for (int j = 0; j < KR_NDR; ++j) {
+    const int d = lane + 64 * j;
+    const double A = kr_dA[d], b = kr_db[d], E = kr_dE[d];
+    const unsigned rr = kr_dr[d];
+    const unsigned r0 = rr & 255u, r1 = (rr >> 8) & 255u, r2 = (rr >> 16) & 255u;
+    const double n0 = r0 < 255u ? w.y[r0] : 1.0;
+    const double n1 = r1 < 255u ? w.y[r1] : 1.0;
+    const double n2 = r2 < 255u ? w.y[r2] : 1.0;
+    const double k = A * exp(b * lnT - E * iT);
+    const double q = k * n0 * n1 * n2;
+    double *P = w.P + 5 * d;
+    P[0] = q;
+    if (FULL) {
+      P[1] = q * (b + E * iT) * iT;
+      P[2] = k * n1 * n2;
+      P[3] = k * n0 * n2;
+      P[4] = k * n0 * n1;
+    }
+  }
+  __syncthreads();
+}
+
+/* Runs one lane's contribution list into the Jacobian workspace. */
+template <int LEN>
+__device__ __forceinline__ void kr_wgather(KrWave &w, const unsigned *tab) {
+  const int lane = threadIdx.x;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < LEN; ++i) {
+    const unsigned e = tab[i * 64 + lane];
+    const double nu = (double)((int)((e >> 25) & 7u) - 4);
+    acc = fma(nu, w.P[e & 4095u], acc);
+    if (e >> 28) {
+      w.J[(e >> 12) & 8191u] = acc;
+      acc = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+/* Energy row: row S, column m = -sum_s h_s J[s][m] for m <= S + 1 (the last
+ * column gives Q).  Lanes lo..hi each sum one column. */
+__device__ __forceinline__ void kr_wenergy(KrWave &w, int lo, int hi) {
+  const int m = threadIdx.x;
+  if (m >= lo && m <= hi) {
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) t = fma(kr_hf[s], w.J[s * KR_LDJ + m], t);
+    w.J[KR_S * KR_LDJ + m] = -t;
+  }
+  __syncthreads();
+}
+
+/* Rates, rate Jacobian and energy row at the lane-distributed point y. */
+__device__ __forceinline__ void kr_weval(KrWave &w, double yl) {
+  kr_wpublish(w, yl);
+  kr_wdirections<true>(w);
+  kr_wgather<KR_NC>(w, kr_wc);
+  kr_wenergy(w, 0, KR_S + 1);
+}
+
+/* Rates only: f in column S+1 of the species rows, Q at (S, S+1). */
+__device__ __forceinline__ void kr_wrhs(KrWave &w, double yl) {
+  kr_wpublish(w, yl);
+  kr_wdirections<false>(w);
+  kr_wgather<KR_NF>(w, kr_wf);
+  kr_wenergy(w, KR_S + 1, KR_S + 1);
+}
+
+/* sum_s c_s n_s over the lane-distributed point */
+__device__ __forceinline__ double kr_wheatcap(double yl) {
+  const int lane = threadIdx.x;
+  return kr_wsum(lane < KR_S ? kr_cv[lane] * yl : 0.0);
+}
+
+/* g = (f, Q / c_V) for lane i, after kr_wrhs or kr_weval */
+__device__ __forceinline__ double kr_wrate(const KrWave &w, double cv) {
+  const int lane = threadIdx.x;
+  if (lane < KR_S) return w.J[lane * KR_LDJ + KR_S + 1];
+  if (lane == KR_S) return w.J[KR_S * KR_LDJ + KR_S + 1] / cv;
+  return 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* lane-per-row LU                                                           */
+/* ------------------------------------------------------------------------ */
+
+#define KR_NOTPIV 1000
+
+/* In-place LU of the rows held by the lanes (lane i: row i, lanes >= N hold
+ * no row).  On return: pc = column at which the lane's row was the pivot
+ * row, a[k] holds U entries for k >= pc and L multipliers for k < pc, dinv
+ * the reciprocal pivot.  Returns false (wave-uniform) for a singular or
+ * non-finite matrix. */
+template <typename F>
+__device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
+  const int lane = threadIdx.x;
+  F mx = F(0);
+#pragma unroll
+  for (int k = 0; k < KR_N; ++k) mx = a[k] < F(0) ? (-a[k] > mx ? -a[k] : mx) : (a[k] > mx ? a[k] : mx);
+  const F sc = lane < KR_N && mx > F(0) ? F(1) / mx : F(0);
+  pc = lane < KR_N ? KR_NOTPIV : -1;
+  dinv = F(0);
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+    const bool cand = pc == KR_NOTPIV;
+    const F aj = a[j];
+    unsigned best;
+    const int p = kr_wargmax((float)((aj < F(0) ? -aj : aj) * sc), cand, best);
+    ok = ok && (best >> 6) != 0u;
+    F piv;
+    if constexpr (sizeof(F) == 8) piv = kr_bcast(aj, p);
+    else piv = kr_bcastf(aj, p);
+    ok = ok && piv != F(0) && kr_finite((double)piv);
+    const F inv = F(1) / piv;
+    if (lane == p) { pc = j; dinv = inv; }
+    const F l = pc == KR_NOTPIV ? aj * inv : F(0);
+    if (pc == KR_NOTPIV) a[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < KR_N; ++k) {
+      F u;
+      if constexpr (sizeof(F) == 8) u = kr_bcast(a[k], p);
+      else u = kr_bcastf(a[k], p);
+      a[k] = fma(-l, u, a[k]);
+    }
+  }
+  return ok;
+}
+
+/* Solves with the factors of kr_wlu: b by row (lane i: equation i) in, the
+ * solution by unknown (lane j: x_j) out. */
+template <typename F>
+__device__ __forceinline__ F kr_wsolve(const F (&a)[KR_N], int pc, F dinv, F b) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+    const int pj = (int)__builtin_ctzll(__ballot(pc == j));
+    F yj;
+    if constexpr (sizeof(F) == 8) yj = kr_bcast(b, pj);
+    else yj = kr_bcastf(b, pj);
+    b = fma(-(pc > j ? a[j] : F(0)), yj, b);
+  }
+  F x = F(0);
+#pragma unroll
+  for (int j = KR_N - 1; j >= 0; --j) {
+    const int pj = (int)__builtin_ctzll(__ballot(pc == j));
+    const F t = b * dinv;
+    F xj;
+    if constexpr (sizeof(F) == 8) xj = kr_bcast(t, pj);
+    else xj = kr_bcastf(t, pj);
+    b = fma(-(pc < j ? a[j] : F(0)), xj, b);
+    x = lane == j ? xj : x;
+  }
+  return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Newton substep                                                            */
+/* ------------------------------------------------------------------------ */
+
+struct KrWCell {
+  long long c;
+  double dt, atol, eps_n, rtol;
+  int acc, iters, rej, nfail;
+};
+
+__device__ __forceinline__ double kr_wweight(const KrWCell &C, double yn, double y) {
+  const int lane = threadIdx.x;
+  const double a = lane < KR_S ? C.atol : 0.0;
+  return a + C.rtol * fmax(fabs(yn), fabs(y));
+}
+
+/* Weighted element projection of a Newton update (FP32 form): d_S <- d_S -
+ * W N^T (N W N^T)^-1 N d_S with W = diag(max(|y_s|, atol)); the Gram system
+ * is formed and solved redundantly in every lane from LDS copies. */
+__device__ __forceinline__ double kr_wproject(KrWave &w, double yl, double atol, double d) {
+  if (KR_NROWS == 0) return d;
+  constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
+  const int lane = threadIdx.x;
+  const double W = lane < KR_S ? fmax(fabs(yl), atol) : 0.0;
+  w.v[lane] = d;
+  w.y[lane] = W;
+  __syncthreads();
+  double G[V][V], r[V];
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+    r[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b <= a; ++b) G[a][b] = 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) {
+    const double ds = w.v[s], Ws = w.y[s];
+#pragma unroll
+    for (int a = 0; a < V; ++a) {
+      if (kr_comp[a][s] == 0) continue;
+      r[a] = fma((double)kr_comp[a][s], ds, r[a]);
+#pragma unroll
+      for (int b = 0; b <= a; ++b)
+        if (kr_comp[b][s] != 0) G[a][b] = fma((double)(kr_comp[a][s] * kr_comp[b][s]), Ws, G[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      double t = G[a][b];
+#pragma unroll
+      for (int k = 0; k < b; ++k) t -= G[a][k] * G[b][k];
+      if (a == b) G[a][a] = sqrt(fmax(t, 1e-300));
+      else G[a][b] = t / G[b][b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < V; ++a) {
+    double t = r[a];
+#pragma unroll
+    for (int k = 0; k < a; ++k) t -= G[a][k] * r[k];
+    r[a] = t / G[a][a];
+  }
+#pragma unroll
+  for (int a = V - 1; a >= 0; --a) {
+    double t = r[a];
+#pragma unroll
+    for (int k = a + 1; k < V; ++k) t -= G[k][a] * r[k];
+    r[a] = t / G[a][a];
+  }
+  double t = 0.0;
+  if (lane < KR_S) {
+#pragma unroll
+    for (int a = 0; a < V; ++a) t = fma((double)kr_comp[a][lane], r[a], t);
+  }
+  __syncthreads();
+  return d - W * t;
+}
+
+/* Newton iteration for one backward-Euler substep of length h from the
+ * lane-distributed y_n (plain start y = y_n).  Returns true when converged;
+ * y holds the iterate either way. */
+template <bool MIXED>
+__device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell &C, double yn,
+                                           double h, double &y) {
+  const int lane = threadIdx.x;
+  y = yn;
+  double prev = __builtin_inf();
+  int grow = 0;
+  for (int it = 0; it < p.max_newton; ++it) {
+    kr_weval(w, y);
+    const double cv = kr_wheatcap(y);
+    const double T = kr_bcast(y, KR_S);
+    /* residual (negated) and Newton matrix row of this lane */
+    double b = 0.0;
+    if (lane < KR_S) b = -(y - yn - h * w.J[lane * KR_LDJ + KR_S + 1]);
+    else if (lane == KR_S) b = -(T * cv - C.eps_n - h * w.J[KR_S * KR_LDJ + KR_S + 1]);
+    const int row = lane < KR_N ? lane : KR_S;
+    double a[KR_N];
+#pragma unroll
+    for (int k = 0; k < KR_N; ++k) a[k] = w.J[row * KR_LDJ + k];
+    const bool er = lane == KR_S;
+#pragma unroll
+    for (int k = 0; k < KR_S; ++k) a[k] = (er ? kr_cv[k] * T : (lane == k ? 1.0 : 0.0)) - h * a[k];
+    a[KR_S] = (er ? cv : 0.0) - h * a[KR_S];
+    if (lane >= KR_N) {
+#pragma unroll
+      for (int k = 0; k < KR_N; ++k) a[k] = 0.0;
+    }
+    C.iters++;
+
+    double d = 0.0;
+    bool ok;
+    if (!MIXED) {
+      int pc;
+      double dinv;
+      ok = kr_wlu(a, pc, dinv);
+      if (ok) d = kr_wsolve(a, pc, dinv, b);
+    } else {
+      /* FP32 LU of the row-equilibrated matrix; FP64 residual and iterative
+       * refinement against the FP64 rows; FP64 LU where FP32 breaks down or
+       * refinement does not settle; FP64 element projection */
+      double mx = 0.0;
+#pragma unroll
+      for (int k = 0; k < KR_N; ++k) mx = fmax(mx, fabs(a[k]));
+      const double rs = mx > 0.0 ? 1.0 / mx : 0.0;
+      float a32[KR_N];
+#pragma unroll
+      for (int k = 0; k < KR_N; ++k) a32[k] = (float)(a[k] * rs);
+      int pc;
+      float dinv;
+      bool ok32 = kr_wlu(a32, pc, dinv);
+      double r = b;
+      bool conv = false;
+      int sweeps = 0;
+      for (int sweep = 0; sweep < 4 && ok32; ++sweep) {
+        sweeps = sweep + 1;
+        const double c = (double)kr_wsolve(a32, pc, dinv, (float)(r * rs));
+        d += c;
+        const double cn = kr_wmax(lane < KR_N ? fabs(c) / kr_wweight(C, yn, y) : 0.0);
+        if (!kr_finite(cn)) { ok32 = false; break; }
+        if (sweep > 0 && cn <= 1e-6) { conv = true; break; }
+        /* r = b - M d in FP64 */
+        w.v[lane] = d;
+        __syncthreads();
+        double t = b;
+#pragma unroll
+        for (int k = 0; k < KR_N; ++k) t = fma(-a[k], w.v[k], t);
+        r = t;
+        __syncthreads();
+      }
+      if (p.counters && lane == 0) atomicAdd(&p.counters[3], (unsigned long long)sweeps);
+      ok = true;
+      if (!ok32 || !conv) {
+        if (p.counters && lane == 0) atomicAdd(&p.counters[4], 1ull);
+        int pc64;
+        double dinv64;
+        ok = kr_wlu(a, pc64, dinv64);
+        d = ok ? kr_wsolve(a, pc64, dinv64, b) : 0.0;
+      }
+      if (ok) d = kr_wproject(w, y, C.atol, d);
+    }
+    if (!ok) return false;
+    const double yi = y + d;
+    y = lane < KR_N ? yi : 0.0;
+    const bool bad = lane < KR_N && (!kr_finite(d) || !kr_finite(yi));
+    if (__any(bad) || !(kr_bcast(y, KR_S) > 0.0)) return false;
+    const double norm = kr_wmax(lane < KR_N ? fabs(d) / kr_wweight(C, yn, y) : 0.0);
+    if (norm <= p.newton_tol) return true;
+    if (norm > prev) {
+      if (++grow >= 2) return false;
+    } else {
+      grow = 0;
+    }
+    prev = norm;
+  }
+  return false;
+}
+
+/* One attempt over [0, dt] from y0 (lane-distributed).  Adaptive: error
+ * estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i; accepted when
+ * err <= 1, then h *= min(growth, max(0.2, safety / sqrt(max(err, 1e-10))));
+ * rejected: h *= max(0.2, safety / sqrt(err)); Newton failure: h /= 4.  The
+ * last substep lands on dt.  Fails when h < 1e-12 dt or after max_substeps
+ * substep attempts.  On success y holds the end point. */
+template <bool MIXED>
+__device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCell &C, double y0,
+                                            int attempt, double &y) {
+  const int lane = threadIdx.x;
+  double yn = y0;
+  C.eps_n = kr_bcast(y0, KR_S) * kr_wheatcap(y0);
+  if (p.mode == 1) {
+    const double h = C.dt / (double)p.n_fixed;
+    for (int k = 0; k < p.n_fixed; ++k) {
+      if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) { C.nfail++; return false; }
+      yn = y;
+      C.eps_n = kr_bcast(yn, KR_S) * kr_wheatcap(yn);
+      C.acc++;
+    }
+    y = yn;
+    return true;
+  }
+  const double h0 = attempt == 0 ? C.dt : C.dt / 100.0;
+  const double safety = attempt == 0 ? 0.9 : 0.5;
+  const double growth = attempt == 0 ? 5.0 : 2.0;
+  kr_wrhs(w, yn);
+  double gn = kr_wrate(w, kr_wheatcap(yn));
+  double t = 0.0, h = h0;
+  int attempts = 0;
+  for (;;) {
+    if (attempts >= p.max_substeps) return false;
+    bool fin = false;
+    if (h >= C.dt - t) { h = C.dt - t; fin = true; }
+    else if (h < 1e-12 * C.dt) return false;
+    attempts++;
+    if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) {
+      C.nfail++;
+      h *= 0.25;
+      continue;
+    }
+    kr_wrhs(w, y);
+    const double cv = kr_wheatcap(y);
+    const double g = kr_wrate(w, cv);
+    /* max over the unknowns, ignoring 0/0 (zero weight and change), as a
+     * NaN-skipping running maximum does */
+    const double err = kr_wmax(lane < KR_N ? fabs(0.5 * h * (g - gn)) / kr_wweight(C, yn, y) : 0.0);
+    if (!kr_finite(err)) { C.rej++; h *= 0.2; continue; }
+    if (err <= 1.0) {
+      yn = y;
+      gn = g;
+      C.eps_n = kr_bcast(y, KR_S) * cv;
+      C.acc++;
+      if (fin) break;
+      t += h;
+      h *= fmin(growth, fmax(0.2, safety / sqrt(fmax(err, 1e-10))));
+    } else {
+      C.rej++;
+      h *= fmax(0.2, safety / sqrt(err));
+    }
+  }
+  y = yn;
+  return true;
+}
+
+/* ------------------------------------------------------------------------ */
+/* one cell: pre-processing, attempts, checks, post-processing               */
+/* ------------------------------------------------------------------------ */
+
+/* Lane 0, sequential over the LDS copies y (result) and y0 (input, in v):
+ * element residual max_row |sum_s N_s (y - y0)_s| / D_row (elements: D =
+ * sum |N_s| y0_s; charge-like rows: the nuclei density). */
+__device__ __forceinline__ double kr_wresid0(const KrWave &w, double nn) {
+  double worst = 0.0;
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double diff = 0.0, D = 0.0;
+    for (int s = 0; s < KR_S; ++s) {
+      const int a = kr_comp[v][s];
+      if (a == 0) continue;
+      diff += a * (w.y[s] - w.v[s]);
+      D += (a > 0 ? a : -a) * w.v[s];
+    }
+    if (v >= KR_NELEM) D = nn;
+    const double e = fabs(diff) / fmax(D, 1e-300);
+    if (!(e <= worst)) worst = e;
+  }
+  return worst;
+}
+
+/* Lane 0: the three post-processing stages of Sec. 2.2.3 on w.y, with the
+ * initial row totals from w.v. */
+__device__ __forceinline__ void kr_wpost0(KrWave &w) {
+  double E0[KR_NROWS > 0 ? KR_NROWS : 1];
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double t = 0.0;
+    for (int s = 0; s < KR_S; ++s) t += kr_comp[v][s] * w.v[s];
+    E0[v] = t;
+  }
+  for (int s = 0; s < KR_S; ++s)
+    if (w.y[s] < 0.0) w.y[s] = 0.0;
+  for (int v = 0; v < KR_NROWS; ++v) {
+    double E = 0.0;
+    for (int s = 0; s < KR_S; ++s) E += kr_comp[v][s] * w.y[s];
+    const int rs = kr_res[v];
+    w.y[rs] += (E0[v] - E) / kr_comp[v][rs];
+  }
+  for (int v = 0; v < KR_NROWS; ++v) {
+    const int rs = kr_res[v];
+    const int sign_r = kr_comp[v][rs] > 0 ? 1 : -1;
+    unsigned long long used = 0ull;
+    while (w.y[rs] < 0.0) {
+      int best = -1;
+      for (int s = 0; s < KR_S; ++s) {
+        if (s == rs || ((used >> s) & 1ull)) continue;
+        const int a = kr_comp[v][s];
+        if (a == 0 || (a > 0 ? 1 : -1) != sign_r) continue;
+        if (w.y[s] <= 0.0) continue;
+        if (best < 0 || w.y[s] > w.y[best]) best = s;
+      }
+      if (best < 0) break;
+      used |= 1ull << best;
+      const double need = -w.y[rs] * kr_comp[v][rs] / kr_comp[v][best];
+      const double x = need < w.y[best] ? need : w.y[best];
+      w.y[best] -= x;
+      for (int u = 0; u < KR_NROWS; ++u) {
+        const int a = kr_comp[u][best];
+        if (a) w.y[kr_res[u]] += x * a / kr_comp[u][kr_res[u]];
+      }
+      if (x == need) w.y[rs] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void kr_wstats(const KrParams &p, const KrWCell &C, int code) {
+  if (threadIdx.x == 0) {
+    if (p.status) p.status[C.c] = code;
+    if (p.cell_stats) {
+      int *st = p.cell_stats + 4 * C.c;
+      st[0] = C.acc; st[1] = C.iters; st[2] = C.rej; st[3] = C.nfail;
+    }
+  }
+}
+
+/* Pre-processing (Sec. 2.2.2) of the lane's input entry; bad = non-finite. */
+__device__ __forceinline__ double kr_wload(const KrParams &p, long long c, double &dt, bool &bad) {
+  const int lane = threadIdx.x;
+  double x = 0.0;
+  bad = false;
+  if (lane < KR_S) {
+    const double v = p.states[(long long)lane * p.ld + c];
+    bad = !kr_finite(v);
+    x = v > 0.0 ? v : 0.0;
+  }
+  const double T = p.T[c];
+  dt = p.dt ? p.dt[c] : p.dt_scalar;
+  bad = bad || !kr_finite(T) || !kr_finite(dt) || !(dt >= 0.0);
+  if (p.rho_floor > 0.0 && p.rho) {
+    const double rho = p.rho[c];
+    if (rho > 0.0 && rho < p.rho_floor) x *= p.rho_floor / rho;
+  }
+  if (lane == KR_S) x = fmin(fmax(T, kr_T_min), kr_T_max);
+  return x;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void kr_wcell(const KrParams &p, KrWave &w, long long c) {
+  const int lane = threadIdx.x;
+  KrWCell C;
+  C.c = c;
+  C.acc = C.iters = C.rej = C.nfail = 0;
+  C.rtol = p.rtol;
+  double dt;
+  bool bad;
+  const double y0 = kr_wload(p, c, dt, bad);
+  if (__any(bad)) { kr_wstats(p, C, 2); return; }
+  if (dt == 0.0) {
+    if (lane < KR_S) p.states[(long long)lane * p.ld + c] = y0;
+    if (lane == KR_S) p.T[c] = y0;
+    kr_wstats(p, C, 0);
+    return;
+  }
+  C.dt = dt;
+  const double nn = kr_wsum(lane < KR_S ? kr_atoms[lane] * y0 : 0.0);
+  C.atol = p.floor * nn;
+  int status = 2;
+  double y = y0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    bool ok = kr_wattempt<MIXED>(p, w, C, y0, attempt, y);
+    if (ok) {
+      const bool badv = lane < KR_N && !kr_finite(y);
+      const bool neg = lane < KR_S && y < -1e-10 * nn;
+      ok = !__any(badv || neg);
+    }
+    if (ok) {
+      w.y[lane] = y;
+      w.v[lane] = y0;
+      __syncthreads();
+      double e = 0.0;
+      if (lane == 0) e = kr_wresid0(w, nn);
+      e = kr_bcast(e, 0);
+      __syncthreads();
+      ok = e <= 1e-10;
+    }
+    if (ok) { status = attempt; break; }
+    if (p.mode == 1) break;
+  }
+  if (status == 2) { kr_wstats(p, C, 2); return; }
+  w.y[lane] = y;
+  w.v[lane] = y0;
+  __syncthreads();
+  if (lane == 0) kr_wpost0(w);
+  __syncthreads();
+  y = w.y[lane];
+  __syncthreads();
+  if (lane < KR_S) p.states[(long long)lane * p.ld + c] = y;
+  if (lane == KR_S) p.T[c] = y;
+  kr_wstats(p, C, status);
+}
+
+/* Claims cells one at a time for the wave; zeroes the Jacobian workspace
+ * once (entries no reaction touches stay zero). */
+template <bool MIXED>
+__device__ __forceinline__ void kr_wintegrate(const KrParams &p) {
+  __shared__ KrWave w;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < KR_N * KR_LDJ; i += 64) w.J[i] = 0.0;
+  __syncthreads();
+  for (;;) {
+    unsigned long long c0 = 0ull;
+    if (lane == 0) c0 = atomicAdd(p.counter, 1ull);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)c0);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(c0 >> 32));
+    const unsigned long long c = ((unsigned long long)hi << 32) | lo;
+    if (c >= (unsigned long long)p.n_cells) break;
+    kr_wcell<MIXED>(p, w, (long long)c);
+  }
+}
+
+/* Fastest self-coupling timescale 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V)
+ * of each cell's input state, capped at 1e7 s (workload set-up). */
+__device__ __forceinline__ void kr_wtimescale(const KrParams &p, double *out) {
+  __shared__ KrWave w;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < KR_N * KR_LDJ; i += 64) w.J[i] = 0.0;
+  __syncthreads();
+  for (long long c = blockIdx.x; c < p.n_cells; c += gridDim.x) {
+    double dt;
+    bool bad;
+    const double y = kr_wload(p, c, dt, bad);
+    kr_weval(w, y);
+    const double cv = kr_wheatcap(y);
+    double m = 0.0;
+    if (lane < KR_S) m = fabs(w.J[lane * KR_LDJ + lane]);
+    if (lane == KR_S && cv > 0.0) m = fabs(w.J[KR_S * KR_LDJ + KR_S]) / cv;
+    m = kr_wmax(m);
+    const double tau = (m > 0.0 && kr_finite(m)) ? 1.0 / m : 1e7;
+    if (lane == 0) out[c] = (kr_finite(tau) && tau < 1e7) ? tau : 1e7;
+    __syncthreads();
+  }
+}
+
+#ifndef KR_WAVES_PER_EU
+#define KR_WAVES_PER_EU 1
+#endif
+
+extern "C" __global__ void __launch_bounds__(64, 1) kr_timescale(KrParams p, double *out) {
+  kr_wtimescale(p, out);
+}
+
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp64(KrParams p) {
+  kr_wintegrate<false>(p);
+}
+
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp32lu(KrParams p) {
+  kr_wintegrate<true>(p);
+}
+
+extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = 0ull;
+}

@@ -81,7 +81,7 @@ def newton_counts(knet: Network, model: GuessModel | None, desc, n: int, salt: i
         h = torch.tensor(sy.log_uniform(n, *H_RANGE, 1, salt + 200), device=dev)
     status = torch.empty(n, dtype=torch.int32, device=dev)
     stats = torch.zeros((n, 4), dtype=torch.int32, device=dev)
-    counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    counters = torch.zeros(8, dtype=torch.int64, device=dev)
     if model is not None:
         guess = model.predict(states, T, dt=h, stream=stream)
         opts = guess_options(guess, counters, mode=KR_FIXED_STEP, n_fixed=1)

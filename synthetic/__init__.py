@@ -200,6 +200,27 @@ def _choose_reactions(rng, comp, cands, n_react, must_touch=None, tries=2000):
     raise RuntimeError("could not draw a spanning reaction set")
 
 
+def _choose_by_shape(rng, comp, cands, quotas, tries=2000):
+    """Like _choose_reactions, with a quota of reactions per side-size shape
+    (len(small side), len(large side)): e.g. {(2, 2): 120, (1, 2): 40}."""
+    by_shape: dict = {}
+    for c in cands:
+        by_shape.setdefault((len(c[0]), len(c[1])), []).append(c)
+    S = comp.shape[1]
+    for _ in range(tries):
+        picks = []
+        for shape, k in sorted(quotas.items()):
+            pool = by_shape[shape]
+            idx = rng.choice(len(pool), size=k, replace=False)
+            picks += [pool[i] for i in sorted(idx)]
+        used = set()
+        for a, b in picks:
+            used |= set(a) | set(b)
+        if used == set(range(S)) and _span_ok(comp, picks):
+            return picks
+    raise RuntimeError("could not draw a spanning reaction set")
+
+
 def _orient_and_draw(rng, picks, h_form, logA_of, b_rng, E_max, small_side_forward=True):
     """Arrhenius parameters for each picked reaction.
 
@@ -393,6 +414,83 @@ def cells_astro23(net: NetworkDesc, n_cells: int, seed_index: int = 2, salt: int
     return CellStates(n, T, _rho(net, n), None, 0.0)
 
 
+# (name, H, C, N, O, linear) of the 43 molecules of the large network
+_LARGE48_MOLECULES = [
+    ("H2", 2, 0, 0, 0, 1), ("C2", 0, 2, 0, 0, 1), ("N2", 0, 0, 2, 0, 1), ("O2", 0, 0, 0, 2, 1),
+    ("CH", 1, 1, 0, 0, 1), ("NH", 1, 0, 1, 0, 1), ("OH", 1, 0, 0, 1, 1), ("CN", 0, 1, 1, 0, 1),
+    ("CO", 0, 1, 0, 1, 1), ("NO", 0, 0, 1, 1, 1),
+    ("H2O", 2, 0, 0, 1, 0), ("CH2", 2, 1, 0, 0, 0), ("NH2", 2, 0, 1, 0, 0), ("HCN", 1, 1, 1, 0, 1),
+    ("HCO", 1, 1, 0, 1, 0), ("HNO", 1, 0, 1, 1, 0), ("CO2", 0, 1, 0, 2, 1), ("N2O", 0, 0, 2, 1, 1),
+    ("NO2", 0, 0, 1, 2, 0), ("O3", 0, 0, 0, 3, 0), ("C2H", 1, 2, 0, 0, 1), ("C3", 0, 3, 0, 0, 1),
+    ("HO2", 1, 0, 0, 2, 0), ("NCO", 0, 1, 1, 1, 1), ("C2O", 0, 2, 0, 1, 1), ("C2N", 0, 2, 1, 0, 1),
+    ("CH3", 3, 1, 0, 0, 0), ("NH3", 3, 0, 1, 0, 0), ("H2CO", 2, 1, 0, 1, 0), ("C2H2", 2, 2, 0, 0, 1),
+    ("HNCO", 1, 1, 1, 1, 0), ("H2O2", 2, 0, 0, 2, 0), ("N2H2", 2, 0, 2, 0, 0), ("HNO2", 1, 0, 1, 2, 0),
+    ("C3H", 1, 3, 0, 0, 1),
+    ("CH4", 4, 1, 0, 0, 0), ("HCOOH", 2, 1, 0, 2, 0), ("CH2CO", 2, 2, 0, 1, 0), ("NH2OH", 3, 0, 1, 1, 0),
+    ("HC3N", 1, 3, 1, 0, 1), ("CH3O", 3, 1, 0, 1, 0),
+    ("CH3OH", 4, 1, 0, 1, 0), ("C2H4", 4, 2, 0, 0, 0),
+]
+
+
+def network_large48(seed_index: int = 3) -> NetworkDesc:
+    """48 neutral species over rows H, He, C, N, O: the five atoms and 43
+    molecules of 2-6 atoms; 200 reversible reactions (120 two-to-two, 50
+    one-to-two, 30 two-to-three; at most one species on both sides, e.g. a
+    third body), spanning the null space of the composition (dimension 43)."""
+    rng = rng_for(seed_index, salt=1)
+    atoms_tab = [("H", 1, 0, 0, 0, 0), ("He", 0, 0, 0, 0, 0), ("C", 0, 1, 0, 0, 0),
+                 ("N", 0, 0, 1, 0, 0), ("O", 0, 0, 0, 1, 0)]
+    table = atoms_tab + _LARGE48_MOLECULES
+    species = [t[0] for t in table]
+    S = len(species)
+    comp = np.zeros((5, S), np.int32)
+    for j, t in enumerate(table):
+        comp[0, j], comp[2, j], comp[3, j], comp[4, j] = t[1], t[2], t[3], t[4]
+    comp[1, 1] = 1                                     # He
+    reservoir = np.array([0, 1, 2, 3, 4], np.int32)
+    atoms = comp.sum(axis=0)
+    cv = np.array([_heat_capacity(int(a), bool(t[5])) for a, t in zip(atoms, table)])
+    h_form, s_form = _thermo(rng, comp, 5)
+    cands = enumerate_reactions(comp, 2, 3, max_common=1)
+    # mostly bimolecular exchange, plus dissociation/association and
+    # third-body (3-species side) reactions
+    picks = _choose_by_shape(rng, comp, cands, {(2, 2): 120, (1, 2): 50, (2, 3): 30})
+
+    # slower than the combustion network (log10 A one to five decades lower,
+    # barriers up to 5e4 K) so that steps up to 1e-2 s at up to 5000 K stay
+    # within a few hundred substeps for most cells
+    def logA(order, g):
+        return {1: g.uniform(2.0, 8.0), 2: g.uniform(-13.0, -10.0)}.get(order, g.uniform(-35.0, -32.0))
+    reac, prod, arr = _orient_and_draw(rng, picks, h_form, logA, (-1.0, 1.0), 5e4)
+    return NetworkDesc("large_48sp", species, ["H", "He", "C", "N", "O"], 5, comp, reservoir, cv,
+                       h_form, s_form, reac, prod, arr, None, p_ref=ATM, T_min=10.0, T_max=1.0e5,
+                       meta={"config_index": 3})
+
+
+def cells_large48(net: NetworkDesc, n_cells: int, seed_index: int = 3, salt: int = 2) -> CellStates:
+    """T log-uniform [50, 5000] K; hydrogen nuclei log-uniform [1, 1e8]
+    cm^-3 split H : 2 H2 by Dirichlet(1,1); He = 0.1 n_H, C = 1e-4 n_H (as
+    CO), N = 5e-5 n_H (as N2), O = 3e-4 n_H (CO, the rest as H2O and O),
+    every other species 10^U[-12,-6] n_H; per-cell step log-uniform in
+    [1e-8, 1e-2] s."""
+    rng = rng_for(seed_index, salt=salt)
+    S = net.n_species
+    idx = {s: i for i, s in enumerate(net.species)}
+    T = 10.0 ** rng.uniform(np.log10(50.0), np.log10(5000.0), size=n_cells)
+    nH = 10.0 ** rng.uniform(0.0, 8.0, size=n_cells)
+    f = rng.dirichlet((1.0, 1.0), size=n_cells)
+    n = 10.0 ** rng.uniform(-12.0, -6.0, size=(S, n_cells)) * nH[None, :]
+    n[idx["H"]] = f[:, 0] * nH
+    n[idx["H2"]] = 0.5 * f[:, 1] * nH
+    n[idx["He"]] = 0.1 * nH
+    n[idx["CO"]] = 1e-4 * nH
+    n[idx["N2"]] = 2.5e-5 * nH
+    n[idx["H2O"]] = 1.5e-4 * nH
+    n[idx["O"]] = 0.5e-4 * nH
+    dt = 10.0 ** rng.uniform(-8.0, -2.0, size=n_cells)
+    return CellStates(n, T, _rho(net, n), dt, 0.0)
+
+
 def log_uniform(n: int, lo: float, hi: float, config_index: int, salt: int) -> np.ndarray:
     """n values log-uniform in [lo, hi] from the seeded stream (config, salt)."""
     rng = rng_for(config_index, salt=salt)
@@ -404,6 +502,10 @@ def network_for(config_index: int) -> NetworkDesc:
         return network_h_he(0)
     if config_index == 1:
         return network_h_o_n(1)
+    if config_index == 2:
+        return network_astro23(2)
+    if config_index == 3:
+        return network_large48(3)
     raise ValueError(f"no network for config {config_index}")
 
 
@@ -412,4 +514,8 @@ def cells_for(config_index: int, net: NetworkDesc, n_cells: int) -> CellStates:
         return cells_h_he(net, n_cells, 0)
     if config_index == 1:
         return cells_h_o_n(net, n_cells, 1)
+    if config_index == 2:
+        return cells_astro23(net, n_cells, 2)
+    if config_index == 3:
+        return cells_large48(net, n_cells, 3)
     raise ValueError(f"no cells for config {config_index}")

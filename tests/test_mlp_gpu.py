@@ -137,7 +137,7 @@ def test_guess_keeps_the_plain_result(setup, oracle_lib):
     T = torch.tensor(cs.T, device="cuda")
     dt = torch.full((300,), 3e-7, dtype=torch.float64, device="cuda")
     guess = model.predict(n, T, dt=dt)
-    counters = torch.zeros(4, dtype=torch.int64, device="cuda")
+    counters = torch.zeros(8, dtype=torch.int64, device="cuda")
     status = torch.empty(300, dtype=torch.int32, device="cuda")
     kr.chem_integrate(knet, n, T, dt=dt, rtol=1e-6, opts=kr.guess_options(guess, counters),
                       status=status)

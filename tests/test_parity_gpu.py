@@ -27,9 +27,9 @@ def _dev(a, dtype=None):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
 
 
-def run_gpu(desc, cs, dt=None, dt_scalar=0.0, rtol=1e-6, **opt):
+def run_gpu(desc, cs, dt=None, dt_scalar=0.0, rtol=1e-6, build=None, **opt):
     kr = _kr()
-    net = kr.Network(desc)
+    net = kr.Network(desc, build)
     n = _dev(cs.n, torch.float64)
     T = _dev(cs.T, torch.float64)
     rho = _dev(cs.rho, torch.float64)

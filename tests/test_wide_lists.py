@@ -1,0 +1,109 @@
+"""Host-side checks of the wavefront layout's generated tables (no GPU):
+the per-lane contribution lists rebuild exactly the rate-Jacobian terms the
+network implies, every destination entry is owned by one lane and closed by
+a flush mark, and the direction tables hold the derived Arrhenius
+parameters of every reaction direction."""
+import re
+from collections import defaultdict
+
+import numpy as np
+import pytest
+
+import synthetic as sy
+
+
+def _kr():
+    import paper_2504_04941_amd as kr
+    kr.lib()
+    return kr
+
+
+def _tables(src):
+    def arr(name, conv):
+        m = re.search(r"kr_%s\[(\d+)\] = \{([^}]*)\}" % name, src)
+        return [conv(x) for x in m.group(2).split(",")]
+    defs = {k: int(v) for k, v in re.findall(r"#define KR_(S|LDJ|NDR|NC|NF) (\d+)", src)}
+    u = lambda x: int(x.rstrip("u"))
+    return defs, {n: arr(n, u) for n in ("dr", "wc", "wf")}, {n: arr(n, float.fromhex) for n in ("dA", "db", "dE")}
+
+
+def _expected(desc, par, S, LDJ):
+    """(destination -> sorted list of (source, nu)) from the network."""
+    full, fonly = defaultdict(list), defaultdict(list)
+    dirs = []
+    for r in range(desc.n_reactions):
+        for d, (re_, pr_) in enumerate(((desc.reac[r], desc.prod[r]), (desc.prod[r], desc.reac[r]))):
+            if par[r, d, 0] == 0.0:
+                continue
+            dirs.append((r, d, [int(x) for x in re_], [int(x) for x in pr_]))
+    for i, (r, d, re_, pr_) in enumerate(dirs):
+        nu = np.zeros(S, int)
+        for s in re_:
+            if s >= 0:
+                nu[s] -= 1
+        for s in pr_:
+            if s >= 0:
+                nu[s] += 1
+        for s in np.nonzero(nu)[0]:
+            full[s * LDJ + S + 1].append((5 * i, int(nu[s])))
+            fonly[s * LDJ + S + 1].append((5 * i, int(nu[s])))
+            full[s * LDJ + S].append((5 * i + 1, int(nu[s])))
+            for k, m in enumerate(re_):
+                if m >= 0:
+                    full[s * LDJ + m].append((5 * i + 2 + k, int(nu[s])))
+    return dirs, full, fonly
+
+
+def _decode(tab, length):
+    got, owner = defaultdict(list), {}
+    for lane in range(64):
+        open_dst = None
+        for i in range(length):
+            e = tab[i * 64 + lane]
+            src, dst, nu, fl = e & 4095, (e >> 12) & 8191, ((e >> 25) & 7) - 4, e >> 28
+            if nu == 0 and not fl:
+                continue                       # padding
+            assert owner.setdefault(dst, lane) == lane, "destination split over lanes"
+            assert open_dst in (None, dst)
+            got[dst].append((src, nu))
+            open_dst = None if fl else dst
+        assert open_dst is None, "list ends without a flush"
+    return got
+
+
+@pytest.mark.parametrize("make", [lambda: sy.network_h_o_n(1), lambda: sy.network_astro23(2),
+                                  lambda: sy.network_large48(3)])
+def test_contribution_lists_rebuild_the_jacobian_terms(oracle_lib, make):
+    kr = _kr()
+    desc = make()
+    src = kr.network_check(desc, build=kr.build_options(layout=kr.KR_LAYOUT_WAVE))
+    defs, ut, dt = _tables(src)
+    S, LDJ = defs["S"], defs["LDJ"]
+    assert LDJ % 2 == 1 and LDJ >= S + 2
+    par = oracle_lib.OracleNet(desc).arrhenius()
+    dirs, full, fonly = _expected(desc, par, S, LDJ)
+    assert defs["NDR"] == (len(dirs) + 63) // 64
+    got = _decode(ut["wc"], defs["NC"])
+    assert {k: sorted(v) for k, v in got.items()} == {k: sorted(v) for k, v in full.items()}
+    gotf = _decode(ut["wf"], defs["NF"])
+    assert {k: sorted(v) for k, v in gotf.items()} == {k: sorted(v) for k, v in fonly.items()}
+    # lists are balanced: no lane longer than the largest entry or the mean
+    terms = sum(len(v) for v in full.values())
+    assert defs["NC"] <= max(max(len(v) for v in full.values()), -(-terms // 64) + 8)
+    # direction tables: derived (A, b, E) and reactant slots, padding inert
+    for i, (r, d, re_, _) in enumerate(dirs):
+        np.testing.assert_allclose([dt["dA"][i], dt["db"][i], dt["dE"][i]], par[r, d], rtol=1e-15)
+        slots = [(ut["dr"][i] >> (8 * k)) & 255 for k in range(3)]
+        assert slots == [m if m >= 0 else 255 for m in re_]
+    assert all(a == 0.0 for a in dt["dA"][len(dirs):])
+
+
+def test_wave_layout_compiles_for_gfx950():
+    kr = _kr()
+    kr.network_check(sy.network_h_o_n(1), compile=True, build=kr.build_options(layout=kr.KR_LAYOUT_WAVE))
+
+
+def test_wave_layout_limits():
+    kr = _kr()
+    with pytest.raises(kr.KrError):
+        kr.network_check(sy.network_h_o_n(1), build=kr.build_options(layout=7))
