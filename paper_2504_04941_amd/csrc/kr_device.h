@@ -730,30 +730,42 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         for (int i = 0; i < KR_N; ++i) r[i] = b[i];
         bool conv = false;
         int sweeps = 0;
+        /* the sweep loop's trip count is wave-uniform (it runs while any
+         * lane still refines); each lane's sweep is predicated */
+        bool live = ok32;
 #pragma unroll 1
-        for (int sweep = 0; sweep < 4 && ok32; ++sweep) {
-          sweeps = sweep + 1;
-          float c32[KR_N];
+        for (int sweep = 0; sweep < 4; ++sweep) {
+          if (!__any(live)) break;
+          if (live) {
+            sweeps = sweep + 1;
+            float c32[KR_N];
 #pragma unroll
-          for (int i = 0; i < KR_N; ++i) c32[i] = (float)(r[i] * rs[i]);
-          kr_lu_apply32(a32, dinv, perm, c32);
-          double cn = 0.0;
+            for (int i = 0; i < KR_N; ++i) c32[i] = (float)(r[i] * rs[i]);
+            kr_lu_apply32(a32, dinv, perm, c32);
+            double cn = 0.0;
 #pragma unroll
-          for (int i = 0; i < KR_N; ++i) {
-            const double c = (double)c32[i];
-            d[i] += c;
-            const double e = fabs(c) * kr_rcp(kr_weight(p, L, i, L.y[i]));
-            cn = e > cn ? e : cn;
-          }
-          if (!kr_finite(cn)) { ok32 = false; break; }
-          if (sweep > 0 && cn <= 1e-6) { conv = true; break; }
-          /* r = b - M d in FP64 */
+            for (int i = 0; i < KR_N; ++i) {
+              const double c = (double)c32[i];
+              d[i] += c;
+              const double e = fabs(c) * kr_rcp(kr_weight(p, L, i, L.y[i]));
+              cn = e > cn ? e : cn;
+            }
+            if (!kr_finite(cn)) {
+              ok32 = false;
+              live = false;
+            } else if (sweep > 0 && cn <= 1e-6) {
+              conv = true;
+              live = false;
+            } else {
+              /* r = b - M d in FP64 */
 #pragma unroll
-          for (int i = 0; i < KR_N; ++i) {
-            double t = b[i];
+              for (int i = 0; i < KR_N; ++i) {
+                double t = b[i];
 #pragma unroll
-            for (int k = 0; k < KR_N; ++k) t = fma(-J[i][k], d[k], t);
-            r[i] = t;
+                for (int k = 0; k < KR_N; ++k) t = fma(-J[i][k], d[k], t);
+                r[i] = t;
+              }
+            }
           }
         }
         if (p.counters) atomicAdd(&p.counters[3], (unsigned long long)sweeps);

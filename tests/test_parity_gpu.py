@@ -241,3 +241,17 @@ def test_element_residual_matches_oracle(oracle_lib):
     np.testing.assert_allclose(resid.cpu().numpy(), ref, rtol=1e-12, atol=1e-30)
     assert mx == pytest.approx(ref.max(), rel=1e-12)
     knet.close()
+
+
+def test_fp32lu_astro23_batch(oracle_lib):
+    """Form (1) on the 23-species network in full waves: every cell's result
+    (and status) matches the oracle when 64 lanes with different refinement
+    sweep counts run together (a per-lane loop exit in this spilled kernel
+    once reverted ~10% of such cells while single cells were correct)."""
+    desc = sy.network_astro23(2)
+    cs = sy.cells_astro23(desc, 256, 2)
+    on = oracle_lib.OracleNet(desc)
+    dt = np.array([1e-2 * on.fastest_timescale(np.r_[cs.n[:, c], cs.T[c]]) for c in range(256)])
+    gpu = run_gpu(desc, cs, dt=dt, precision=1)
+    orc = run_oracle(oracle_lib, desc, cs, dt=dt)
+    assert_parity(gpu, orc, cs, 1e-6, "astro23 fp32lu batch", desc=desc)
