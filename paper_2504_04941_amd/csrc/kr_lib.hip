@@ -538,15 +538,6 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
   n->build = bo;
   n->wide = use_wide(n, bo);
   if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
-  if (n->wide) {
-    /* The wavefront layout generates and compiles (kr_network_check_ex),
-     * but its kernels did not return on gfx950 for a one-cell batch whose
-     * CPU execution takes one substep; until the cause is known, networks
-     * are not created with it. */
-    delete n;
-    return fail(KR_EINVAL, "the wavefront-per-cell layout is disabled on devices (n_species %d >= %d or "
-                "layout forced); see the design notes", desc->n_species, KR_WIDE_MIN_SPECIES);
-  }
   n->source = full_source(n, bo);
   std::vector<char> code;
   std::string log;

@@ -22,10 +22,16 @@
  *    (heat release q_r = -sum_s nu_rs h_s), as one column sum per lane;
  *  - LU: lane i holds row i of the Newton matrix in registers; column j is
  *    eliminated by a wave-wide arg-max over the remaining rows (implicit row
- *    scaling as in the paper's Algorithm 1), a broadcast of the pivot row and
- *    one FMA per remaining entry.  Rows are never moved: each lane records
- *    the column at which its row became pivot row, and the triangular
- *    solves walk the pivot order (found by a ballot per column).
+ *    scaling as in the paper's Algorithm 1), a broadcast of the pivot row
+ *    through LDS and one FMA per remaining entry.  Rows are never moved:
+ *    each lane records the column at which its row became pivot row, and the
+ *    triangular solves walk the pivot order (found by a ballot per column).
+ *
+ * Control flow is wave-uniform by construction, and visibly so to the
+ * compiler: every value a branch or loop depends on is moved to a scalar
+ * register (read from one lane, or a ballot), and no loop has per-lane
+ * exits.  Per-lane loop exits are lowered to exec-mask loops, which in
+ * kernels this large (register spills) have mis-executed on gfx950.
  *
  * Generated section (network compiler) defines:
  *   KR_S, KR_NROWS, KR_NELEM, KR_LDJ (LDS row stride of the Jacobian),
@@ -61,6 +67,11 @@ __device__ __forceinline__ double kr_bcast(double v, int src) {
 __device__ __forceinline__ float kr_bcastf(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
+
+/* lane 0's value as a scalar (for values every lane holds alike) */
+__device__ __forceinline__ double kr_u(double v) { return kr_bcast(v, 0); }
+__device__ __forceinline__ int kr_ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ bool kr_uany(bool b) { return __ballot(b) != 0ull; }
 
 __device__ __forceinline__ double kr_wsum(double v) {
 #pragma unroll
@@ -202,11 +213,11 @@ __device__ __forceinline__ double kr_wrate(const KrWave &w, double cv) {
  * the reciprocal pivot.  Returns false (wave-uniform) for a singular or
  * non-finite matrix. */
 template <typename F>
-__device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
+__device__ __forceinline__ bool kr_wlu(KrWave &w, F (&a)[KR_N], int &pc, F &dinv) {
   const int lane = threadIdx.x;
   F mx = F(0);
 #pragma unroll
-  for (int k = 0; k < KR_N; ++k) mx = a[k] < F(0) ? (-a[k] > mx ? -a[k] : mx) : (a[k] > mx ? a[k] : mx);
+  for (int k = 0; k < KR_N; ++k) mx = fmax(mx, fabs(a[k]));
   const F sc = lane < KR_N && mx > F(0) ? F(1) / mx : F(0);
   pc = lane < KR_N ? KR_NOTPIV : -1;
   dinv = F(0);
@@ -216,23 +227,28 @@ __device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
     const bool cand = pc == KR_NOTPIV;
     const F aj = a[j];
     unsigned best;
-    const int p = kr_wargmax((float)((aj < F(0) ? -aj : aj) * sc), cand, best);
+    /* fabs: a -0 candidate would carry the sign bit into the key */
+    const int p = kr_wargmax(fabsf((float)(fabs((double)aj) * (double)sc)), cand, best);
     ok = ok && (best >> 6) != 0u;
     F piv;
     if constexpr (sizeof(F) == 8) piv = kr_bcast(aj, p);
     else piv = kr_bcastf(aj, p);
     ok = ok && piv != F(0) && kr_finite((double)piv);
     const F inv = F(1) / piv;
+    if (j + 1 < KR_N) {
+      /* the pivot row's remaining entries, broadcast through LDS */
+      if (lane == p) {
+#pragma unroll
+        for (int k = j + 1; k < KR_N; ++k) w.v[k] = (double)a[k];
+      }
+      __syncthreads();
+    }
     if (lane == p) { pc = j; dinv = inv; }
     const F l = pc == KR_NOTPIV ? aj * inv : F(0);
     if (pc == KR_NOTPIV) a[j] = l;
 #pragma unroll
-    for (int k = j + 1; k < KR_N; ++k) {
-      F u;
-      if constexpr (sizeof(F) == 8) u = kr_bcast(a[k], p);
-      else u = kr_bcastf(a[k], p);
-      a[k] = fma(-l, u, a[k]);
-    }
+    for (int k = j + 1; k < KR_N; ++k) a[k] = fma(-l, (F)w.v[k], a[k]);
+    __syncthreads();
   }
   return ok;
 }
@@ -281,33 +297,22 @@ __device__ __forceinline__ double kr_wweight(const KrWCell &C, double yn, double
 }
 
 /* Weighted element projection of a Newton update (FP32 form): d_S <- d_S -
- * W N^T (N W N^T)^-1 N d_S with W = diag(max(|y_s|, atol)); the Gram system
- * is formed and solved redundantly in every lane from LDS copies. */
-__device__ __forceinline__ double kr_wproject(KrWave &w, double yl, double atol, double d) {
+ * W N^T (N W N^T)^-1 N d_S with W = diag(max(|y_s|, atol)).  The row sums are
+ * wave reductions; the small Gram system is solved alike in every lane. */
+__device__ __forceinline__ double kr_wproject(double yl, double atol, double d) {
   if (KR_NROWS == 0) return d;
   constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
   const int lane = threadIdx.x;
   const double W = lane < KR_S ? fmax(fabs(yl), atol) : 0.0;
-  w.v[lane] = d;
-  w.y[lane] = W;
-  __syncthreads();
   double G[V][V], r[V];
 #pragma unroll
   for (int a = 0; a < V; ++a) {
-    r[a] = 0.0;
+    const double na = lane < KR_S ? (double)kr_comp[a][lane] : 0.0;
+    r[a] = kr_u(kr_wsum(na * d));
 #pragma unroll
-    for (int b = 0; b <= a; ++b) G[a][b] = 0.0;
-  }
-#pragma unroll
-  for (int s = 0; s < KR_S; ++s) {
-    const double ds = w.v[s], Ws = w.y[s];
-#pragma unroll
-    for (int a = 0; a < V; ++a) {
-      if (kr_comp[a][s] == 0) continue;
-      r[a] = fma((double)kr_comp[a][s], ds, r[a]);
-#pragma unroll
-      for (int b = 0; b <= a; ++b)
-        if (kr_comp[b][s] != 0) G[a][b] = fma((double)(kr_comp[a][s] * kr_comp[b][s]), Ws, G[a][b]);
+    for (int b = 0; b <= a; ++b) {
+      const double nb = lane < KR_S ? (double)kr_comp[b][lane] : 0.0;
+      G[a][b] = kr_u(kr_wsum(na * nb * W));
     }
   }
 #pragma unroll
@@ -336,11 +341,8 @@ __device__ __forceinline__ double kr_wproject(KrWave &w, double yl, double atol,
     r[a] = t / G[a][a];
   }
   double t = 0.0;
-  if (lane < KR_S) {
 #pragma unroll
-    for (int a = 0; a < V; ++a) t = fma((double)kr_comp[a][lane], r[a], t);
-  }
-  __syncthreads();
+  for (int a = 0; a < V; ++a) t = fma(lane < KR_S ? (double)kr_comp[a][lane] : 0.0, r[a], t);
   return d - W * t;
 }
 
@@ -354,9 +356,10 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
   y = yn;
   double prev = __builtin_inf();
   int grow = 0;
-  for (int it = 0; it < p.max_newton; ++it) {
+  const int max_newton = kr_ui(p.max_newton);
+  for (int it = 0; it < max_newton; ++it) {
     kr_weval(w, y);
-    const double cv = kr_wheatcap(y);
+    const double cv = kr_u(kr_wheatcap(y));
     const double T = kr_bcast(y, KR_S);
     /* residual (negated) and Newton matrix row of this lane */
     double b = 0.0;
@@ -381,7 +384,7 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
     if (!MIXED) {
       int pc;
       double dinv;
-      ok = kr_wlu(a, pc, dinv);
+      ok = kr_wlu(w, a, pc, dinv);
       if (ok) d = kr_wsolve(a, pc, dinv, b);
     } else {
       /* FP32 LU of the row-equilibrated matrix; FP64 residual and iterative
@@ -396,15 +399,16 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
       for (int k = 0; k < KR_N; ++k) a32[k] = (float)(a[k] * rs);
       int pc;
       float dinv;
-      bool ok32 = kr_wlu(a32, pc, dinv);
+      bool ok32 = kr_wlu(w, a32, pc, dinv);
       double r = b;
       bool conv = false;
       int sweeps = 0;
-      for (int sweep = 0; sweep < 4 && ok32; ++sweep) {
+      for (int sweep = 0; sweep < 4; ++sweep) {
+        if (!ok32) break;
         sweeps = sweep + 1;
         const double c = (double)kr_wsolve(a32, pc, dinv, (float)(r * rs));
         d += c;
-        const double cn = kr_wmax(lane < KR_N ? fabs(c) / kr_wweight(C, yn, y) : 0.0);
+        const double cn = kr_u(kr_wmax(lane < KR_N ? fabs(c) / kr_wweight(C, yn, y) : 0.0));
         if (!kr_finite(cn)) { ok32 = false; break; }
         if (sweep > 0 && cn <= 1e-6) { conv = true; break; }
         /* r = b - M d in FP64 */
@@ -416,23 +420,23 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
         r = t;
         __syncthreads();
       }
-      if (p.counters && lane == 0) atomicAdd(&p.counters[3], (unsigned long long)sweeps);
+      if (p.counters) atomicAdd(&p.counters[3], lane == 0 ? (unsigned long long)sweeps : 0ull);
       ok = true;
       if (!ok32 || !conv) {
-        if (p.counters && lane == 0) atomicAdd(&p.counters[4], 1ull);
+        if (p.counters) atomicAdd(&p.counters[4], lane == 0 ? 1ull : 0ull);
         int pc64;
         double dinv64;
-        ok = kr_wlu(a, pc64, dinv64);
+        ok = kr_wlu(w, a, pc64, dinv64);
         d = ok ? kr_wsolve(a, pc64, dinv64, b) : 0.0;
       }
-      if (ok) d = kr_wproject(w, y, C.atol, d);
+      if (ok) d = kr_wproject(y, C.atol, d);
     }
     if (!ok) return false;
     const double yi = y + d;
     y = lane < KR_N ? yi : 0.0;
     const bool bad = lane < KR_N && (!kr_finite(d) || !kr_finite(yi));
-    if (__any(bad) || !(kr_bcast(y, KR_S) > 0.0)) return false;
-    const double norm = kr_wmax(lane < KR_N ? fabs(d) / kr_wweight(C, yn, y) : 0.0);
+    if (kr_uany(bad) || !(kr_bcast(y, KR_S) > 0.0)) return false;
+    const double norm = kr_u(kr_wmax(lane < KR_N ? fabs(d) / kr_wweight(C, yn, y) : 0.0));
     if (norm <= p.newton_tol) return true;
     if (norm > prev) {
       if (++grow >= 2) return false;
@@ -445,23 +449,25 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
 }
 
 /* One attempt over [0, dt] from y0 (lane-distributed).  Adaptive: error
- * estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i; accepted when
- * err <= 1, then h *= min(growth, max(0.2, safety / sqrt(max(err, 1e-10))));
- * rejected: h *= max(0.2, safety / sqrt(err)); Newton failure: h /= 4.  The
- * last substep lands on dt.  Fails when h < 1e-12 dt or after max_substeps
- * substep attempts.  On success y holds the end point. */
+ * estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i (a running
+ * maximum that skips 0/0); accepted when err <= 1, then h *= min(growth,
+ * max(0.2, safety / sqrt(max(err, 1e-10)))); rejected: h *= max(0.2, safety /
+ * sqrt(err)); Newton failure: h /= 4.  The last substep lands on dt.  Fails
+ * when h < 1e-12 dt or after max_substeps substep attempts.  On success y
+ * holds the end point. */
 template <bool MIXED>
 __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCell &C, double y0,
                                             int attempt, double &y) {
   const int lane = threadIdx.x;
   double yn = y0;
-  C.eps_n = kr_bcast(y0, KR_S) * kr_wheatcap(y0);
-  if (p.mode == 1) {
-    const double h = C.dt / (double)p.n_fixed;
-    for (int k = 0; k < p.n_fixed; ++k) {
+  C.eps_n = kr_bcast(y0, KR_S) * kr_u(kr_wheatcap(y0));
+  if (kr_ui(p.mode) == 1) {
+    const int nf = kr_ui(p.n_fixed);
+    const double h = C.dt / (double)nf;
+    for (int k = 0; k < nf; ++k) {
       if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) { C.nfail++; return false; }
       yn = y;
-      C.eps_n = kr_bcast(yn, KR_S) * kr_wheatcap(yn);
+      C.eps_n = kr_bcast(yn, KR_S) * kr_u(kr_wheatcap(yn));
       C.acc++;
     }
     y = yn;
@@ -470,34 +476,31 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
   const double h0 = attempt == 0 ? C.dt : C.dt / 100.0;
   const double safety = attempt == 0 ? 0.9 : 0.5;
   const double growth = attempt == 0 ? 5.0 : 2.0;
+  const int max_substeps = kr_ui(p.max_substeps);
   kr_wrhs(w, yn);
-  double gn = kr_wrate(w, kr_wheatcap(yn));
+  double gn = kr_wrate(w, kr_u(kr_wheatcap(yn)));
   double t = 0.0, h = h0;
-  int attempts = 0;
-  for (;;) {
-    if (attempts >= p.max_substeps) return false;
+  bool done = false;
+  for (int attempts = 0; attempts < max_substeps; ++attempts) {
     bool fin = false;
     if (h >= C.dt - t) { h = C.dt - t; fin = true; }
-    else if (h < 1e-12 * C.dt) return false;
-    attempts++;
+    else if (h < 1e-12 * C.dt) break;
     if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) {
       C.nfail++;
       h *= 0.25;
       continue;
     }
     kr_wrhs(w, y);
-    const double cv = kr_wheatcap(y);
+    const double cv = kr_u(kr_wheatcap(y));
     const double g = kr_wrate(w, cv);
-    /* max over the unknowns, ignoring 0/0 (zero weight and change), as a
-     * NaN-skipping running maximum does */
-    const double err = kr_wmax(lane < KR_N ? fabs(0.5 * h * (g - gn)) / kr_wweight(C, yn, y) : 0.0);
+    const double err = kr_u(kr_wmax(lane < KR_N ? fabs(0.5 * h * (g - gn)) / kr_wweight(C, yn, y) : 0.0));
     if (!kr_finite(err)) { C.rej++; h *= 0.2; continue; }
     if (err <= 1.0) {
       yn = y;
       gn = g;
       C.eps_n = kr_bcast(y, KR_S) * cv;
       C.acc++;
-      if (fin) break;
+      if (fin) { done = true; break; }
       t += h;
       h *= fmin(growth, fmax(0.2, safety / sqrt(fmax(err, 1e-10))));
     } else {
@@ -506,85 +509,113 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
     }
   }
   y = yn;
-  return true;
+  return done;
 }
 
 /* ------------------------------------------------------------------------ */
 /* one cell: pre-processing, attempts, checks, post-processing               */
 /* ------------------------------------------------------------------------ */
 
-/* Lane 0, sequential over the LDS copies y (result) and y0 (input, in v):
- * element residual max_row |sum_s N_s (y - y0)_s| / D_row (elements: D =
- * sum |N_s| y0_s; charge-like rows: the nuclei density). */
-__device__ __forceinline__ double kr_wresid0(const KrWave &w, double nn) {
+/* sum over the lane-distributed species of comp[v][s] * x_s */
+__device__ __forceinline__ double kr_wrow(int v, double x) {
+  const int lane = threadIdx.x;
+  return kr_u(kr_wsum(lane < KR_S ? (double)kr_comp[v][lane] * x : 0.0));
+}
+
+/* Element residual max_row |sum_s N_s (y - y0)_s| / D_row (elements: D =
+ * sum |N_s| y0_s; charge-like rows: the nuclei density nn); NaN propagates. */
+__device__ __forceinline__ double kr_wresid(double y, double y0, double nn) {
+  const int lane = threadIdx.x;
   double worst = 0.0;
+#pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) {
-    double diff = 0.0, D = 0.0;
-    for (int s = 0; s < KR_S; ++s) {
-      const int a = kr_comp[v][s];
-      if (a == 0) continue;
-      diff += a * (w.y[s] - w.v[s]);
-      D += (a > 0 ? a : -a) * w.v[s];
-    }
-    if (v >= KR_NELEM) D = nn;
+    const double a = lane < KR_S ? (double)kr_comp[v][lane] : 0.0;
+    const double diff = kr_u(kr_wsum(a * (y - y0)));
+    const double D = v >= KR_NELEM ? nn : kr_u(kr_wsum(fabs(a) * y0));
     const double e = fabs(diff) / fmax(D, 1e-300);
     if (!(e <= worst)) worst = e;
   }
   return worst;
 }
 
-/* Lane 0: the three post-processing stages of Sec. 2.2.3 on w.y, with the
- * initial row totals from w.v. */
-__device__ __forceinline__ void kr_wpost0(KrWave &w) {
+/* Lane with the largest value among candidates (lowest lane on ties), or -1. */
+__device__ __forceinline__ int kr_wargmaxd(double v, bool cand) {
+  const int lane = threadIdx.x;
+  double bv = cand ? v : -1.0;
+  int bl = cand ? lane : 64;
+#pragma unroll
+  for (int o = 32; o; o >>= 1) {
+    const double ov = __shfl_xor(bv, o);
+    const int ol = __shfl_xor(bl, o);
+    if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; }
+  }
+  bl = kr_ui(bl);
+  return bl < 64 ? bl : -1;
+}
+
+/* The three post-processing stages of Sec. 2.2.3 on the lane-distributed
+ * end point y, with the initial row totals from y0. */
+__device__ __forceinline__ double kr_wpost(double y, double y0) {
+  const int lane = threadIdx.x;
   double E0[KR_NROWS > 0 ? KR_NROWS : 1];
+#pragma unroll
+  for (int v = 0; v < KR_NROWS; ++v) E0[v] = kr_wrow(v, y0);
+  if (lane < KR_S && y < 0.0) y = 0.0;
+#pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) {
-    double t = 0.0;
-    for (int s = 0; s < KR_S; ++s) t += kr_comp[v][s] * w.v[s];
-    E0[v] = t;
-  }
-  for (int s = 0; s < KR_S; ++s)
-    if (w.y[s] < 0.0) w.y[s] = 0.0;
-  for (int v = 0; v < KR_NROWS; ++v) {
-    double E = 0.0;
-    for (int s = 0; s < KR_S; ++s) E += kr_comp[v][s] * w.y[s];
+    const double E = kr_wrow(v, y);
     const int rs = kr_res[v];
-    w.y[rs] += (E0[v] - E) / kr_comp[v][rs];
+    if (lane == rs) y += (E0[v] - E) / kr_comp[v][rs];
   }
+#pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) {
     const int rs = kr_res[v];
     const int sign_r = kr_comp[v][rs] > 0 ? 1 : -1;
-    unsigned long long used = 0ull;
-    while (w.y[rs] < 0.0) {
-      int best = -1;
-      for (int s = 0; s < KR_S; ++s) {
-        if (s == rs || ((used >> s) & 1ull)) continue;
-        const int a = kr_comp[v][s];
-        if (a == 0 || (a > 0 ? 1 : -1) != sign_r) continue;
-        if (w.y[s] <= 0.0) continue;
-        if (best < 0 || w.y[s] > w.y[best]) best = s;
-      }
+    const int a = lane < KR_S ? kr_comp[v][lane] : 0;
+    bool used = false;
+    for (int it = 0; it < KR_S; ++it) {
+      const double yr = kr_bcast(y, rs);
+      if (!(yr < 0.0)) break;
+      const bool cand = lane < KR_S && lane != rs && !used && a != 0 && (a > 0 ? 1 : -1) == sign_r && y > 0.0;
+      const int best = kr_wargmaxd(y, cand);
       if (best < 0) break;
-      used |= 1ull << best;
-      const double need = -w.y[rs] * kr_comp[v][rs] / kr_comp[v][best];
-      const double x = need < w.y[best] ? need : w.y[best];
-      w.y[best] -= x;
+      if (lane == best) used = true;
+      const double yb = kr_bcast(y, best);
+      const double need = -yr * kr_comp[v][rs] / kr_comp[v][best];
+      const double x = need < yb ? need : yb;
+      if (lane == best) y -= x;
+#pragma unroll
       for (int u = 0; u < KR_NROWS; ++u) {
-        const int a = kr_comp[u][best];
-        if (a) w.y[kr_res[u]] += x * a / kr_comp[u][kr_res[u]];
+        const int au = kr_comp[u][best];
+        if (au != 0 && lane == kr_res[u]) y += x * au / kr_comp[u][kr_res[u]];
       }
-      if (x == need) w.y[rs] = 0.0;
+      if (x == need && lane == rs) y = 0.0;
     }
+  }
+  return y;
+}
+
+/* Status and statistics of the cell.  Every lane stores the same (uniform)
+ * values: no branch on the lane index, which the optimiser would otherwise
+ * thread into the loop exits and so turn the uniform loops divergent. */
+__device__ __forceinline__ void kr_wstats(const KrParams &p, const KrWCell &C, int code) {
+  if (p.status) p.status[C.c] = code;
+  if (p.cell_stats) {
+    int *st = p.cell_stats + 4 * C.c;
+    st[0] = C.acc; st[1] = C.iters; st[2] = C.rej; st[3] = C.nfail;
   }
 }
 
-__device__ __forceinline__ void kr_wstats(const KrParams &p, const KrWCell &C, int code) {
-  if (threadIdx.x == 0) {
-    if (p.status) p.status[C.c] = code;
-    if (p.cell_stats) {
-      int *st = p.cell_stats + 4 * C.c;
-      st[0] = C.acc; st[1] = C.iters; st[2] = C.rej; st[3] = C.nfail;
-    }
-  }
+/* Stores the lane-distributed point: lane s < S its abundance, lanes from S
+ * on store T (the same value each), without a branch on the lane index. */
+__device__ __forceinline__ void kr_wstore(const KrParams &p, long long c, double y) {
+  const int lane = threadIdx.x;
+  const double T = kr_bcast(y, KR_S);
+  const double last = kr_bcast(y, KR_S - 1);
+  const int s = lane < KR_S ? lane : KR_S - 1;
+  const double v = lane < KR_S ? y : last;
+  p.states[(long long)s * p.ld + c] = v;
+  p.T[c] = T;
 }
 
 /* Pre-processing (Sec. 2.2.2) of the lane's input entry; bad = non-finite. */
@@ -597,11 +628,11 @@ __device__ __forceinline__ double kr_wload(const KrParams &p, long long c, doubl
     bad = !kr_finite(v);
     x = v > 0.0 ? v : 0.0;
   }
-  const double T = p.T[c];
-  dt = p.dt ? p.dt[c] : p.dt_scalar;
+  const double T = kr_u(p.T[c]);
+  dt = kr_u(p.dt ? p.dt[c] : p.dt_scalar);
   bad = bad || !kr_finite(T) || !kr_finite(dt) || !(dt >= 0.0);
   if (p.rho_floor > 0.0 && p.rho) {
-    const double rho = p.rho[c];
+    const double rho = kr_u(p.rho[c]);
     if (rho > 0.0 && rho < p.rho_floor) x *= p.rho_floor / rho;
   }
   if (lane == KR_S) x = fmin(fmax(T, kr_T_min), kr_T_max);
@@ -618,16 +649,16 @@ __device__ __forceinline__ void kr_wcell(const KrParams &p, KrWave &w, long long
   double dt;
   bool bad;
   const double y0 = kr_wload(p, c, dt, bad);
-  if (__any(bad)) { kr_wstats(p, C, 2); return; }
+  if (kr_uany(bad)) { kr_wstats(p, C, 2); return; }
   if (dt == 0.0) {
-    if (lane < KR_S) p.states[(long long)lane * p.ld + c] = y0;
-    if (lane == KR_S) p.T[c] = y0;
+    kr_wstore(p, c, y0);
     kr_wstats(p, C, 0);
     return;
   }
   C.dt = dt;
-  const double nn = kr_wsum(lane < KR_S ? kr_atoms[lane] * y0 : 0.0);
+  const double nn = kr_u(kr_wsum(lane < KR_S ? kr_atoms[lane] * y0 : 0.0));
   C.atol = p.floor * nn;
+  const int mode = kr_ui(p.mode);
   int status = 2;
   double y = y0;
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -635,31 +666,14 @@ __device__ __forceinline__ void kr_wcell(const KrParams &p, KrWave &w, long long
     if (ok) {
       const bool badv = lane < KR_N && !kr_finite(y);
       const bool neg = lane < KR_S && y < -1e-10 * nn;
-      ok = !__any(badv || neg);
-    }
-    if (ok) {
-      w.y[lane] = y;
-      w.v[lane] = y0;
-      __syncthreads();
-      double e = 0.0;
-      if (lane == 0) e = kr_wresid0(w, nn);
-      e = kr_bcast(e, 0);
-      __syncthreads();
-      ok = e <= 1e-10;
+      ok = !kr_uany(badv || neg) && kr_wresid(y, y0, nn) <= 1e-10;
     }
     if (ok) { status = attempt; break; }
-    if (p.mode == 1) break;
+    if (mode == 1) break;
   }
   if (status == 2) { kr_wstats(p, C, 2); return; }
-  w.y[lane] = y;
-  w.v[lane] = y0;
-  __syncthreads();
-  if (lane == 0) kr_wpost0(w);
-  __syncthreads();
-  y = w.y[lane];
-  __syncthreads();
-  if (lane < KR_S) p.states[(long long)lane * p.ld + c] = y;
-  if (lane == KR_S) p.T[c] = y;
+  y = kr_wpost(y, y0);
+  kr_wstore(p, c, y);
   kr_wstats(p, C, status);
 }
 
@@ -669,15 +683,20 @@ template <bool MIXED>
 __device__ __forceinline__ void kr_wintegrate(const KrParams &p) {
   __shared__ KrWave w;
   const int lane = threadIdx.x;
-  for (int i = lane; i < KR_N * KR_LDJ; i += 64) w.J[i] = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < (KR_N * KR_LDJ + 63) / 64; ++k) {
+    const int i = 64 * k + lane;
+    if (i < KR_N * KR_LDJ) w.J[i] = 0.0;
+  }
   __syncthreads();
+  const unsigned long long n = (unsigned long long)p.n_cells;
   for (;;) {
-    unsigned long long c0 = 0ull;
-    if (lane == 0) c0 = atomicAdd(p.counter, 1ull);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)c0);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(c0 >> 32));
+    /* one claim per wave: lane 0 adds 1, the others 0; lane 0's result */
+    const unsigned long long c0 = atomicAdd(p.counter, lane == 0 ? 1ull : 0ull);
+    const unsigned lo = (unsigned)kr_ui((int)(unsigned)c0);
+    const unsigned hi = (unsigned)kr_ui((int)(unsigned)(c0 >> 32));
     const unsigned long long c = ((unsigned long long)hi << 32) | lo;
-    if (c >= (unsigned long long)p.n_cells) break;
+    if (c >= n) break;
     kr_wcell<MIXED>(p, w, (long long)c);
   }
 }
@@ -687,21 +706,24 @@ __device__ __forceinline__ void kr_wintegrate(const KrParams &p) {
 __device__ __forceinline__ void kr_wtimescale(const KrParams &p, double *out) {
   __shared__ KrWave w;
   const int lane = threadIdx.x;
-  for (int i = lane; i < KR_N * KR_LDJ; i += 64) w.J[i] = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < (KR_N * KR_LDJ + 63) / 64; ++k) {
+    const int i = 64 * k + lane;
+    if (i < KR_N * KR_LDJ) w.J[i] = 0.0;
+  }
   __syncthreads();
   for (long long c = blockIdx.x; c < p.n_cells; c += gridDim.x) {
     double dt;
     bool bad;
     const double y = kr_wload(p, c, dt, bad);
     kr_weval(w, y);
-    const double cv = kr_wheatcap(y);
+    const double cv = kr_u(kr_wheatcap(y));
     double m = 0.0;
     if (lane < KR_S) m = fabs(w.J[lane * KR_LDJ + lane]);
     if (lane == KR_S && cv > 0.0) m = fabs(w.J[KR_S * KR_LDJ + KR_S]) / cv;
-    m = kr_wmax(m);
+    m = kr_u(kr_wmax(m));
     const double tau = (m > 0.0 && kr_finite(m)) ? 1.0 / m : 1e7;
-    if (lane == 0) out[c] = (kr_finite(tau) && tau < 1e7) ? tau : 1e7;
-    __syncthreads();
+    out[c] = (kr_finite(tau) && tau < 1e7) ? tau : 1e7;
   }
 }
 

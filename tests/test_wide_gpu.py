@@ -9,9 +9,7 @@ import synthetic as sy
 from tests.test_parity_gpu import assert_parity, run_gpu, run_oracle
 
 torch = pytest.importorskip("torch")
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="wavefront layout disabled: its kernel did not return on gfx950 "
-                                      "for a one-cell batch (cause not found; device creation raises)")]
+pytestmark = pytest.mark.gpu
 
 
 def _kr():
