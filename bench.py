@@ -63,7 +63,7 @@ def flops_per_unit(desc):
     return f_it, f_rhs
 
 
-def cpu_baseline(desc, cs, dt_scalar, sample, seed=7):
+def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None):
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(seed)
@@ -71,7 +71,8 @@ def cpu_baseline(desc, cs, dt_scalar, sample, seed=7):
     on = oracle.OracleNet(desc)
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    on.integrate(cs.n[:, idx], cs.T[idx], cs.rho[idx], dt_scalar=dt_scalar, nthreads=cores)
+    on.integrate(cs.n[:, idx], cs.T[idx], cs.rho[idx], dt=None if dt is None else dt[idx],
+                 dt_scalar=dt_scalar, nthreads=cores)
     el = time.perf_counter() - t0
     return {"value": sample / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{sample} cells drawn uniformly (seed {seed}) from the same {cs.n.shape[1]}-cell "
@@ -79,7 +80,10 @@ def cpu_baseline(desc, cs, dt_scalar, sample, seed=7):
 
 
 MIX_FRACTIONS = (0.5, 0.3, 0.2)
-MIX_U_RANGE = (-4.0, -1.5)   # dt = tau_fast * 10^U[...]: substeps span ~1 to a few hundred
+# per-network step ranges, dt = tau_fast * 10^U[lo, hi], read off the
+# calibration table (bench.py --workload calibrate, 16384 cells per network)
+# so that the largest substep count of each network stays near 200
+MIX_U_RANGES = ((-4.0, -1.0), (-5.5, -4.0), (-4.0, -2.0))
 
 
 def _mix_descs():
@@ -100,8 +104,10 @@ _MIX_MAKERS = [_cells("cells_h_he"), _cells("cells_h_o_n"), _cells("cells_astro2
 def run_mixed(args):
     """Uneven batch in one persistent launch: 2^22 cells mixing the 6-, 10-
     and 24-unknown networks (50/30/20%), each cell's step a seeded multiple
-    10^U[-4,-1.5] of its own fastest timescale, FP32 LU with FP64
-    refinement, one hipGraph-replayed launch per step."""
+    10^U[lo, hi] (per network, MIX_U_RANGES) of its own fastest timescale,
+    FP32 LU with FP64 refinement, one hipGraph-replayed launch per step; the
+    5- and 9-species networks run one cell per lane, the 23-species one one
+    cell per wavefront (or as the autotuner picks)."""
     import torch
     import paper_2504_04941_amd as kr
     import synthetic as sy
@@ -121,21 +127,23 @@ def run_mixed(args):
         n0 = torch.tensor(cs.n, device=dev)
         T0 = torch.tensor(cs.T, device=dev)
         tau = kr.fastest_timescale(base_nets[k], n0, T0)
-        dt = tau * torch.tensor(sy.log_uniform(n, 10 ** MIX_U_RANGE[0], 10 ** MIX_U_RANGE[1], 2, 300 + k),
-                                device=dev)
+        lo, hi = MIX_U_RANGES[k]
+        dt = tau * torch.tensor(sy.log_uniform(n, 10 ** lo, 10 ** hi, 2, 300 + k), device=dev)
         init.append((n0, T0))
         bufs.append({"states": n0.clone(), "T": T0.clone(), "dt": dt,
                      "status": torch.empty(n, dtype=torch.int32, device=dev),
                      "cell_stats": torch.empty((n, 4), dtype=torch.int32, device=dev)})
     setup_s = time.perf_counter() - t0
     report = None
+    layouts = [kr.KR_LAYOUT_AUTO] * len(descs)
     if args.autotune:
         sample = [{k2: (v[..., : max(1, v.shape[-1] // 64)].contiguous() if k2 in ("states",) else
                         v[: max(1, v.shape[0] // 64)].contiguous()) for k2, v in b.items()} for b in bufs]
-        bo, report = autotune.tune_multi(descs, sample, precision=kr.KR_FP32LU_REFINE,
-                                         candidates=[(1, 0.1), (1, 0.01)],
-                                         log=lambda s: print("# " + s, file=sys.stderr, flush=True))
-    nets = [kr.Network(d, bo) for d in descs]
+        bo, layouts, report = autotune.tune_multi(descs, sample, precision=kr.KR_FP32LU_REFINE,
+                                                  candidates=[(1, 0.1), (1, 0.01)],
+                                                  log=lambda s: print("# " + s, file=sys.stderr, flush=True))
+    nets = [kr.Network(d, kr.build_options(waves_per_eu=bo.waves_per_eu, pivot_tau=bo.pivot_tau, layout=L))
+            for d, L in zip(descs, layouts)]
     multi = kr.Multi(nets, bo)
     opts = kr.default_options(precision=kr.KR_FP32LU_REFINE)
     stream = torch.cuda.current_stream()
@@ -178,14 +186,104 @@ def run_mixed(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32lu",
            "data": "synthetic",
            "config": {"workload": f"mixed: {args.cells} cells, 5/9/23-species networks 50/30/20%, "
-                                  "dt = tau_fast*10^U[-4,-1.5], FP32 LU + FP64 refinement, "
-                                  "one persistent hipGraph launch", "build": [bo.waves_per_eu, bo.pivot_tau]},
+                                  f"dt = tau_fast*10^U[range] per network {list(MIX_U_RANGES)}, FP32 LU + "
+                                  "FP64 refinement, one persistent hipGraph launch",
+                      "build": [bo.waves_per_eu, bo.pivot_tau],
+                      "layouts": ["wave" if n.wide else "lane" for n in nets]},
            "per_network": per_net, "graph": {"launches": launches, "captures": captures},
            "autotune": report, "setup_s": setup_s,
            "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": PEAK_FP64 / 1e12,
                         "unit": "TFLOP/s", "frac": flops / kernel_s / PEAK_FP64, "traffic": None,
                         "kernel": "kr_integrate_multi_fp32lu"}}
     print(json.dumps(out), flush=True)
+
+
+def run_large(args):
+    """Large network: 48 species / 200 reversible reactions / 5 element rows
+    + energy (49x49 LU), one cell per wavefront; per-cell steps log-uniform
+    in [1e-8, 1e-2] s; plain FP64 and the FP32 LU form."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    dev = torch.device("cuda", 0)
+    desc = sy.network_large48(3)
+    cs = sy.cells_large48(desc, args.cells, 3)
+    t0 = time.perf_counter()
+    net = kr.Network(desc)
+    setup_s = time.perf_counter() - t0
+    n0 = torch.tensor(cs.n, device=dev)
+    T0 = torch.tensor(cs.T, device=dev)
+    dt = torch.tensor(cs.dt, device=dev)
+    n, T = torch.empty_like(n0), torch.empty_like(T0)
+    status = torch.empty(args.cells, dtype=torch.int32, device=dev)
+    stats = torch.empty((args.cells, 4), dtype=torch.int32, device=dev)
+    counters = torch.zeros(8, dtype=torch.int64, device=dev)
+    f_it, f_rhs = flops_per_unit(desc)
+    stream = torch.cuda.current_stream()
+    results = {}
+    for variant in args.variants.split(","):
+        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE}.get(variant)
+        if prec is None:
+            continue
+        opts = kr.default_options(precision=prec)
+        opts.counters = counters.data_ptr()
+
+        def step():
+            n.copy_(n0)
+            T.copy_(T0)
+            counters.zero_()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            kr.chem_integrate(net, n, T, dt=dt, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
+                              stream=stream)
+            ev1.record(stream)
+            return ev0, ev1
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_s = np.mean([a.elapsed_time(b) for a, b in evs]) * 1e-3
+        st = stats.cpu().numpy().astype(np.int64)
+        acc = st[:, 0]
+        flops = st[:, 1].sum() * f_it + (st[:, 0] + st[:, 2]).sum() * f_rhs
+        results[variant] = {
+            "ms_per_step": wall / args.steps * 1e3, "value": args.cells * args.steps / wall,
+            "kernel_ms": kernel_s * 1e3, "flops_per_launch": float(flops),
+            "achieved_tflops": flops / kernel_s / 1e12,
+            "newton_iters_per_cell": float(st[:, 1].mean()), "substeps_per_cell": float(acc.mean()),
+            "max_substeps": int(acc.max()),
+            "substep_histogram": {"1": int((acc <= 1).sum()), "2-10": int(((acc > 1) & (acc <= 10)).sum()),
+                                  "11-200": int(((acc > 10) & (acc <= 200)).sum()),
+                                  "201-10^4": int(((acc > 200) & (acc <= 10000)).sum()),
+                                  ">10^4": int((acc > 10000).sum())},
+            "status_counts": np.bincount(status.cpu().numpy(), minlength=3).tolist(),
+            "counters_last_step": dict(zip(("guess_starts", "guess_fallbacks", "row_exchanges",
+                                            "fp32_solves", "fp64_fallbacks"),
+                                           counters.cpu().numpy()[:5].tolist()))}
+        print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
+    head = results.get("fp64") or next(iter(results.values()))
+    out = {"metric": "cell-steps/s implicit chem update, 48-species network, 1 GPU",
+           "value": head["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"large_48sp: {args.cells} cells, 48 species / 200 reversible reactions / "
+                                  "5 element rows + energy (49x49 LU), dt log-uniform [1e-8, 1e-2] s, rtol 1e-6, "
+                                  "one cell per wavefront",
+                      "layout": "wave" if net.wide else "lane"},
+           "variants": results, "setup_s": setup_s,
+           "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
+                        "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64, "traffic": None,
+                        "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
+                        "flops_per_error_estimate": f_rhs}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc, cs, 0.0, min(args.cpu_sample, args.cells), dt=cs.dt)
+    print(json.dumps(out), flush=True)
+    net.close()
 
 
 def calibrate_mixed(args):
@@ -230,7 +328,7 @@ def calibrate_mixed(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="h_o_n", choices=["h_o_n", "mixed", "calibrate"])
+    ap.add_argument("--workload", default="h_o_n", choices=["h_o_n", "mixed", "large48", "calibrate"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -248,6 +346,15 @@ def main():
 
     if args.workload == "calibrate":
         calibrate_mixed(args)
+        return
+    if args.workload == "large48":
+        if args.cells == 1 << 20:
+            args.cells = 1 << 18
+        if args.variants == "fp64,fp32lu,fp32lu+mlp":
+            args.variants = "fp64,fp32lu"
+        if args.cpu_sample == 1024:
+            args.cpu_sample = 48
+        run_large(args)
         return
     if args.workload == "mixed":
         if args.cells == 1 << 20:

@@ -124,14 +124,16 @@ void kr_network_destroy(kr_network *net);
  *                 layout; the wave-per-cell LU takes the best candidate)
  *   layout        KR_LAYOUT_AUTO: one cell per lane below
  *                 KR_WIDE_MIN_SPECIES species, one cell per wavefront from
- *                 there; KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
+ *                 there (measured on gfx950: the lane layout is 2-10x
+ *                 faster at 5 and 9 species, the wavefront layout 5x faster
+ *                 at 23); KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
  *                 wavefront layout holds the Newton matrix one row per lane
  *                 and needs n_species <= 62 and 5 * 2 * n_reactions
  *                 rounded up to 320 <= 4095 (n_reactions <= 384). */
 #define KR_LAYOUT_AUTO 0
 #define KR_LAYOUT_LANE 1
 #define KR_LAYOUT_WAVE 2
-#define KR_WIDE_MIN_SPECIES 32
+#define KR_WIDE_MIN_SPECIES 16
 typedef struct {
   int32_t waves_per_eu;
   float pivot_tau;
@@ -145,6 +147,8 @@ int kr_network_create_ex(const kr_network_desc *desc, const kr_build_opts *opt,
 
 /* Number of unknowns per cell (n_species + 1: abundances and temperature). */
 int kr_network_unknowns(const kr_network *net);
+/* Layout the network was compiled for: KR_LAYOUT_LANE or KR_LAYOUT_WAVE. */
+int kr_network_layout(const kr_network *net);
 
 /* Derived Arrhenius table actually used: out[r][dir][3] = (A, b, E), dir 0
  * forward, 1 reverse (host memory, n_reactions * 6 doubles). */

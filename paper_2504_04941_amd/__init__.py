@@ -27,9 +27,9 @@ KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
 KR_FP64, KR_FP32LU_REFINE = 0, 1
 KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
 KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
-KR_WIDE_MIN_SPECIES = 32
+KR_WIDE_MIN_SPECIES = 16
 
-EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns",
+EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns", "kr_network_layout",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
             "kr_default_options", "kr_chem_integrate", "kr_element_residual",
             "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
@@ -219,6 +219,7 @@ class Network:
         self.n_species = d.n_species
         self.n_reactions = d.n_reactions
         self.n_unknowns = lib().kr_network_unknowns(h)
+        self.wide = lib().kr_network_layout(h) == KR_LAYOUT_WAVE
 
     @property
     def handle(self):

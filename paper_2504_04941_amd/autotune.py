@@ -1,10 +1,12 @@
 """Autotuner for the generated integrator kernels.
 
-Tunables (compile-time, `kr_build_opts`): the occupancy target the register
-allocator budgets for (waves per SIMD; the lane's Newton matrix lives in
-VGPRs, so a higher target trades registers for scratch spills) and the
-threshold of the LU's partial pivoting (a smaller threshold takes fewer row
-exchanges, which execute wave-wide when any lane needs one).  Each candidate
+Tunables (compile-time, `kr_build_opts`): per network, the layout (one cell
+per lane, or one cell per wavefront with the Newton matrix one row per
+lane); for the module, the occupancy target the register allocator budgets
+for (waves per SIMD; the lane's Newton matrix lives in VGPRs, so a higher
+target trades registers for scratch spills) and the threshold of the LU's
+partial pivoting (a smaller threshold takes fewer row exchanges, which
+execute wave-wide when any lane needs one).  Each candidate
 is compiled, run on a sample of the caller's own cells (fresh copies per
 timing) and timed with HIP events on the launch stream; the fastest wins.
 Choices are cached in a JSON file keyed by the generated source (which
@@ -18,7 +20,8 @@ import json
 import os
 import time
 
-from . import BuildOpts, Multi, Network, build_options, default_options, multi_check, network_check
+from . import (KR_LAYOUT_LANE, KR_LAYOUT_WAVE, BuildOpts, Multi, Network, build_options, chem_integrate,
+               default_options, multi_check, network_check)
 
 CACHE = os.environ.get("KR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "kr_autotune.json"))
@@ -66,27 +69,78 @@ def _time_call(fn, reps):
     return best
 
 
+def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log=None):
+    """Faster layout (KR_LAYOUT_LANE or KR_LAYOUT_WAVE) of one network on a
+    sample of its cells (batch: dict as for Multi.integrate, copied before
+    every timed run).  Returns (layout, report)."""
+    import torch
+    srcs = [network_check(desc, build=build_options(layout=L)) for L in (KR_LAYOUT_LANE, KR_LAYOUT_WAVE)]
+    key = "layout-" + _key(srcs, precision)
+    db = _load() if use_cache else {}
+    if key in db:
+        return int(db[key]["best"]), db[key]
+    opts = default_options(precision=precision)
+    report = {"candidates": [], "sample_cells": int(batch["T"].numel())}
+    best, best_t = None, float("inf")
+    for L in (KR_LAYOUT_LANE, KR_LAYOUT_WAVE):
+        t0 = time.time()
+        net = Network(desc, build_options(layout=L))
+        compile_s = time.time() - t0
+
+        def run(prep):
+            if prep is None:
+                return {k: (v.clone() if torch.is_tensor(v) else v) for k, v in batch.items()}
+            chem_integrate(net, prep["states"], prep["T"], rho=prep.get("rho"), dt=prep.get("dt"),
+                           dt_scalar=prep.get("dt_scalar", 0.0), rtol=rtol, opts=opts,
+                           status=prep.get("status"), cell_stats=prep.get("cell_stats"))
+            return None
+
+        ms = _time_call(run, reps)
+        net.close()
+        report["candidates"].append({"layout": L, "ms": ms, "compile_s": compile_s})
+        if log:
+            log(f"autotune layout={'lane' if L == KR_LAYOUT_LANE else 'wave'}: {ms:.2f} ms "
+                f"(compile {compile_s:.1f} s)")
+        if ms < best_t:
+            best, best_t = L, ms
+    report["best"] = best
+    if use_cache:
+        db = _load()
+        db[key] = report
+        _store(db)
+    return best, report
+
+
 def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, reps=2,
                use_cache=True, log=None):
-    """Best build options for a set of networks integrated together.
+    """Best layout per network (tune_layout on its own sample) and best
+    module build options for the networks integrated together.
 
     batches: list of dicts as for Multi.integrate (a sample of the cells;
     they are copied before every timed run and left untouched).  Returns
-    (BuildOpts, report)."""
+    (BuildOpts, layouts, report)."""
     import torch
-    key = _key([multi_check(descs)], precision)
+    layouts, lay_reports = [], []
+    for d, b in zip(descs, batches):
+        L, r = tune_layout(d, b, precision, rtol, reps, use_cache, log)
+        layouts.append(L)
+        lay_reports.append(r)
+    key = _key([multi_check(descs)] + [str(layouts)], precision)
     db = _load() if use_cache else {}
     if key in db:
         w, tau = db[key]["best"]
-        return build_options(waves_per_eu=int(w), pivot_tau=float(tau)), db[key]
+        return build_options(waves_per_eu=int(w), pivot_tau=float(tau)), layouts, db[key]
     nets_cache = {}
-    report = {"candidates": [], "sample_cells": [int(b["T"].numel()) for b in batches]}
+    report = {"candidates": [], "sample_cells": [int(b["T"].numel()) for b in batches],
+              "layouts": ["lane" if L == KR_LAYOUT_LANE else "wave" for L in layouts],
+              "layout_timings": lay_reports}
     opts = default_options(precision=precision)
     best, best_t = None, float("inf")
     for w, tau in candidates:
         bo = build_options(waves_per_eu=w, pivot_tau=tau)
         t0 = time.time()
-        nets = [Network(d, bo) for d in descs]
+        nets = [Network(d, build_options(waves_per_eu=w, pivot_tau=tau, layout=L))
+                for d, L in zip(descs, layouts)]
         multi = Multi(nets, bo)
         compile_s = time.time() - t0
 
@@ -113,4 +167,4 @@ def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, re
         db = _load()
         db[key] = report
         _store(db)
-    return build_options(waves_per_eu=best[0], pivot_tau=best[1]), report
+    return build_options(waves_per_eu=best[0], pivot_tau=best[1]), layouts, report

@@ -581,6 +581,10 @@ extern "C" void kr_network_destroy(kr_network *net) { release(net); }
 
 extern "C" int kr_network_unknowns(const kr_network *net) { return net ? net->S + 1 : KR_EINVAL; }
 
+extern "C" int kr_network_layout(const kr_network *net) {
+  return net ? (net->wide ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE) : KR_EINVAL;
+}
+
 extern "C" int kr_network_arrhenius(const kr_network *net, double *out) {
   if (!net || !out) return fail(KR_EINVAL, "null argument");
   std::memcpy(out, net->par.data(), sizeof(double) * net->par.size());
@@ -824,8 +828,13 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
   std::string s = "/* per-cell implicit thermochemistry: several networks in one launch */\n" +
                   build_prefix(o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
-    s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" + kDeviceSource +
-         "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";
+    if (nets[k]->wide)
+      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_wide(nets[k]) + "\n" + kWideSource +
+           "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n#undef KR_LDJ\n#undef KR_NDR\n"
+           "#undef KR_NC\n#undef KR_NF\n#undef KR_NDP\n#undef KR_NOTPIV\n";
+    else
+      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" + kDeviceSource +
+           "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";
   }
   s += "struct KrMulti { KrParams net[" + std::to_string(KR_MAX_NETS) + "]; int n_nets; };\n";
   for (int mixed = 0; mixed < 2; ++mixed) {
@@ -838,8 +847,9 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
          "    const int k = (int)((blockIdx.x + i) % (unsigned)m.n_nets);\n"
          "    switch (k) {\n";
     for (size_t k = 0; k < nets.size(); ++k)
-      s += "      case " + std::to_string(k) + ": kr_m" + std::to_string(k) + "::kr_integrate_body<" +
-           (mixed ? "true" : "false") + ">(m.net[" + std::to_string(k) + "]); break;\n";
+      s += "      case " + std::to_string(k) + ": kr_m" + std::to_string(k) +
+           (nets[k]->wide ? "::kr_wintegrate<" : "::kr_integrate_body<") + (mixed ? "true" : "false") +
+           ">(m.net[" + std::to_string(k) + "]); break;\n";
     s += "      default: break;\n    }\n  }\n}\n";
   }
   s += "extern \"C\" __global__ void kr_reset_counters(unsigned long long *c, int n) {\n"
@@ -864,7 +874,6 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
   for (int k = 0; k < n_nets; ++k) {
     if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
-    if (nets[k]->wide) return fail(KR_EINVAL, "network %d uses the wavefront layout, not supported here", k);
   }
   kr_build_opts bo;
   kr_default_build_options(&bo);
@@ -919,6 +928,13 @@ extern "C" int kr_multi_check(const kr_network_desc *const *descs, int32_t n_net
   }
   kr_build_opts bo;
   kr_default_build_options(&bo);
+  for (int k = 0; k < n_nets; ++k) {
+    tabs[k].wide = use_wide(&tabs[k], bo);
+    if (tabs[k].wide) {
+      int rc = check_wide(&tabs[k]);
+      if (rc != KR_OK) return rc;
+    }
+  }
   const std::string src = multi_source(ptrs, bo);
   if (src_buf && src_len > 0) {
     const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
@@ -984,7 +1000,9 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
   hipFunction_t f = o.precision == KR_FP64 ? m->f_fp64 : m->f_fp32;
   const int occ = o.precision == KR_FP64 ? m->occ_fp64 : m->occ_fp32;
   long long blocks = (long long)m->cu_count * (occ > 0 ? occ : 1);
-  const long long need = (total + 63) / 64;
+  long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
+  for (int k = 0; k < h.n_nets; ++k)
+    need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
   unsigned long long *cnt = m->d_counters;

@@ -731,6 +731,7 @@ __device__ __forceinline__ void kr_wtimescale(const KrParams &p, double *out) {
 #define KR_WAVES_PER_EU 1
 #endif
 
+#ifndef KR_NO_KERNELS
 extern "C" __global__ void __launch_bounds__(64, 1) kr_timescale(KrParams p, double *out) {
   kr_wtimescale(p, out);
 }
@@ -746,3 +747,4 @@ extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_f
 extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = 0ull;
 }
+#endif /* KR_NO_KERNELS */

@@ -252,6 +252,7 @@ def test_fp32lu_astro23_batch(oracle_lib):
     cs = sy.cells_astro23(desc, 256, 2)
     on = oracle_lib.OracleNet(desc)
     dt = np.array([1e-2 * on.fastest_timescale(np.r_[cs.n[:, c], cs.T[c]]) for c in range(256)])
-    gpu = run_gpu(desc, cs, dt=dt, precision=1)
+    kr = _kr()
+    gpu = run_gpu(desc, cs, dt=dt, precision=1, build=kr.build_options(layout=kr.KR_LAYOUT_LANE))
     orc = run_oracle(oracle_lib, desc, cs, dt=dt)
     assert_parity(gpu, orc, cs, 1e-6, "astro23 fp32lu batch", desc=desc)
