@@ -63,6 +63,25 @@ def flops_per_unit(desc):
     return f_it, f_rhs
 
 
+PROFILE = os.path.join(ROOT, "profiles", "kr_integrate_fp64_h_o_n_1M.md")
+
+
+def measured_traffic(kernel_source):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this exact kernel (hash of the generated device source); else
+    None."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("source_sha256") != hashlib.sha256(kernel_source.encode()).hexdigest():
+        return None
+    return rec["traffic_bytes"]
+
+
 def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None):
     import oracle
     oracle.build(force=False)
@@ -336,7 +355,7 @@ def main():
     ap.add_argument("--variants", default="fp64,fp32lu,fp32lu+mlp")
     ap.add_argument("--train-pairs", type=int, default=1 << 22)
     ap.add_argument("--train-steps", type=int, default=2000)
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -352,7 +371,7 @@ def main():
             args.cells = 1 << 18
         if args.variants == "fp64,fp32lu,fp32lu+mlp":
             args.variants = "fp64,fp32lu"
-        if args.cpu_sample == 1024:
+        if args.cpu_sample == 8192:
             args.cpu_sample = 48
         run_large(args)
         return
@@ -484,7 +503,7 @@ def main():
         "learned_guess": learned_info,
         "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64,
-                     "traffic": None,
+                     "traffic": measured_traffic(kr.network_check(desc)),
                      "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
                      "flops_per_error_estimate": f_rhs, "exp_log_flops": C_EXP},
     }
