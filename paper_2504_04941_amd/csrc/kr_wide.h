@@ -85,17 +85,29 @@ __device__ __forceinline__ double kr_wmax(double v) {
   return v;
 }
 
+/* max(k, k of the lane the DPP control selects); lanes of rows outside
+ * row_mask, or whose source lane does not exist, keep k */
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned kr_dpp_max(unsigned k) {
+  const unsigned t = (unsigned)__builtin_amdgcn_update_dpp((int)k, (int)k, CTRL, ROWS, 0xF, false);
+  return t > k ? t : k;
+}
+
 /* Lane holding the largest non-negative key (lowest lane on ties); key 0 for
- * lanes that do not compete.  Returns the winning lane, and its key. */
+ * lanes that do not compete.  Returns the winning lane, and its key.  The
+ * wave maximum is built with DPP moves (quad permutes, half-row and row
+ * mirrors, then the row broadcasts 15 and 31 into the upper rows), which
+ * leaves it in lane 63: no LDS round trips. */
 __device__ __forceinline__ int kr_wargmax(float key, bool cand, unsigned &best) {
   const int lane = threadIdx.x;
   unsigned k = cand ? ((__float_as_uint(key) & ~63u) | (unsigned)(63 - lane)) : 0u;
-#pragma unroll
-  for (int o = 32; o; o >>= 1) {
-    const unsigned t = (unsigned)__shfl_xor((int)k, o);
-    k = t > k ? t : k;
-  }
-  best = (unsigned)__builtin_amdgcn_readfirstlane((int)k);
+  k = kr_dpp_max<0xB1, 0xF>(k);    /* quad_perm [1,0,3,2] */
+  k = kr_dpp_max<0x4E, 0xF>(k);    /* quad_perm [2,3,0,1] */
+  k = kr_dpp_max<0x141, 0xF>(k);   /* row_half_mirror */
+  k = kr_dpp_max<0x140, 0xF>(k);   /* row_mirror: every lane holds its row's max */
+  k = kr_dpp_max<0x142, 0xA>(k);   /* row_bcast:15 into rows 1 and 3 */
+  k = kr_dpp_max<0x143, 0xC>(k);   /* row_bcast:31 into rows 2 and 3: lane 63 holds the max */
+  best = (unsigned)__builtin_amdgcn_readlane((int)k, 63);
   return 63 - (int)(best & 63u);
 }
 
