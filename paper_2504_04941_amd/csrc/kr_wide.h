@@ -73,16 +73,39 @@ __device__ __forceinline__ double kr_u(double v) { return kr_bcast(v, 0); }
 __device__ __forceinline__ int kr_ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ bool kr_uany(bool b) { return __ballot(b) != 0ull; }
 
-__device__ __forceinline__ double kr_wsum(double v) {
-#pragma unroll
-  for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+/* v of the lane the DPP control selects; 0 in rows outside row_mask or where
+ * the source lane does not exist */
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double kr_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+/* Wave sum by DPP moves (quad permutes, half-row and row mirrors, then the
+ * row broadcasts 15 and 31): lane 63 ends with the total, which every lane
+ * receives as a scalar.  The order of additions is fixed. */
+__device__ __forceinline__ double kr_wsum(double v) {
+  v += kr_dpp<0xB1, 0xF>(v);
+  v += kr_dpp<0x4E, 0xF>(v);
+  v += kr_dpp<0x141, 0xF>(v);
+  v += kr_dpp<0x140, 0xF>(v);
+  v += kr_dpp<0x142, 0xA>(v);
+  v += kr_dpp<0x143, 0xC>(v);
+  return kr_bcast(v, 63);
+}
+
+/* Wave maximum of non-negative values (a NaN is skipped, as by a running
+ * maximum that keeps the larger of the two), by the same DPP moves. */
 __device__ __forceinline__ double kr_wmax(double v) {
-#pragma unroll
-  for (int o = 32; o; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = fmax(v, kr_dpp<0xB1, 0xF>(v));
+  v = fmax(v, kr_dpp<0x4E, 0xF>(v));
+  v = fmax(v, kr_dpp<0x141, 0xF>(v));
+  v = fmax(v, kr_dpp<0x140, 0xF>(v));
+  v = fmax(v, kr_dpp<0x142, 0xA>(v));
+  v = fmax(v, kr_dpp<0x143, 0xC>(v));
+  return kr_bcast(v, 63);
 }
 
 /* max(k, k of the lane the DPP control selects); lanes of rows outside
