@@ -156,9 +156,10 @@ def run_mixed(args):
     report = None
     layouts = [kr.KR_LAYOUT_AUTO] * len(descs)
     if args.autotune:
-        sample = [{k2: (v[..., : max(1, v.shape[-1] // 64)].contiguous() if k2 in ("states",) else
-                        v[: max(1, v.shape[0] // 64)].contiguous()) for k2, v in b.items()} for b in bufs]
-        bo, layouts, report = autotune.tune_multi(descs, sample, precision=kr.KR_FP32LU_REFINE,
+        # tuned on the whole batch: the layouts' relative speed depends on how
+        # many cells each lane or wavefront gets (a 1/64 sample picked the
+        # wavefront layout for the 9-species network, which is slower at size)
+        bo, layouts, report = autotune.tune_multi(descs, bufs, precision=kr.KR_FP32LU_REFINE,
                                                   candidates=[(1, 0.1), (1, 0.01)],
                                                   log=lambda s: print("# " + s, file=sys.stderr, flush=True))
     nets = [kr.Network(d, kr.build_options(waves_per_eu=bo.waves_per_eu, pivot_tau=bo.pivot_tau, layout=L))
