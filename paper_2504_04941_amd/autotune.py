@@ -10,8 +10,10 @@ execute wave-wide when any lane needs one).  Each candidate
 is compiled, run on a sample of the caller's own cells (fresh copies per
 timing) and timed with HIP events on the launch stream; the fastest wins.
 Choices are cached in a JSON file keyed by the generated source (which
-encodes the network and the kernel template), the device name and the
-precision, so a network is tuned once per machine.
+encodes the network and the kernel template), the device name, the
+precision and the batch size class (log2 of the cell count: the layouts'
+relative speed depends on the cells per lane or wavefront), so a network is
+tuned once per machine and size class.
 """
 from __future__ import annotations
 
@@ -75,7 +77,9 @@ def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log
     every timed run).  Returns (layout, report)."""
     import torch
     srcs = [network_check(desc, build=build_options(layout=L)) for L in (KR_LAYOUT_LANE, KR_LAYOUT_WAVE)]
-    key = "layout-" + _key(srcs, precision)
+    # the answer depends on how many cells there are per lane or wavefront
+    size_class = int(batch["T"].numel()).bit_length()
+    key = "layout-" + _key(srcs + [str(size_class)], precision)
     db = _load() if use_cache else {}
     if key in db:
         return int(db[key]["best"]), db[key]
@@ -125,7 +129,8 @@ def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, re
         L, r = tune_layout(d, b, precision, rtol, reps, use_cache, log)
         layouts.append(L)
         lay_reports.append(r)
-    key = _key([multi_check(descs)] + [str(layouts)], precision)
+    key = _key([multi_check(descs)] + [str(layouts)] + [str(int(b["T"].numel()).bit_length()) for b in batches],
+               precision)
     db = _load() if use_cache else {}
     if key in db:
         w, tau = db[key]["best"]
