@@ -175,6 +175,15 @@ int kr_network_check_ex(const kr_network_desc *desc, const kr_build_opts *opt, i
 
 enum { KR_FP64 = 0, KR_FP32LU_REFINE = 1 };  /* precision of the linear solve */
 enum { KR_ADAPTIVE = 0, KR_FIXED_STEP = 1 }; /* substep control */
+/* Order in which the persistent kernel hands out a batch's cells.  Results
+ * per cell are the same either way.  KR_ORDER_WORK first sorts the cells by
+ * an estimate of their work, largest first, so that long cells do not start
+ * last and leave the rest of their wavefront (and the GPU) idle: the
+ * estimate is dt (sum_s |f_s| / sum_s n_s + |Q| / eps) at the input state,
+ * bucketed in half-octaves (three extra kernels on the stream; the first
+ * call with a larger batch than before allocates n_cells * 5 bytes and
+ * synchronises the device). */
+enum { KR_ORDER_INPUT = 0, KR_ORDER_WORK = 1 };
 
 typedef struct {
   int32_t precision;    /* KR_FP64 (default) or KR_FP32LU_REFINE: LU in FP32,
@@ -184,7 +193,7 @@ typedef struct {
   int32_t n_fixed;      /* substeps per cell in KR_FIXED_STEP (>= 1) */
   int32_t max_newton;   /* Newton iterations per substep (default 10) */
   int32_t max_substeps; /* substep attempts per cell and attempt (100000) */
-  int32_t reserved;
+  int32_t order;        /* KR_ORDER_WORK (default) or KR_ORDER_INPUT */
   double floor;         /* absolute tolerance as a fraction of the nuclei
                            density (default 1e-20) */
   double newton_tol;    /* weighted max-norm bound on the Newton update
@@ -229,6 +238,19 @@ int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
                       const double *dt, double dt_scalar, double rtol,
                       const kr_options *opt, int32_t *status,
                       int32_t *cell_stats, kr_stream_t stream);
+
+/* The order in which kr_chem_integrate with KR_ORDER_WORK hands out this
+ * batch's cells: order[i] = index of the i-th cell handed out, largest
+ * expected work first (see KR_ORDER_WORK; cells of one half-octave bucket
+ * in arbitrary order).  states, ld, T, rho, dt, dt_scalar as for
+ * kr_chem_integrate (read only); opt supplies floor and rho_floor (NULL for
+ * defaults); order device [n_cells] uint32.  Shares the network's ordering
+ * scratch with kr_chem_integrate: calls on one network are serialised by
+ * the caller.  Errors: KR_EINVAL (NULL arrays, ld < n_cells,
+ * n_cells > 2^32 - 1), KR_EDEVICE, KR_ENOMEM. */
+int kr_work_order(const kr_network *net, int64_t n_cells, const double *states, int64_t ld,
+                  const double *T, const double *rho, const double *dt, double dt_scalar,
+                  const kr_options *opt, uint32_t *order, kr_stream_t stream);
 
 /* Per-cell conservation residual (the constant-element-abundance invariant,
  * Sec. 2.1 eq. method-const-elem, taken per cell between two states):

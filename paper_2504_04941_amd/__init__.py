@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libkr.so")
 KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
 KR_FP64, KR_FP32LU_REFINE = 0, 1
 KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
+KR_ORDER_INPUT, KR_ORDER_WORK = 0, 1
 KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
 KR_WIDE_MIN_SPECIES = 16
 
@@ -57,7 +58,7 @@ class _Desc(C.Structure):
 class Options(C.Structure):
     """kr_options; defaults from kr_default_options."""
     _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("n_fixed", C.c_int32),
-                ("max_newton", C.c_int32), ("max_substeps", C.c_int32), ("reserved", C.c_int32),
+                ("max_newton", C.c_int32), ("max_substeps", C.c_int32), ("order", C.c_int32),
                 ("floor", C.c_double), ("newton_tol", C.c_double), ("rho_floor", C.c_double),
                 ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p)]
 
@@ -115,6 +116,7 @@ def lib():
         L.kr_default_build_options.restype = None
         L.kr_network_create_ex.argtypes = [C.POINTER(_Desc), C.POINTER(BuildOpts), C.POINTER(vp)]
         L.kr_fastest_timescale.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+        L.kr_work_order.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.c_double, C.POINTER(Options), vp, vp]
         L.kr_multi_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(BuildOpts), C.POINTER(vp)]
         L.kr_multi_destroy.argtypes = [vp]
         L.kr_multi_destroy.restype = None
@@ -295,6 +297,26 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
         _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar), float(rtol), C.byref(o),
         _dev_ptr(status, torch.int32, "status"), _dev_ptr(cell_stats, torch.int32, "cell_stats"),
         _stream_ptr(stream)))
+
+
+def work_order(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
+               opts: Options | None = None, out=None, stream=None):
+    """kr_work_order: the order (int32 view of uint32 cell indices) in which
+    kr_chem_integrate with KR_ORDER_WORK hands out the cells, largest
+    expected work first."""
+    import torch
+    n = int(T.numel())
+    if states.dim() != 2 or states.stride(1) != 1 or states.shape[1] < n:
+        raise ValueError("states must be [n_species, ld] with unit stride along cells")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=T.device)
+    o = opts if opts is not None else default_options()
+    _check(lib().kr_work_order(net.handle, n, _dev_ptr(states, torch.float64, "states"),
+                               int(states.stride(0)), _dev_ptr(T, torch.float64, "T"),
+                               _dev_ptr(rho, torch.float64, "rho"), _dev_ptr(dt, torch.float64, "dt"),
+                               float(dt_scalar), C.byref(o), _dev_ptr(out, torch.int32, "out"),
+                               _stream_ptr(stream)))
+    return out
 
 
 def fastest_timescale(net: Network, states, T, out=None, stream=None):

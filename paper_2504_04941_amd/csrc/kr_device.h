@@ -498,6 +498,10 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
   const unsigned long long c = atomicAdd(p.counter, 1ull);
   if (c >= (unsigned long long)p.n_cells) return false;
   L.cell = (long long)c;
+  if (p.order) {
+    const long long o = (long long)p.order[c];
+    L.cell = o < p.n_cells ? o : L.cell;    /* range guard; always true */
+  }
   L.acc = L.iters = L.rej = L.nfail = 0;
   L.attempt = 0;
   L.gstate = p.guess ? 1 : 0;
@@ -830,6 +834,32 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #define KR_WAVES_PER_EU 1
 #endif
 
+/* Expected-work bucket of each cell at its pre-processed input state
+ * (kr_order.h): w = dt (sum_s |f_s| / sum_s n_s + |Q| / eps); cells that
+ * are reverted or have nothing to integrate get bucket 0. */
+__device__ __forceinline__ void kr_order_keys_body(const KrParams &p, unsigned char *bucket,
+                                                   unsigned *hist) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < p.n_cells;
+       c += (long long)gridDim.x * blockDim.x) {
+    double y[KR_N], g[KR_N], J[KR_N][KR_N], dt;
+    const bool ok = kr_load_input(p, c, y, dt);
+    unsigned b = 0u;
+    if (ok && dt > 0.0) {
+      kr_eval(y, g, J);
+      double sf = 0.0, sn = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) {
+        sf += fabs(g[s]);
+        sn += y[s];
+      }
+      const double eps = y[KR_S] * kr_heat_capacity(y);
+      b = kr_work_bucket(dt * (sf / sn + fabs(g[KR_S]) / eps));
+    }
+    bucket[c] = (unsigned char)b;
+    atomicAdd(&hist[b], 1u);
+  }
+}
+
 /* Fastest self-coupling timescale of each cell at its input state:
  * 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s (workload set-up:
  * steps expressed in units of it). */
@@ -864,5 +894,10 @@ extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_f
 
 extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}
+
+extern "C" __global__ void __launch_bounds__(64, 1) kr_order_keys(KrParams p, unsigned char *bucket,
+                                                                  unsigned *hist) {
+  kr_order_keys_body(p, bucket, hist);
 }
 #endif /* KR_NO_KERNELS */

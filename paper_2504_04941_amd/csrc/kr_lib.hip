@@ -39,8 +39,15 @@ static const char *kWideSource =
 static const char *kParamsSource =
 #include "kr_params_src.inc"
     ;
+static const char *kMathSource =
+#include "kr_math_src.inc"
+    ;
+static const char *kOrderSource =
+#include "kr_order_src.inc"
+    ;
 
 static const double kBoltzmann = 1.380649e-16; /* erg / K */
+static const int KR_ORDER_NBUCKETS = 256;       /* KR_ORDER_BUCKETS of kr_order.h */
 
 /* ------------------------------------------------------------------------ */
 /* errors                                                                    */
@@ -71,6 +78,22 @@ extern "C" const char *kr_last_error(void) { return g_err.c_str(); }
 /* network                                                                   */
 /* ------------------------------------------------------------------------ */
 
+/* Buffers of the largest-work-first cell order (kr_order.h): cell order,
+ * per-cell bucket, histogram + bucket starts; grown to the largest batch. */
+struct OrderBufs {
+  unsigned *order = nullptr;
+  unsigned char *bucket = nullptr;
+  unsigned *hist = nullptr;
+  long long cap = 0;
+};
+
+static void order_free(OrderBufs &b) {
+  if (b.order) (void)hipFree(b.order);
+  if (b.bucket) (void)hipFree(b.bucket);
+  if (b.hist) (void)hipFree(b.hist);
+  b = OrderBufs{};
+}
+
 struct kr_network {
   int S = 0, n_rows = 0, n_elem = 0, R = 0;
   std::vector<int32_t> comp, res, reac, prod;
@@ -79,9 +102,11 @@ struct kr_network {
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
+  hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
   bool wide = false;            /* one wavefront per cell */
+  OrderBufs ord;
   unsigned long long *d_counter = nullptr;
   unsigned long long *d_max = nullptr;
   int32_t *d_comp = nullptr;
@@ -305,12 +330,15 @@ static std::string generate_wide(const kr_network *n) {
   o += "__device__ static constexpr double kr_hf[" + std::to_string(S) + "] = {";
   for (int s = 0; s < S; ++s) o += hexd(n->h[s]) + (s + 1 < S ? "," : "");
   o += "};\n";
-  const char *names[3] = {"kr_dA", "kr_db", "kr_dE"};
+  /* per direction log2 A (-4096 for an empty slot: 2^-4096 is 0), b, C */
+  const char *names[3] = {"kr_da2", "kr_db", "kr_dE"};
   for (int q = 0; q < 3; ++q) {
     o += std::string("__device__ static constexpr double ") + names[q] + "[" + std::to_string(NDP) + "] = {";
     for (int d = 0; d < NDP; ++d) {
-      double v = 0.0;
-      if (d < (int)dirs.size()) v = q == 0 ? dirs[d].A : (q == 1 ? dirs[d].b : dirs[d].E);
+      double v = q == 0 ? -4096.0 : 0.0;
+      if (d < (int)dirs.size())
+        v = q == 0 ? (dirs[d].A > 0.0 ? (double)log2l((long double)dirs[d].A) : -4096.0)
+                   : (q == 1 ? dirs[d].b : dirs[d].E);
       o += hexd(v) + (d + 1 < NDP ? "," : "");
     }
     o += "};\n";
@@ -367,6 +395,21 @@ static std::string network_tables(const kr_network *n) {
   return o;
 }
 
+/* k = A T^b exp(-C/T) as 2^(log2 A + b log2 T - C log2(e) / T) (kr_math.h):
+ * the generated code holds log2 A and C log2(e), rounded once from extended
+ * precision; l2T and iT are the evaluation point's log2 T and 1/T. */
+static std::string arrhenius_code(const double *abc) {
+  const long double log2e = 1.4426950408889634073599246810018921L;
+  const double a2 = (double)log2l((long double)abc[0]);
+  const double b = abc[1];
+  const double c2 = (double)((long double)abc[2] * log2e);
+  if (b == 0.0 && c2 == 0.0) return hexd(abc[0]);
+  std::string x = hexd(a2);
+  if (b != 0.0) x = "fma(" + hexd(b) + ", l2T, " + x + ")";
+  if (c2 != 0.0) x = "fma(" + hexd(-c2) + ", iT, " + x + ")";
+  return "kr_exp2(" + x + ")";
+}
+
 /* The network-specific section of the lane-per-cell device source. */
 static std::string generate_network(const kr_network *n) {
   const int S = n->S, V = n->n_rows;
@@ -380,7 +423,7 @@ static std::string generate_network(const kr_network *n) {
        "                                        double (&J)[KR_S + 1][KR_S + 1]) {\n"
        "#pragma unroll\n  for (int i = 0; i <= KR_S; ++i) {\n    g[i] = 0.0;\n"
        "#pragma unroll\n    for (int j = 0; j <= KR_S; ++j) J[i][j] = 0.0;\n  }\n"
-       "  const double T = y[KR_S];\n  const double lnT = log(T);\n  const double iT = 1.0 / T;\n";
+       "  const double T = y[KR_S];\n  const double l2T = kr_log2(T);\n  const double iT = 1.0 / T;\n";
   const std::string ST = std::to_string(S);
   for (int r = 0; r < n->R; ++r) {
     const double *pf = &n->par[6 * (size_t)r], *pr = pf + 3;
@@ -399,8 +442,7 @@ static std::string generate_network(const kr_network *n) {
       const double *pp = dir ? pr : pf;
       if (pp[0] == 0.0) continue;
       const std::string k = dir ? "kr" : "kf";
-      o += "    const double " + k + " = " + hexd(pp[0]) + " * exp(" + hexd(pp[1]) + " * lnT - " +
-           hexd(pp[2]) + " * iT);\n";
+      o += "    const double " + k + " = " + arrhenius_code(pp) + ";\n";
       SideCode c = side_code(k, dir ? &n->prod[3 * r] : &n->reac[3 * r]);
       const std::string q = dir ? "qr" : "qf";
       o += "    const double " + q + " = " + c.q + ";\n";
@@ -508,13 +550,14 @@ static bool use_wide(const kr_network *n, const kr_build_opts &o) {
 static std::string full_source(const kr_network *n, const kr_build_opts &o) {
   if (use_wide(n, o))
     return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(o) +
-           kParamsSource + "\n" + generate_wide(n) + "\n" + kWideSource;
+           kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_wide(n) + "\n" + kWideSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         build_prefix(o) + kParamsSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
+         build_prefix(o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
 }
 
 static void release(kr_network *n) {
   if (!n) return;
+  order_free(n->ord);
   if (n->d_counter) (void)hipFree(n->d_counter);
   if (n->d_max) (void)hipFree(n->d_max);
   if (n->d_comp) (void)hipFree(n->d_comp);
@@ -560,6 +603,9 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
   CREATE_TRY(hipModuleGetFunction(&n->f_fp32, n->module, "kr_integrate_fp32lu"));
   CREATE_TRY(hipModuleGetFunction(&n->f_reset, n->module, "kr_reset_counter"));
   CREATE_TRY(hipModuleGetFunction(&n->f_tau, n->module, "kr_timescale"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_keys, n->module, "kr_order_keys"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_scan, n->module, "kr_order_scan"));
+  CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
   CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
   CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
   CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
@@ -636,6 +682,56 @@ extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *
 /* integration                                                               */
 /* ------------------------------------------------------------------------ */
 
+/* Room for a batch of n cells (allocation synchronises the device, so the
+ * first call with a larger batch is not graph-capturable; callers reserve
+ * before capturing). */
+static int order_reserve(OrderBufs &b, long long n) {
+  if (n <= b.cap) return KR_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (b.order) (void)hipFree(b.order);
+  if (b.bucket) (void)hipFree(b.bucket);
+  b.order = nullptr;
+  b.bucket = nullptr;
+  b.cap = 0;
+  HIP_TRY(hipMalloc(&b.order, (size_t)n * sizeof(unsigned)));
+  HIP_TRY(hipMalloc(&b.bucket, (size_t)n));
+  if (!b.hist) {
+    HIP_TRY(hipMalloc(&b.hist, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)));
+    HIP_TRY(hipMemset(b.hist, 0, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)));
+  }
+  b.cap = n;
+  return KR_OK;
+}
+
+/* Largest-expected-work-first order of the batch in p (kr_order.h): key
+ * kernel -> scan -> scatter on stream st; sets p.order.  The buffers must
+ * hold p.n_cells (order_reserve).  The histogram is cleared by the scan
+ * kernel itself, so the sequence can be captured into a graph. */
+static int order_launch(hipFunction_t keys, hipFunction_t scan, hipFunction_t scatter, const OrderBufs &b,
+                        bool wide, int cu_count, KrParams &p, hipStream_t st) {
+  const long long n = p.n_cells;
+  unsigned *hist = b.hist, *start = b.hist + KR_ORDER_NBUCKETS;
+  unsigned char *bucket = b.bucket;
+  unsigned *order = b.order;
+  const long long grid = (long long)cu_count * 8;
+  const long long kb = wide ? std::min<long long>(n, grid) : std::min<long long>((n + 63) / 64, grid);
+  p.order = nullptr;
+  void *kargs[] = {&p, &bucket, &hist};
+  HIP_TRY(hipModuleLaunchKernel(keys, (unsigned)kb, 1, 1, 64, 1, 1, 0, st, kargs, nullptr));
+  void *sargs[] = {&hist, &start};
+  HIP_TRY(hipModuleLaunchKernel(scan, 1, 1, 1, 64, 1, 1, 0, st, sargs, nullptr));
+  long long nn = n;
+  const long long cb = std::min<long long>((n + 63) / 64, grid);
+  void *cargs[] = {&nn, &bucket, &start, &order};
+  HIP_TRY(hipModuleLaunchKernel(scatter, (unsigned)cb, 1, 1, 64, 1, 1, 0, st, cargs, nullptr));
+  p.order = order;
+  return KR_OK;
+}
+
+static bool want_order(const kr_options &o, long long n) {
+  return o.order == KR_ORDER_WORK && n > 1 && n <= 0xFFFFFFFFll;
+}
+
 extern "C" void kr_default_options(kr_options *o) {
   if (!o) return;
   o->precision = KR_FP64;
@@ -643,7 +739,7 @@ extern "C" void kr_default_options(kr_options *o) {
   o->n_fixed = 1;
   o->max_newton = 10;
   o->max_substeps = 100000;
-  o->reserved = 0;
+  o->order = KR_ORDER_WORK;
   o->floor = 1e-20;
   o->newton_tol = 1e-3;
   o->rho_floor = 0.0;
@@ -665,7 +761,7 @@ extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double 
   if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
       (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
       o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
-      !(o.rho_floor >= 0.0))
+      !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
     return fail(KR_EINVAL, "bad options");
   if (n_cells == 0) return KR_OK;
   if (!states || !T) return fail(KR_EINVAL, "null state arrays");
@@ -682,6 +778,14 @@ extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double 
   if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
   if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
   p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
+  p.order = nullptr;
+  if (want_order(o, n_cells)) {
+    kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
+    int rc = order_reserve(mnet->ord, n_cells);
+    if (rc == KR_OK)
+      rc = order_launch(net->f_keys, net->f_scan, net->f_scatter, net->ord, net->wide, net->cu_count, p, st);
+    if (rc != KR_OK) return rc;
+  }
 
   unsigned long long *cnt = net->d_counter;
   void *rargs[] = {&cnt};
@@ -778,6 +882,32 @@ extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const
   return KR_OK;
 }
 
+extern "C" int kr_work_order(const kr_network *net, int64_t n_cells, const double *states, int64_t ld,
+                             const double *T, const double *rho, const double *dt, double dt_scalar,
+                             const kr_options *opt, uint32_t *order, kr_stream_t stream) {
+  if (!net) return fail(KR_EINVAL, "null network");
+  if (n_cells < 0 || ld < n_cells || n_cells > 0xFFFFFFFFll)
+    return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
+  if (n_cells == 0) return KR_OK;
+  if (!states || !T || !order) return fail(KR_EINVAL, "null array");
+  if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+  kr_options o;
+  kr_default_options(&o);
+  if (opt) o = *opt;
+  if (!(o.floor >= 0.0) || !(o.rho_floor >= 0.0)) return fail(KR_EINVAL, "bad options");
+  HIP_TRY(hipSetDevice(net->device));
+  KrParams p{};
+  p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.rho = rho; p.dt = dt;
+  p.dt_scalar = dt_scalar; p.floor = o.floor; p.rho_floor = o.rho_floor;
+  kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
+  int rc = order_reserve(mnet->ord, n_cells);
+  if (rc != KR_OK) return rc;
+  OrderBufs b = net->ord;
+  b.order = order;
+  return order_launch(net->f_keys, net->f_scan, net->f_scatter, b, net->wide, net->cu_count, p,
+                      (hipStream_t)stream);
+}
+
 /* ------------------------------------------------------------------------ */
 /* fastest timescale (workload set-up)                                       */
 /* ------------------------------------------------------------------------ */
@@ -815,6 +945,8 @@ struct kr_multi {
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
+  hipFunction_t f_keys[KR_MAX_NETS] = {}, f_scan = nullptr, f_scatter = nullptr;
+  OrderBufs ord[KR_MAX_NETS];
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
   unsigned long long *d_counters = nullptr; /* one per network */
   hipStream_t capture = nullptr;
@@ -826,7 +958,7 @@ struct kr_multi {
 
 static std::string multi_source(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
   std::string s = "/* per-cell implicit thermochemistry: several networks in one launch */\n" +
-                  build_prefix(o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n";
+                  build_prefix(o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
     if (nets[k]->wide)
       s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_wide(nets[k]) + "\n" + kWideSource +
@@ -852,6 +984,10 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
            ">(m.net[" + std::to_string(k) + "]); break;\n";
     s += "      default: break;\n    }\n  }\n}\n";
   }
+  for (size_t k = 0; k < nets.size(); ++k)
+    s += "extern \"C\" __global__ void __launch_bounds__(64, 1) kr_order_keys_m" + std::to_string(k) +
+         "(KrParams p, unsigned char *bucket, unsigned *hist) {\n  kr_m" + std::to_string(k) +
+         (nets[k]->wide ? "::kr_worder_keys" : "::kr_order_keys_body") + "(p, bucket, hist);\n}\n";
   s += "extern \"C\" __global__ void kr_reset_counters(unsigned long long *c, int n) {\n"
        "  if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = 0ull;\n}\n";
   return s;
@@ -863,6 +999,7 @@ static void release_multi(kr_multi *m) {
   if (m->graph) (void)hipGraphDestroy(m->graph);
   if (m->capture) (void)hipStreamDestroy(m->capture);
   if (m->d_counters) (void)hipFree(m->d_counters);
+  for (int k = 0; k < KR_MAX_NETS; ++k) order_free(m->ord[k]);
   if (m->module) (void)hipModuleUnload(m->module);
   delete m;
 }
@@ -905,6 +1042,10 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   MULTI_TRY(hipModuleGetFunction(&m->f_fp64, m->module, "kr_integrate_multi_fp64"));
   MULTI_TRY(hipModuleGetFunction(&m->f_fp32, m->module, "kr_integrate_multi_fp32lu"));
   MULTI_TRY(hipModuleGetFunction(&m->f_reset, m->module, "kr_reset_counters"));
+  MULTI_TRY(hipModuleGetFunction(&m->f_scan, m->module, "kr_order_scan"));
+  MULTI_TRY(hipModuleGetFunction(&m->f_scatter, m->module, "kr_order_scatter"));
+  for (int k = 0; k < n_nets; ++k)
+    MULTI_TRY(hipModuleGetFunction(&m->f_keys[k], m->module, ("kr_order_keys_m" + std::to_string(k)).c_str()));
   MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64, m->f_fp64, 64, 0));
   MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32, m->f_fp32, 64, 0));
   MULTI_TRY(hipMalloc(&m->d_counters, sizeof(unsigned long long) * KR_MAX_NETS));
@@ -972,7 +1113,7 @@ static int validate_options(const kr_options &o) {
   if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
       (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
       o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
-      !(o.rho_floor >= 0.0))
+      !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
     return fail(KR_EINVAL, "bad options");
   return KR_OK;
 }
@@ -1005,18 +1146,39 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
     need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
+  /* largest-work-first order of each batch: buffers reserved here, outside
+   * any capture; the order kernels run on the launch stream ahead of the
+   * counter reset (and are part of the captured graph) */
+  bool ordered[KR_MAX_NETS] = {};
+  for (int k = 0; k < h.n_nets; ++k) {
+    if (!want_order(o, batches[k].n_cells)) continue;
+    if ((rc = order_reserve(m->ord[k], batches[k].n_cells))) return rc;
+    ordered[k] = true;
+    h.net[k].order = m->ord[k].order;
+  }
+  auto launch_orders = [&](hipStream_t s) -> int {
+    for (int k = 0; k < h.n_nets; ++k) {
+      if (!ordered[k]) continue;
+      KrParams pk = h.net[k];
+      int r = order_launch(m->f_keys[k], m->f_scan, m->f_scatter, m->ord[k], m->nets[k]->wide, m->cu_count, pk, s);
+      if (r != KR_OK) return r;
+    }
+    return KR_OK;
+  };
   unsigned long long *cnt = m->d_counters;
   int nn = h.n_nets;
   void *rargs[] = {&cnt, &nn};
   void *args[] = {&h};
   if (!use_graph) {
+    if ((rc = launch_orders(st))) return rc;
     HIP_TRY(hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
     HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
     return KR_OK;
   }
-  /* graph of [reset the work counters] -> [persistent integrate], captured
-   * once per distinct launch configuration and replayed on the caller's
-   * stream (the counters are cleared by a kernel, not a memset node) */
+  /* graph of [order kernels] -> [reset the work counters] -> [persistent
+   * integrate], captured once per distinct launch configuration and replayed
+   * on the caller's stream (counters and histograms are cleared by kernels,
+   * not memset nodes) */
   std::vector<char> key(sizeof h + sizeof blocks + sizeof f);
   std::memcpy(key.data(), &h, sizeof h);
   std::memcpy(key.data() + sizeof h, &blocks, sizeof blocks);
@@ -1025,14 +1187,15 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
     if (m->exec) { (void)hipGraphExecDestroy(m->exec); m->exec = nullptr; }
     if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
     HIP_TRY(hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal));
+    const int r0 = launch_orders(m->capture);
     hipError_t e1 = hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, m->capture, rargs, nullptr);
     hipError_t e2 = hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, m->capture, args, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e3 = hipStreamEndCapture(m->capture, &g);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    if (r0 != KR_OK || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return fail(KR_EDEVICE, "graph capture failed: %s / %s / %s", hipGetErrorString(e1),
-                  hipGetErrorString(e2), hipGetErrorString(e3));
+      return fail(r0 != KR_OK ? r0 : KR_EDEVICE, "graph capture failed: order %d / %s / %s / %s", r0,
+                  hipGetErrorString(e1), hipGetErrorString(e2), hipGetErrorString(e3));
     }
     m->graph = g;
     HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));

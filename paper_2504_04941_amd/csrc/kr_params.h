@@ -27,8 +27,9 @@ struct KrParams {
   unsigned long long *counter; /* next unclaimed cell */
   const double *guess;   /* [S+1][guess_ld] first-substep Newton guess, or null */
   long long guess_ld;
-  unsigned long long *counters; /* [4] guess starts, guess fallbacks, row
-                                   exchanges, reserved; or null */
+  unsigned long long *counters; /* [8] statistics (see kr_options), or null */
+  const unsigned *order;  /* [n_cells] cell handed out at each claim, or null
+                             for the input order */
 };
 
 #endif

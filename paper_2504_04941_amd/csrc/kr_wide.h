@@ -11,7 +11,8 @@
  *  - vectors of the cell (iterate y, substep start y_n, rates g_n, weights)
  *    are spread over the lanes: lane i holds entry i;
  *  - rates: lane l evaluates reaction directions l, l+64, ...: the rate
- *    coefficient k = A exp(b ln T - E/T), the rate of progress q = k prod n,
+ *    coefficient k = A T^b exp(-E/T) (as a base-2 exponential, kr_math.h),
+ *    the rate of progress q = k prod n,
  *    dq/dT and dq/dn per reactant slot, into an LDS table P;
  *  - the rate Jacobian is gathered into LDS (rows = species; columns =
  *    species, T and the rate f itself) from per-lane contribution lists that
@@ -37,7 +38,7 @@
  *   KR_S, KR_NROWS, KR_NELEM, KR_LDJ (LDS row stride of the Jacobian),
  *   KR_NDR (direction rounds of 64), KR_NC / KR_NF (contribution list lengths)
  *   kr_comp, kr_res, kr_cv, kr_atoms, kr_hf, kr_T_min, kr_T_max
- *   kr_dA, kr_db, kr_dE [KR_NDR * 64]   direction Arrhenius parameters
+ *   kr_da2, kr_db, kr_dE [KR_NDR * 64]  direction Arrhenius parameters (log2 A, b, E)
  *   kr_dr [KR_NDR * 64]                 reactant slots, 8 bits each (255 none)
  *   kr_wc [KR_NC * 64], kr_wf [KR_NF * 64]  contribution lists (lane-interleaved):
  *       bits 0-11 source in P, 12-24 destination in the Jacobian,
@@ -150,23 +151,25 @@ template <bool FULL>
 __device__ __forceinline__ void kr_wdirections(KrWave &w) {
   const int lane = threadIdx.x;
   const double T = w.y[KR_S];
-  const double lnT = log(T);
+  const double l2T = kr_log2(T);
   const double iT = 1.0 / T;
 #pragma unroll
   for (int j = 0; j < KR_NDR; ++j) {
     const int d = lane + 64 * j;
-    const double A = kr_dA[d], b = kr_db[d], E = kr_dE[d];
+    const double a2 = kr_da2[d], b = kr_db[d], E = kr_dE[d];
     const unsigned rr = kr_dr[d];
     const unsigned r0 = rr & 255u, r1 = (rr >> 8) & 255u, r2 = (rr >> 16) & 255u;
     const double n0 = r0 < 255u ? w.y[r0] : 1.0;
     const double n1 = r1 < 255u ? w.y[r1] : 1.0;
     const double n2 = r2 < 255u ? w.y[r2] : 1.0;
-    const double k = A * exp(b * lnT - E * iT);
+    /* k = A T^b exp(-E/T) = 2^(log2 A + b log2 T - E log2(e) / T) */
+    const double eiT = E * iT;
+    const double k = kr_exp2(fma(-eiT, 0x1.71547652b82fep+0, fma(b, l2T, a2)));
     const double q = k * n0 * n1 * n2;
     double *P = w.P + 5 * d;
     P[0] = q;
     if (FULL) {
-      P[1] = q * (b + E * iT) * iT;
+      P[1] = q * (b + eiT) * iT;
       P[2] = k * n1 * n2;
       P[3] = k * n0 * n2;
       P[4] = k * n0 * n1;
@@ -732,7 +735,12 @@ __device__ __forceinline__ void kr_wintegrate(const KrParams &p) {
     const unsigned hi = (unsigned)kr_ui((int)(unsigned)(c0 >> 32));
     const unsigned long long c = ((unsigned long long)hi << 32) | lo;
     if (c >= n) break;
-    kr_wcell<MIXED>(p, w, (long long)c);
+    long long cell = (long long)c;
+    if (p.order) {   /* range guard on the ordered index; always true */
+      const long long o = (long long)(unsigned)kr_ui((int)p.order[c]);
+      cell = o < p.n_cells ? o : cell;
+    }
+    kr_wcell<MIXED>(p, w, cell);
   }
 }
 
@@ -762,6 +770,37 @@ __device__ __forceinline__ void kr_wtimescale(const KrParams &p, double *out) {
   }
 }
 
+/* Expected-work bucket of each cell (kr_order.h), one cell per wave:
+ * w = dt (sum_s |f_s| / sum_s n_s + |Q| / eps) at the input state. */
+__device__ __forceinline__ void kr_worder_keys(const KrParams &p, unsigned char *bucket, unsigned *hist) {
+  __shared__ KrWave w;
+  const int lane = threadIdx.x;
+#pragma unroll 1
+  for (int k = 0; k < (KR_N * KR_LDJ + 63) / 64; ++k) {
+    const int i = 64 * k + lane;
+    if (i < KR_N * KR_LDJ) w.J[i] = 0.0;
+  }
+  __syncthreads();
+  for (long long c = blockIdx.x; c < p.n_cells; c += gridDim.x) {
+    double dt;
+    bool bad;
+    const double y = kr_wload(p, c, dt, bad);
+    unsigned b = 0u;
+    if (!kr_uany(bad) && dt > 0.0) {
+      kr_wrhs(w, y);
+      const double eps = kr_bcast(y, KR_S) * kr_u(kr_wheatcap(y));
+      const double sf = kr_u(kr_wsum(lane < KR_S ? fabs(w.J[lane * KR_LDJ + KR_S + 1]) : 0.0));
+      const double sn = kr_u(kr_wsum(lane < KR_S ? y : 0.0));
+      const double Q = w.J[KR_S * KR_LDJ + KR_S + 1];
+      b = kr_work_bucket(dt * (sf / sn + fabs(Q) / eps));
+    }
+    b = (unsigned)kr_ui((int)b);
+    bucket[c] = (unsigned char)b;
+    atomicAdd(&hist[b], lane == 0 ? 1u : 0u);
+    __syncthreads();
+  }
+}
+
 #ifndef KR_WAVES_PER_EU
 #define KR_WAVES_PER_EU 1
 #endif
@@ -781,5 +820,10 @@ extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_f
 
 extern "C" __global__ void kr_reset_counter(unsigned long long *c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = 0ull;
+}
+
+extern "C" __global__ void __launch_bounds__(64, 1) kr_order_keys(KrParams p, unsigned char *bucket,
+                                                                  unsigned *hist) {
+  kr_worder_keys(p, bucket, hist);
 }
 #endif /* KR_NO_KERNELS */

@@ -88,8 +88,12 @@ def test_derived_reverse_parameters_match_oracle(oracle_lib):
     desc = sy.network_h_o_n(1)
     src = kr.network_check(desc)
     par = oracle_lib.OracleNet(desc).arrhenius()
-    lits = re.findall(r"const double kr = (\S+) \* exp\((\S+) \* lnT - (\S+) \* iT\)", src)
+    # k = 2^(log2 A + b log2 T - C log2(e) / T): literals -C log2(e), b, log2 A
+    lits = re.findall(r"const double kr = kr_exp2\(fma\((\S+), iT, fma\((\S+), l2T, (\S+)\)\)\);", src)
     assert len(lits) == desc.n_reactions
-    for r, (A, b, E) in enumerate(lits):
-        got = np.array([float.fromhex(A), float.fromhex(b), float.fromhex(E)])
-        np.testing.assert_allclose(got, par[r, 1], rtol=1e-15)
+    for r, (mc2, b, a2) in enumerate(lits):
+        # log2 A is rounded once: A carries ~|log2 A| ulp of relative error
+        a2 = float.fromhex(a2)
+        assert abs(2.0 ** a2 / par[r, 1, 0] - 1.0) <= 2.5e-16 * (abs(a2) + 1.0)
+        assert float.fromhex(b) == par[r, 1, 1]
+        np.testing.assert_allclose(-float.fromhex(mc2) / np.log2(np.e), par[r, 1, 2], rtol=1e-15)

@@ -24,7 +24,7 @@ def _tables(src):
         return [conv(x) for x in m.group(2).split(",")]
     defs = {k: int(v) for k, v in re.findall(r"#define KR_(S|LDJ|NDR|NC|NF) (\d+)", src)}
     u = lambda x: int(x.rstrip("u"))
-    return defs, {n: arr(n, u) for n in ("dr", "wc", "wf")}, {n: arr(n, float.fromhex) for n in ("dA", "db", "dE")}
+    return defs, {n: arr(n, u) for n in ("dr", "wc", "wf")}, {n: arr(n, float.fromhex) for n in ("da2", "db", "dE")}
 
 
 def _expected(desc, par, S, LDJ):
@@ -90,12 +90,15 @@ def test_contribution_lists_rebuild_the_jacobian_terms(oracle_lib, make):
     # lists are balanced: no lane longer than the largest entry or the mean
     terms = sum(len(v) for v in full.values())
     assert defs["NC"] <= max(max(len(v) for v in full.values()), -(-terms // 64) + 8)
-    # direction tables: derived (A, b, E) and reactant slots, padding inert
+    # direction tables: derived (log2 A, b, E) and reactant slots, padding
+    # inert (log2 A = -4096, i.e. k = 0)
     for i, (r, d, re_, _) in enumerate(dirs):
-        np.testing.assert_allclose([dt["dA"][i], dt["db"][i], dt["dE"][i]], par[r, d], rtol=1e-15)
+        a2 = dt["da2"][i]
+        assert abs(2.0 ** a2 / par[r, d, 0] - 1.0) <= 2.5e-16 * (abs(a2) + 1.0)
+        np.testing.assert_allclose([dt["db"][i], dt["dE"][i]], par[r, d, 1:], rtol=1e-15)
         slots = [(ut["dr"][i] >> (8 * k)) & 255 for k in range(3)]
         assert slots == [m if m >= 0 else 255 for m in re_]
-    assert all(a == 0.0 for a in dt["dA"][len(dirs):])
+    assert all(a == -4096.0 for a in dt["da2"][len(dirs):])
 
 
 def test_wave_layout_compiles_for_gfx950():
