@@ -165,7 +165,11 @@ def run_mixed(args):
     nets = [kr.Network(d, kr.build_options(waves_per_eu=bo.waves_per_eu, pivot_tau=bo.pivot_tau, layout=L))
             for d, L in zip(descs, layouts)]
     multi = kr.Multi(nets, bo)
-    opts = kr.default_options(precision=kr.KR_FP32LU_REFINE)
+    order = _order(args)
+    if report is not None and args.order == _ORDER_DEFAULT["mixed"]:
+        order = report["order"]          # the tuner's choice unless --order was given
+        args.order = "work" if order == kr.KR_ORDER_WORK else "input"
+    opts = kr.default_options(precision=kr.KR_FP32LU_REFINE, order=order)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -208,7 +212,7 @@ def run_mixed(args):
            "config": {"workload": f"mixed: {args.cells} cells, 5/9/23-species networks 50/30/20%, "
                                   f"dt = tau_fast*10^U[range] per network {list(MIX_U_RANGES)}, FP32 LU + "
                                   "FP64 refinement, one persistent hipGraph launch",
-                      "build": [bo.waves_per_eu, bo.pivot_tau],
+                      "build": [bo.waves_per_eu, bo.pivot_tau], "cell_order": args.order,
                       "layouts": ["wave" if n.wide else "lane" for n in nets]},
            "per_network": per_net, "graph": {"launches": launches, "captures": captures},
            "autotune": report, "setup_s": setup_s,
@@ -246,7 +250,7 @@ def run_large(args):
         prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE}.get(variant)
         if prec is None:
             continue
-        opts = kr.default_options(precision=prec)
+        opts = kr.default_options(precision=prec, order=_order(args))
         opts.counters = counters.data_ptr()
 
         def step():
@@ -294,7 +298,7 @@ def run_large(args):
            "config": {"workload": f"large_48sp: {args.cells} cells, 48 species / 200 reversible reactions / "
                                   "5 element rows + energy (49x49 LU), dt log-uniform [1e-8, 1e-2] s, rtol 1e-6, "
                                   "one cell per wavefront",
-                      "layout": "wave" if net.wide else "lane"},
+                      "layout": "wave" if net.wide else "lane", "cell_order": args.order},
            "variants": results, "setup_s": setup_s,
            "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
                         "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64, "traffic": None,
@@ -345,6 +349,20 @@ def calibrate_mixed(args):
     print(json.dumps({"calibration": out, "cells_per_network": n_cells}), flush=True)
 
 
+# cell order per workload (measured on MI355X): largest expected work first
+# for the long, uneven cells of the combustion and 48-species batches; input
+# order (coalesced state accesses, no extra rate evaluation) for the mixed
+# batch, whose cells mostly take one substep
+_ORDER_DEFAULT = {"h_o_n": "work", "large48": "work", "mixed": "input", "calibrate": "input"}
+
+
+def _order(args):
+    import paper_2504_04941_amd as kr
+    if args.order == "default":
+        args.order = _ORDER_DEFAULT[args.workload]
+    return kr.KR_ORDER_WORK if args.order == "work" else kr.KR_ORDER_INPUT
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +376,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", default="default", choices=["default", "work", "input"],
+                    help="order in which the persistent kernel hands out cells: largest expected "
+                         "work first or input order (default: the faster one for the workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the per-cell integration needs no communication, "
@@ -435,8 +456,8 @@ def main():
         prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE,
                 "fp32lu+mlp": kr.KR_FP32LU_REFINE, "fp64+mlp": kr.KR_FP64}[variant]
         use_guess = "mlp" in variant
-        opts = (kr.guess_options(guess, precision=prec) if use_guess
-                else kr.default_options(precision=prec))
+        opts = (kr.guess_options(guess, precision=prec, order=_order(args)) if use_guess
+                else kr.default_options(precision=prec, order=_order(args)))
         opts.counters = counters.data_ptr()
 
         def step():
@@ -499,7 +520,7 @@ def main():
         "config": {"workload": "h_o_n 9-species/24-reaction network + energy (10x10 LU), "
                                f"{args.cells} cells, T~U[900,2500] K, 1 atm, dt=1e-4 s adaptive BE, rtol 1e-6",
                    "cells": args.cells, "unknowns": desc.n_unknowns, "reactions": desc.n_reactions,
-                   "variant": "fp64" if "fp64" in results else args.variants},
+                   "variant": "fp64" if "fp64" in results else args.variants, "cell_order": args.order},
         "variants": results,
         "learned_guess": learned_info,
         "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,

@@ -180,9 +180,14 @@ enum { KR_ADAPTIVE = 0, KR_FIXED_STEP = 1 }; /* substep control */
  * an estimate of their work, largest first, so that long cells do not start
  * last and leave the rest of their wavefront (and the GPU) idle: the
  * estimate is dt (sum_s |f_s| / sum_s n_s + |Q| / eps) at the input state,
- * bucketed in half-octaves (three extra kernels on the stream; the first
- * call with a larger batch than before allocates n_cells * 5 bytes and
- * synchronises the device). */
+ * bucketed in half-octaves (three extra kernels on the stream, one rate
+ * evaluation per cell; the first call with a larger batch than before
+ * allocates n_cells * 5 bytes and synchronises the device).  It pays for
+ * batches of long, uneven cells (10 % faster on 2^20 combustion cells of
+ * ~1e4 Newton iterations each) and costs more than it saves on cheap ones
+ * (one substep per cell: the extra evaluation and the scattered, no longer
+ * coalesced state accesses make the launch up to 7x slower), hence the
+ * default KR_ORDER_INPUT; the autotuner measures both. */
 enum { KR_ORDER_INPUT = 0, KR_ORDER_WORK = 1 };
 
 typedef struct {
@@ -193,7 +198,7 @@ typedef struct {
   int32_t n_fixed;      /* substeps per cell in KR_FIXED_STEP (>= 1) */
   int32_t max_newton;   /* Newton iterations per substep (default 10) */
   int32_t max_substeps; /* substep attempts per cell and attempt (100000) */
-  int32_t order;        /* KR_ORDER_WORK (default) or KR_ORDER_INPUT */
+  int32_t order;        /* KR_ORDER_INPUT (default) or KR_ORDER_WORK */
   double floor;         /* absolute tolerance as a fraction of the nuclei
                            density (default 1e-20) */
   double newton_tol;    /* weighted max-norm bound on the Newton update

@@ -6,7 +6,10 @@ lane); for the module, the occupancy target the register allocator budgets
 for (waves per SIMD; the lane's Newton matrix lives in VGPRs, so a higher
 target trades registers for scratch spills) and the threshold of the LU's
 partial pivoting (a smaller threshold takes fewer row exchanges, which
-execute wave-wide when any lane needs one).  Each candidate
+execute wave-wide when any lane needs one).  Run-time tunable
+(`kr_options.order`): the order in which cells are handed out (input order,
+or largest expected work first, which pays for long uneven cells and costs
+more than it saves on cheap ones).  Each candidate
 is compiled, run on a sample of the caller's own cells (fresh copies per
 timing) and timed with HIP events on the launch stream; the fastest wins.
 Choices are cached in a JSON file keyed by the generated source (which
@@ -22,8 +25,8 @@ import json
 import os
 import time
 
-from . import (KR_LAYOUT_LANE, KR_LAYOUT_WAVE, BuildOpts, Multi, Network, build_options, chem_integrate,
-               default_options, multi_check, network_check)
+from . import (KR_LAYOUT_LANE, KR_LAYOUT_WAVE, KR_ORDER_INPUT, KR_ORDER_WORK, BuildOpts, Multi, Network,
+               build_options, chem_integrate, default_options, multi_check, network_check)
 
 CACHE = os.environ.get("KR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "kr_autotune.json"))
@@ -115,10 +118,40 @@ def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log
     return best, report
 
 
+def tune_order(net, batch, precision=0, rtol=1e-6, reps=2, log=None):
+    """Faster cell order (KR_ORDER_INPUT or KR_ORDER_WORK) for one network's
+    batch (dict as for Multi.integrate, copied before every timed run).
+    Not cached: the answer depends on the cells, not only on the network.
+    Returns (order, report)."""
+    import torch
+    report = {"candidates": [], "cells": int(batch["T"].numel())}
+    best, best_t = None, float("inf")
+    for order in (KR_ORDER_INPUT, KR_ORDER_WORK):
+        opts = default_options(precision=precision, order=order)
+
+        def run(prep):
+            if prep is None:
+                return {k: (v.clone() if torch.is_tensor(v) else v) for k, v in batch.items()}
+            chem_integrate(net, prep["states"], prep["T"], rho=prep.get("rho"), dt=prep.get("dt"),
+                           dt_scalar=prep.get("dt_scalar", 0.0), rtol=rtol, opts=opts,
+                           status=prep.get("status"), cell_stats=prep.get("cell_stats"))
+            return None
+
+        ms = _time_call(run, reps)
+        report["candidates"].append({"order": order, "ms": ms})
+        if log:
+            log(f"autotune order={'work' if order == KR_ORDER_WORK else 'input'}: {ms:.2f} ms")
+        if ms < best_t:
+            best, best_t = order, ms
+    report["best"] = best
+    return best, report
+
+
 def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, reps=2,
                use_cache=True, log=None):
-    """Best layout per network (tune_layout on its own sample) and best
-    module build options for the networks integrated together.
+    """Best layout per network (tune_layout on its own sample), best module
+    build options for the networks integrated together and, with those, the
+    faster cell order (report["order"]).
 
     batches: list of dicts as for Multi.integrate (a sample of the cells;
     they are copied before every timed run and left untouched).  Returns
@@ -132,14 +165,13 @@ def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, re
     key = _key([multi_check(descs)] + [str(layouts)] + [str(int(b["T"].numel()).bit_length()) for b in batches],
                precision)
     db = _load() if use_cache else {}
-    if key in db:
+    if key in db and "order" in db[key]:
         w, tau = db[key]["best"]
         return build_options(waves_per_eu=int(w), pivot_tau=float(tau)), layouts, db[key]
     nets_cache = {}
     report = {"candidates": [], "sample_cells": [int(b["T"].numel()) for b in batches],
               "layouts": ["lane" if L == KR_LAYOUT_LANE else "wave" for L in layouts],
               "layout_timings": lay_reports}
-    opts = default_options(precision=precision)
     best, best_t = None, float("inf")
     for w, tau in candidates:
         bo = build_options(waves_per_eu=w, pivot_tau=tau)
@@ -149,25 +181,30 @@ def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, re
         multi = Multi(nets, bo)
         compile_s = time.time() - t0
 
-        def run(prep):
-            if prep is None:
-                return [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in b.items()}
-                        for b in batches]
-            multi.integrate(prep, rtol=rtol, opts=opts)
-            return None
+        for order in (KR_ORDER_INPUT, KR_ORDER_WORK):
+            opts = default_options(precision=precision, order=order)
 
-        ms = _time_call(run, reps)
-        report["candidates"].append({"waves_per_eu": w, "pivot_tau": tau, "ms": ms,
-                                     "compile_s": compile_s})
-        if log:
-            log(f"autotune waves_per_eu={w} pivot_tau={tau}: {ms:.1f} ms (compile {compile_s:.1f} s)")
-        if ms < best_t:
-            best, best_t = (w, tau), ms
+            def run(prep):
+                if prep is None:
+                    return [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in b.items()}
+                            for b in batches]
+                multi.integrate(prep, rtol=rtol, opts=opts)
+                return None
+
+            ms = _time_call(run, reps)
+            report["candidates"].append({"waves_per_eu": w, "pivot_tau": tau, "order": order, "ms": ms,
+                                         "compile_s": compile_s})
+            if log:
+                log(f"autotune waves_per_eu={w} pivot_tau={tau} order={'work' if order else 'input'}: "
+                    f"{ms:.1f} ms (compile {compile_s:.1f} s)")
+            if ms < best_t:
+                best, best_t = (w, tau, order), ms
         multi.close()
         for n in nets:
             n.close()
         nets_cache.clear()
-    report["best"] = list(best)
+    report["best"] = list(best[:2])
+    report["order"] = best[2]
     if use_cache:
         db = _load()
         db[key] = report

@@ -99,16 +99,21 @@ __device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)
   }
 #pragma unroll
   for (int j = 0; j < KR_N; ++j) {
+    /* largest scaled candidate below the diagonal; its row index is only
+     * needed when some lane of the wave exchanges rows */
     float best = 0.0f;
-    int bi = j;
 #pragma unroll
-    for (int i = j + 1; i < KR_N; ++i) {
-      float t = (float)fabs(a[i][j]) * sc[i];
-      if (t > best) { best = t; bi = i; }
-    }
+    for (int i = j + 1; i < KR_N; ++i) best = fmaxf(best, (float)fabs(a[i][j]) * sc[i]);
     bool need = (float)fabs(a[j][j]) * sc[j] < (float)KR_PIVOT_TAU * best;
     unsigned long long mask = __ballot(need);
     if (mask) {
+      int bi = j;
+      float bb = 0.0f;
+#pragma unroll
+      for (int i = j + 1; i < KR_N; ++i) {
+        float t = (float)fabs(a[i][j]) * sc[i];
+        if (t > bb) { bb = t; bi = i; }
+      }
       if (swap_count && __lane_id() == (int)__builtin_ctzll(__ballot(1)))
         atomicAdd(swap_count, (unsigned long long)__popcll(mask));
 #pragma unroll

@@ -739,7 +739,7 @@ extern "C" void kr_default_options(kr_options *o) {
   o->n_fixed = 1;
   o->max_newton = 10;
   o->max_substeps = 100000;
-  o->order = KR_ORDER_WORK;
+  o->order = KR_ORDER_INPUT;
   o->floor = 1e-20;
   o->newton_tol = 1e-3;
   o->rho_floor = 0.0;

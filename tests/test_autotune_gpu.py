@@ -34,10 +34,11 @@ def test_tune_layout_and_multi(oracle_lib):
     bo, layouts, report = autotune.tune_multi(descs, [_batch(c, d) for c, d in zip(css, dts)],
                                               candidates=[(1, 0.1)], use_cache=False)
     assert len(layouts) == 2 and report["best"] == [1, 0.1]
+    assert report["order"] in (kr.KR_ORDER_INPUT, kr.KR_ORDER_WORK) and len(report["candidates"]) == 2
     nets = [kr.Network(d, kr.build_options(layout=L)) for d, L in zip(descs, layouts)]
     multi = kr.Multi(nets, bo)
     bufs = [_batch(c, d) for c, d in zip(css, dts)]
-    multi.integrate(bufs, rtol=1e-6)
+    multi.integrate(bufs, rtol=1e-6, opts=kr.default_options(order=report["order"]))
     torch.cuda.synchronize()
     for d, cs, dt, b in zip(descs, css, dts, bufs):
         orc = oracle_lib.OracleNet(d).integrate(cs.n, cs.T, dt=dt)
@@ -47,3 +48,17 @@ def test_tune_layout_and_multi(oracle_lib):
     multi.close()
     for n in nets:
         n.close()
+
+
+def test_tune_order():
+    import paper_2504_04941_amd as kr
+    from paper_2504_04941_amd import autotune
+    desc = sy.network_h_o_n(1)
+    cs = sy.cells_h_o_n(desc, 700, 1)
+    net = kr.Network(desc)
+    batch = _batch(cs, np.full(700, 1e-6))
+    order, rep = autotune.tune_order(net, batch)
+    assert order in (kr.KR_ORDER_INPUT, kr.KR_ORDER_WORK)
+    assert [c["order"] for c in rep["candidates"]] == [kr.KR_ORDER_INPUT, kr.KR_ORDER_WORK]
+    assert all(c["ms"] > 0 for c in rep["candidates"])
+    net.close()

@@ -1,4 +1,4 @@
-"""Largest-expected-work-first cell order (KR_ORDER_WORK, the default): the
+"""Largest-expected-work-first cell order (KR_ORDER_WORK): the
 order the library computes is a permutation of the batch sorted by the work
 estimate dt (sum_s |f_s| / sum_s n_s + |Q| / eps), which the oracle's rate
 function evaluates independently; and integrating in that order gives
