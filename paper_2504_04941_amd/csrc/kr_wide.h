@@ -23,8 +23,10 @@
  *    (heat release q_r = -sum_s nu_rs h_s), as one column sum per lane;
  *  - LU: lane i holds row i of the Newton matrix in registers; column j is
  *    eliminated by a wave-wide arg-max over the remaining rows (implicit row
- *    scaling as in the paper's Algorithm 1), a broadcast of the pivot row
- *    through LDS and one FMA per remaining entry.  Rows are never moved:
+ *    scaling as in the paper's Algorithm 1), the pivot row's entries read
+ *    straight from the pivot lane's registers (readlane into scalar
+ *    registers, no LDS round trip or barrier) and one FMA per remaining
+ *    entry.  Rows are never moved:
  *    each lane records the column at which its row became pivot row, and the
  *    triangular solves walk the pivot order (found by a ballot per column).
  *
@@ -251,7 +253,28 @@ __device__ __forceinline__ double kr_wrate(const KrWave &w, double cv) {
  * the reciprocal pivot.  Returns false (wave-uniform) for a singular or
  * non-finite matrix. */
 template <typename F>
-__device__ __forceinline__ bool kr_wlu(KrWave &w, F (&a)[KR_N], int &pc, F &dinv) {
+__device__ __forceinline__ F kr_wbc(F v, int src) {
+  if constexpr (sizeof(F) == 8) return kr_bcast(v, src);
+  else return kr_bcastf(v, src);
+}
+
+/* 1/x: for FP64 the hardware estimate (relative error ~2^-24) refined by
+ * two Newton steps, within an ulp or so of the quotient */
+template <typename F>
+__device__ __forceinline__ F kr_wrcp(F x) {
+  if constexpr (sizeof(F) == 8) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  } else {
+    return F(1) / x;
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
   const int lane = threadIdx.x;
   F mx = F(0);
 #pragma unroll
@@ -268,25 +291,15 @@ __device__ __forceinline__ bool kr_wlu(KrWave &w, F (&a)[KR_N], int &pc, F &dinv
     /* fabs: a -0 candidate would carry the sign bit into the key */
     const int p = kr_wargmax(fabsf((float)(fabs((double)aj) * (double)sc)), cand, best);
     ok = ok && (best >> 6) != 0u;
-    F piv;
-    if constexpr (sizeof(F) == 8) piv = kr_bcast(aj, p);
-    else piv = kr_bcastf(aj, p);
+    const F piv = kr_wbc(aj, p);
     ok = ok && piv != F(0) && kr_finite((double)piv);
-    const F inv = F(1) / piv;
-    if (j + 1 < KR_N) {
-      /* the pivot row's remaining entries, broadcast through LDS */
-      if (lane == p) {
-#pragma unroll
-        for (int k = j + 1; k < KR_N; ++k) w.v[k] = (double)a[k];
-      }
-      __syncthreads();
-    }
+    const F inv = kr_wrcp(piv);
     if (lane == p) { pc = j; dinv = inv; }
     const F l = pc == KR_NOTPIV ? aj * inv : F(0);
     if (pc == KR_NOTPIV) a[j] = l;
+    /* the pivot row's remaining entries, read from lane p's registers */
 #pragma unroll
-    for (int k = j + 1; k < KR_N; ++k) a[k] = fma(-l, (F)w.v[k], a[k]);
-    __syncthreads();
+    for (int k = j + 1; k < KR_N; ++k) a[k] = fma(-l, kr_wbc(a[k], p), a[k]);
   }
   return ok;
 }
@@ -422,7 +435,7 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
     if (!MIXED) {
       int pc;
       double dinv;
-      ok = kr_wlu(w, a, pc, dinv);
+      ok = kr_wlu(a, pc, dinv);
       if (ok) d = kr_wsolve(a, pc, dinv, b);
     } else {
       /* FP32 LU of the row-equilibrated matrix; FP64 residual and iterative
@@ -437,7 +450,7 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
       for (int k = 0; k < KR_N; ++k) a32[k] = (float)(a[k] * rs);
       int pc;
       float dinv;
-      bool ok32 = kr_wlu(w, a32, pc, dinv);
+      bool ok32 = kr_wlu(a32, pc, dinv);
       double r = b;
       bool conv = false;
       int sweeps = 0;
@@ -464,7 +477,7 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
         if (p.counters) atomicAdd(&p.counters[4], lane == 0 ? 1ull : 0ull);
         int pc64;
         double dinv64;
-        ok = kr_wlu(w, a, pc64, dinv64);
+        ok = kr_wlu(a, pc64, dinv64);
         d = ok ? kr_wsolve(a, pc64, dinv64, b) : 0.0;
       }
       if (ok) d = kr_wproject(y, C.atol, d);
