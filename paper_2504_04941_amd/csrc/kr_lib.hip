@@ -286,6 +286,7 @@ static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pai
   }
   len = 1;
   for (const auto &l : lanes) len = std::max(len, (int)l.size());
+  len = (len + 7) / 8 * 8;   /* the gather fetches entries eight at a time */
   std::vector<uint32_t> tab((size_t)len * 64, 4u << 25);
   for (int l = 0; l < 64; ++l)
     for (size_t i = 0; i < lanes[l].size(); ++i) tab[i * 64 + l] = lanes[l][i];

@@ -54,8 +54,9 @@ struct KrWave {
   double y[64];                 /* broadcast copy of the current point */
   double v[64];                 /* scratch vector */
   double P[5 * KR_NDP];         /* per direction: q, dq/dT, dq/dn (3 slots) */
-  double J[KR_N * KR_LDJ];      /* rows 0..S-1 species (cols 0..S-1 d/dn, S d/dT,
-                                   S+1 f), row S energy (dQ/dn, dQ/dT, Q) */
+  double J[KR_N * KR_LDJ + 64]; /* rows 0..S-1 species (cols 0..S-1 d/dn, S d/dT,
+                                   S+1 f), row S energy (dQ/dn, dQ/dT, Q); then
+                                   one spare slot per lane (kr_wgather) */
 };
 
 __device__ __forceinline__ bool kr_finite(double x) { return __builtin_isfinite(x); }
@@ -180,20 +181,41 @@ __device__ __forceinline__ void kr_wdirections(KrWave &w) {
   __syncthreads();
 }
 
-/* Runs one lane's contribution list into the Jacobian workspace. */
+/* Runs one lane's contribution list into the Jacobian workspace.  The
+ * list entries are fetched eight at a time, the next eight while the
+ * current ones are accumulated (the table is read from L2: a fetch per
+ * entry, waited for at once, left the loop bound by load latency); an entry
+ * that ends a destination's group stores the sum (entries that do not store
+ * into the lane's spare slot past the matrix, so the loop has no
+ * branches). */
 template <int LEN>
 __device__ __forceinline__ void kr_wgather(KrWave &w, const unsigned *tab) {
+  static_assert(LEN % 8 == 0, "contribution lists are padded to a multiple of 8");
   const int lane = threadIdx.x;
   double acc = 0.0;
-#pragma unroll 4
-  for (int i = 0; i < LEN; ++i) {
-    const unsigned e = tab[i * 64 + lane];
-    const double nu = (double)((int)((e >> 25) & 7u) - 4);
-    acc = fma(nu, w.P[e & 4095u], acc);
-    if (e >> 28) {
-      w.J[(e >> 12) & 8191u] = acc;
-      acc = 0.0;
+  unsigned e[8], f[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) e[u] = tab[u * 64 + lane];
+#pragma unroll 1
+  for (int i0 = 0; i0 < LEN; i0 += 8) {
+    const int in = i0 + 8 < LEN ? i0 + 8 : i0;   /* the last pass refetches its own chunk */
+#pragma unroll
+    for (int u = 0; u < 8; ++u) f[u] = tab[(in + u) * 64 + lane];
+    /* the eight partials first: their LDS reads overlap (stores into the
+     * matrix below would otherwise keep each read behind the last store) */
+    double pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pv[u] = w.P[e[u] & 4095u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double nu = (double)((int)((e[u] >> 25) & 7u) - 4);
+      acc = fma(nu, pv[u], acc);
+      const bool fl = (e[u] >> 28) != 0u;
+      w.J[fl ? ((e[u] >> 12) & 8191u) : (unsigned)(KR_N * KR_LDJ + lane)] = acc;
+      acc = fl ? 0.0 : acc;
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = f[u];
   }
   __syncthreads();
 }

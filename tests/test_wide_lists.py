@@ -87,9 +87,12 @@ def test_contribution_lists_rebuild_the_jacobian_terms(oracle_lib, make):
     assert {k: sorted(v) for k, v in got.items()} == {k: sorted(v) for k, v in full.items()}
     gotf = _decode(ut["wf"], defs["NF"])
     assert {k: sorted(v) for k, v in gotf.items()} == {k: sorted(v) for k, v in fonly.items()}
-    # lists are balanced: no lane longer than the largest entry or the mean
+    # lists are balanced: no lane longer than the largest entry or the mean,
+    # rounded up to the gather's chunk of eight entries
     terms = sum(len(v) for v in full.values())
-    assert defs["NC"] <= max(max(len(v) for v in full.values()), -(-terms // 64) + 8)
+    bound = max(max(len(v) for v in full.values()), -(-terms // 64) + 8)
+    assert defs["NC"] % 8 == 0 and defs["NF"] % 8 == 0
+    assert defs["NC"] <= -(-bound // 8) * 8
     # direction tables: derived (log2 A, b, E) and reactant slots, padding
     # inert (log2 A = -4096, i.e. k = 0)
     for i, (r, d, re_, _) in enumerate(dirs):
