@@ -349,7 +349,7 @@ static std::string generate_wide(const kr_network *n) {
     uint32_t r = 0xFFFFFFu;
     if (d < (int)dirs.size()) {
       r = 0;
-      for (int k = 0; k < 3; ++k) r |= (uint32_t)(dirs[d].slot[k] >= 0 ? dirs[d].slot[k] : 255) << (8 * k);
+      for (int k = 0; k < 3; ++k) r |= (uint32_t)(dirs[d].slot[k] >= 0 ? dirs[d].slot[k] : 63) << (8 * k);
     }
     o += std::to_string(r) + "u" + (d + 1 < NDP ? "," : "");
   }

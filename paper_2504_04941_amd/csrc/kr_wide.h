@@ -38,10 +38,12 @@
  *
  * Generated section (network compiler) defines:
  *   KR_S, KR_NROWS, KR_NELEM, KR_LDJ (LDS row stride of the Jacobian),
- *   KR_NDR (direction rounds of 64), KR_NC / KR_NF (contribution list lengths)
+ *   KR_NDR (direction rounds of 64), KR_NC / KR_NF (contribution list lengths,
+ *   multiples of 8)
  *   kr_comp, kr_res, kr_cv, kr_atoms, kr_hf, kr_T_min, kr_T_max
  *   kr_da2, kr_db, kr_dE [KR_NDR * 64]  direction Arrhenius parameters (log2 A, b, E)
- *   kr_dr [KR_NDR * 64]                 reactant slots, 8 bits each (255 none)
+ *   kr_dr [KR_NDR * 64]                 reactant slots, 8 bits each (63: none, reads
+ *                                       the 1.0 that lane 63 publishes)
  *   kr_wc [KR_NC * 64], kr_wf [KR_NF * 64]  contribution lists (lane-interleaved):
  *       bits 0-11 source in P, 12-24 destination in the Jacobian,
  *       25-27 stoichiometric coefficient + 4, 28 last contribution of its entry
@@ -144,7 +146,9 @@ __device__ __forceinline__ int kr_wargmax(float key, bool cand, unsigned &best) 
 
 /* Publishes the lane-distributed point y to LDS. */
 __device__ __forceinline__ void kr_wpublish(KrWave &w, double yl) {
-  if ((int)threadIdx.x < KR_N) w.y[threadIdx.x] = yl;
+  /* lanes past the unknowns publish 1.0: slot 63 stands for an empty
+   * reactant slot in the direction tables */
+  w.y[threadIdx.x] = (int)threadIdx.x < KR_N ? yl : 1.0;
   __syncthreads();
 }
 
@@ -161,10 +165,7 @@ __device__ __forceinline__ void kr_wdirections(KrWave &w) {
     const int d = lane + 64 * j;
     const double a2 = kr_da2[d], b = kr_db[d], E = kr_dE[d];
     const unsigned rr = kr_dr[d];
-    const unsigned r0 = rr & 255u, r1 = (rr >> 8) & 255u, r2 = (rr >> 16) & 255u;
-    const double n0 = r0 < 255u ? w.y[r0] : 1.0;
-    const double n1 = r1 < 255u ? w.y[r1] : 1.0;
-    const double n2 = r2 < 255u ? w.y[r2] : 1.0;
+    const double n0 = w.y[rr & 63u], n1 = w.y[(rr >> 8) & 63u], n2 = w.y[(rr >> 16) & 63u];
     /* k = A T^b exp(-E/T) = 2^(log2 A + b log2 T - E log2(e) / T) */
     const double eiT = E * iT;
     const double k = kr_exp2(fma(-eiT, 0x1.71547652b82fep+0, fma(b, l2T, a2)));
@@ -320,8 +321,19 @@ __device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
     const F l = pc == KR_NOTPIV ? aj * inv : F(0);
     if (pc == KR_NOTPIV) a[j] = l;
     /* the pivot row's remaining entries, read from lane p's registers */
+    /* two entries per step: the second readlane pair covers the first
+     * pair's wait before its FMA */
 #pragma unroll
-    for (int k = j + 1; k < KR_N; ++k) a[k] = fma(-l, kr_wbc(a[k], p), a[k]);
+    for (int k = j + 1; k < KR_N; k += 2) {
+      const F u0 = kr_wbc(a[k], p);
+      if (k + 1 < KR_N) {
+        const F u1 = kr_wbc(a[k + 1], p);
+        a[k] = fma(-l, u0, a[k]);
+        a[k + 1] = fma(-l, u1, a[k + 1]);
+      } else {
+        a[k] = fma(-l, u0, a[k]);
+      }
+    }
   }
   return ok;
 }
