@@ -296,8 +296,8 @@ __device__ __forceinline__ F kr_wrcp(F x) {
   }
 }
 
-template <typename F>
-__device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
+template <typename F, bool AUG>
+__device__ __forceinline__ bool kr_wlu_impl(F (&a)[KR_N], int &pc, F &dinv, F &b) {
   const int lane = threadIdx.x;
   F mx = F(0);
 #pragma unroll
@@ -320,6 +320,8 @@ __device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
     if (lane == p) { pc = j; dinv = inv; }
     const F l = pc == KR_NOTPIV ? aj * inv : F(0);
     if (pc == KR_NOTPIV) a[j] = l;
+    /* augmented column: the forward substitution of kr_wsolve, step j */
+    if (AUG) b = fma(-l, kr_wbc(b, p), b);
     /* the pivot row's remaining entries, read from lane p's registers */
     /* two entries per step: the second readlane pair covers the first
      * pair's wait before its FMA */
@@ -338,19 +340,25 @@ __device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
   return ok;
 }
 
-/* Solves with the factors of kr_wlu: b by row (lane i: equation i) in, the
- * solution by unknown (lane j: x_j) out. */
 template <typename F>
-__device__ __forceinline__ F kr_wsolve(const F (&a)[KR_N], int pc, F dinv, F b) {
+__device__ __forceinline__ bool kr_wlu(F (&a)[KR_N], int &pc, F &dinv) {
+  F unused = F(0);
+  return kr_wlu_impl<F, false>(a, pc, dinv, unused);
+}
+
+/* kr_wlu with b (by row) carried along as an extra column: on return b has
+ * been through the forward substitution (the same operations, in the same
+ * order, as the first half of kr_wsolve), ready for kr_wback. */
+template <typename F>
+__device__ __forceinline__ bool kr_wlu_fwd(F (&a)[KR_N], int &pc, F &dinv, F &b) {
+  return kr_wlu_impl<F, true>(a, pc, dinv, b);
+}
+
+/* Back substitution with the factors of kr_wlu: b after the forward
+ * substitution, by row, in; the solution by unknown (lane j: x_j) out. */
+template <typename F>
+__device__ __forceinline__ F kr_wback(const F (&a)[KR_N], int pc, F dinv, F b) {
   const int lane = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < KR_N; ++j) {
-    const int pj = (int)__builtin_ctzll(__ballot(pc == j));
-    F yj;
-    if constexpr (sizeof(F) == 8) yj = kr_bcast(b, pj);
-    else yj = kr_bcastf(b, pj);
-    b = fma(-(pc > j ? a[j] : F(0)), yj, b);
-  }
   F x = F(0);
 #pragma unroll
   for (int j = KR_N - 1; j >= 0; --j) {
@@ -363,6 +371,21 @@ __device__ __forceinline__ F kr_wsolve(const F (&a)[KR_N], int pc, F dinv, F b) 
     x = lane == j ? xj : x;
   }
   return x;
+}
+
+/* Solves with the factors of kr_wlu: b by row (lane i: equation i) in, the
+ * solution by unknown (lane j: x_j) out. */
+template <typename F>
+__device__ __forceinline__ F kr_wsolve(const F (&a)[KR_N], int pc, F dinv, F b) {
+#pragma unroll
+  for (int j = 0; j < KR_N; ++j) {
+    const int pj = (int)__builtin_ctzll(__ballot(pc == j));
+    F yj;
+    if constexpr (sizeof(F) == 8) yj = kr_bcast(b, pj);
+    else yj = kr_bcastf(b, pj);
+    b = fma(-(pc > j ? a[j] : F(0)), yj, b);
+  }
+  return kr_wback(a, pc, dinv, b);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -469,8 +492,9 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
     if (!MIXED) {
       int pc;
       double dinv;
-      ok = kr_wlu(a, pc, dinv);
-      if (ok) d = kr_wsolve(a, pc, dinv, b);
+      double bf = b;
+      ok = kr_wlu_fwd(a, pc, dinv, bf);
+      if (ok) d = kr_wback(a, pc, dinv, bf);
     } else {
       /* FP32 LU of the row-equilibrated matrix; FP64 residual and iterative
        * refinement against the FP64 rows; FP64 LU where FP32 breaks down or
