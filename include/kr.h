@@ -29,8 +29,9 @@
  *     the call synchronises the stream before returning.
  *   - A network handle is immutable after creation and may be shared by
  *     calls on different streams, except that concurrent kr_chem_integrate
- *     calls on one handle race on its work counter: serialise them per
- *     handle (one stream per handle).
+ *     / kr_work_order calls on one handle race on its work counter and its
+ *     cell-order scratch: serialise them per handle (one stream per
+ *     handle).
  */
 #ifndef KR_H
 #define KR_H
@@ -237,7 +238,8 @@ void kr_default_options(kr_options *opt);
  *   cell_stats device [n_cells][4] int32 or NULL: accepted substeps, Newton
  *           iterations, rejected substeps, Newton failures
  * Errors: KR_EINVAL (NULL handle/arrays, n_cells < 0, ld < n_cells,
- * rtol <= 0, bad options), KR_EDEVICE.  n_cells == 0 is a no-op. */
+ * rtol <= 0, bad options), KR_EDEVICE, KR_ENOMEM (cell-order scratch with
+ * KR_ORDER_WORK).  n_cells == 0 is a no-op. */
 int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
                       int64_t ld, double *T, const double *rho,
                       const double *dt, double dt_scalar, double rtol,

@@ -694,12 +694,13 @@ static int order_reserve(OrderBufs &b, long long n) {
   b.order = nullptr;
   b.bucket = nullptr;
   b.cap = 0;
-  HIP_TRY(hipMalloc(&b.order, (size_t)n * sizeof(unsigned)));
-  HIP_TRY(hipMalloc(&b.bucket, (size_t)n));
-  if (!b.hist) {
-    HIP_TRY(hipMalloc(&b.hist, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)));
-    HIP_TRY(hipMemset(b.hist, 0, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)));
+  if (hipMalloc(&b.order, (size_t)n * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&b.bucket, (size_t)n) != hipSuccess ||
+      (!b.hist && hipMalloc(&b.hist, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)) != hipSuccess)) {
+    order_free(b);
+    return fail(KR_ENOMEM, "cell-order scratch for %lld cells", n);
   }
+  HIP_TRY(hipMemset(b.hist, 0, 2 * KR_ORDER_NBUCKETS * sizeof(unsigned)));
   b.cap = n;
   return KR_OK;
 }
