@@ -147,3 +147,18 @@ def test_order_in_multi_network_launch():
     multi.close()
     for n in nets:
         n.close()
+
+
+def test_work_order_invalid_arguments():
+    kr = _kr()
+    desc = sy.network_h_he(0)
+    cs = sy.cells_h_he(desc, 100, 0)
+    net = kr.Network(desc)
+    n, T = _dev(cs.n), _dev(cs.T)
+    with pytest.raises(kr.KrError):      # no step given: dt_scalar must be finite and >= 0
+        kr.work_order(net, n, T, dt_scalar=float("nan"))
+    with pytest.raises(kr.KrError):
+        kr.chem_integrate(net, n, T, dt_scalar=1.0, opts=kr.default_options(order=7))
+    out = kr.work_order(net, n[:, :0], T[:0], dt_scalar=1.0)   # empty batch: nothing to do
+    assert out.numel() == 0
+    net.close()
