@@ -381,8 +381,8 @@ def main():
                          "work first or input order (default: the faster one for the workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the per-cell integration needs no communication, "
-              "and multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the per-cell integration needs no communication "
+              "between GPUs, and only the single-GPU path is implemented (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "calibrate":
