@@ -118,7 +118,11 @@ void kr_network_destroy(kr_network *net);
 /* Compile-time tuning of the generated kernels (chosen by the autotuner):
  *   waves_per_eu  occupancy the register allocator budgets for (1..8; the
  *                 lane's Newton matrix lives in VGPRs, so more waves means
- *                 fewer registers per lane and possibly scratch spills)
+ *                 fewer registers per lane and possibly scratch spills).
+ *                 0 (default) chooses per network: 1 for the lane layout,
+ *                 for the wavefront layout 2 where its LDS block leaves
+ *                 room for two waves per SIMD, else 1; a several-network
+ *                 kernel takes the smallest of its networks' choices
  *   pivot_tau     threshold of the LU's partial pivoting, (0, 1]: the
  *                 diagonal is kept unless its scaled magnitude is below
  *                 pivot_tau times the best candidate's (lane-per-cell

@@ -510,17 +510,14 @@ static int compile_source(const std::string &src, std::vector<char> &code, std::
 }
 
 /* Occupancy target of the integrator kernels (waves per SIMD the compiler
- * budgets registers for).  One wave: from ~8 unknowns the lane's FP64
- * Newton matrix alone needs most of 256 VGPRs, and even at 6 unknowns a
- * two-wave budget forces scratch spills that cost more than the extra wave
- * hides (measured: 390 vs 490 ms on 2^18 five-species cells).
+ * budgets registers for); 0 = chosen per network by auto_waves_per_eu.
  * KR_WAVES_PER_EU in the environment overrides (tuning experiments). */
 static int default_waves_per_eu() {
   if (const char *e = getenv("KR_WAVES_PER_EU")) {
     const int w = atoi(e);
-    if (w >= 1 && w <= 8) return w;
+    if (w >= 0 && w <= 8) return w;
   }
-  return 1;
+  return 0;
 }
 
 extern "C" void kr_default_build_options(kr_build_opts *o) {
@@ -531,15 +528,15 @@ extern "C" void kr_default_build_options(kr_build_opts *o) {
 }
 
 static int check_build_options(const kr_build_opts *o) {
-  if (o->waves_per_eu < 1 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [1, 8]");
+  if (o->waves_per_eu < 0 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [0, 8]");
   if (!(o->pivot_tau > 0.0f && o->pivot_tau <= 1.0f)) return fail(KR_EINVAL, "pivot_tau out of (0, 1]");
   if (o->layout < KR_LAYOUT_AUTO || o->layout > KR_LAYOUT_WAVE) return fail(KR_EINVAL, "layout out of [0, 2]");
   return KR_OK;
 }
 
-static std::string build_prefix(const kr_build_opts &o) {
+static std::string build_prefix(int waves_per_eu, const kr_build_opts &o) {
   char b[160];
-  snprintf(b, sizeof b, "#define KR_WAVES_PER_EU %d\n#define KR_PIVOT_TAU %a\n", o.waves_per_eu,
+  snprintf(b, sizeof b, "#define KR_WAVES_PER_EU %d\n#define KR_PIVOT_TAU %a\n", waves_per_eu,
            (double)o.pivot_tau);
   return b;
 }
@@ -548,12 +545,35 @@ static bool use_wide(const kr_network *n, const kr_build_opts &o) {
   return o.layout == KR_LAYOUT_WAVE || (o.layout == KR_LAYOUT_AUTO && n->S >= KR_WIDE_MIN_SPECIES);
 }
 
+/* Automatic occupancy target of one network's integrator.  Lane layout: one
+ * wave; from ~8 unknowns the lane's FP64 Newton matrix alone needs most of
+ * 256 VGPRs, and even at 6 unknowns a two-wave budget forces scratch spills
+ * that cost more than the extra wave hides (measured: 390 vs 490 ms on 2^18
+ * five-species cells).  Wavefront layout: the matrix lives in LDS and the
+ * kernel is latency bound, so a second wave per SIMD pays wherever the LDS
+ * block (the KrWave struct) leaves room for it, even at the cost of a few
+ * spilled registers (measured on 2^20 23-species cells: 70 vs 105 ms FP64,
+ * 88 vs 138 ms with the FP32 LU); the 48-species block (39 KB) allows one
+ * wave per SIMD only. */
+static int wide_block_bytes(const kr_network *n) {
+  const int ldj = wide_ldj(n->S), ndp = 64 * std::max<int>(1, (int)((wide_directions(n).size() + 63) / 64));
+  return 8 * (64 + 64 + 5 * ndp + (n->S + 1) * ldj + 64);
+}
+
+static int auto_waves_per_eu(const kr_network *n, const kr_build_opts &o) {
+  if (o.waves_per_eu > 0) return o.waves_per_eu;
+  if (!use_wide(n, o)) return 1;
+  const int per_simd = 160 * 1024 / 4 / wide_block_bytes(n);
+  return std::max(1, std::min(2, per_simd));
+}
+
 static std::string full_source(const kr_network *n, const kr_build_opts &o) {
+  const int w = auto_waves_per_eu(n, o);
   if (use_wide(n, o))
-    return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(o) +
+    return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(w, o) +
            kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_wide(n) + "\n" + kWideSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         build_prefix(o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
+         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
 }
 
 static void release(kr_network *n) {
@@ -580,6 +600,7 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
   rc = build_tables(desc, n);
   if (rc != KR_OK) { delete n; return rc; }
   n->build = bo;
+  n->build.waves_per_eu = auto_waves_per_eu(n, bo);
   n->wide = use_wide(n, bo);
   if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
   n->source = full_source(n, bo);
@@ -958,9 +979,19 @@ struct kr_multi {
   long long graph_launches = 0, graph_captures = 0;
 };
 
+/* One kernel serves all networks of a multi launch: the smallest of their
+ * automatic targets (a lane-layout network makes it one wave). */
+static int multi_waves_per_eu(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
+  if (o.waves_per_eu > 0) return o.waves_per_eu;
+  int w = 8;
+  for (const kr_network *n : nets) w = std::min(w, auto_waves_per_eu(n, n->wide ? kr_build_opts{0, o.pivot_tau, KR_LAYOUT_WAVE}
+                                                                                 : kr_build_opts{0, o.pivot_tau, KR_LAYOUT_LANE}));
+  return w;
+}
+
 static std::string multi_source(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
   std::string s = "/* per-cell implicit thermochemistry: several networks in one launch */\n" +
-                  build_prefix(o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n";
+                  build_prefix(multi_waves_per_eu(nets, o), o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
     if (nets[k]->wide)
       s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_wide(nets[k]) + "\n" + kWideSource +
@@ -1023,6 +1054,7 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   if (!m) return fail(KR_ENOMEM, "out of host memory");
   m->nets.assign(nets, nets + n_nets);
   m->build = bo;
+  m->build.waves_per_eu = multi_waves_per_eu(m->nets, bo);
   m->source = multi_source(m->nets, bo);
   std::vector<char> code;
   std::string log;

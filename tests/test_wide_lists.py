@@ -113,3 +113,28 @@ def test_wave_layout_limits():
     kr = _kr()
     with pytest.raises(kr.KrError):
         kr.network_check(sy.network_h_o_n(1), build=kr.build_options(layout=7))
+
+
+def test_automatic_occupancy_target():
+    """waves_per_eu = 0: one wave per SIMD for the lane layout, two for a
+    wavefront network whose LDS block leaves room for them (23 species,
+    11 KB), one where it does not (48 species, 39 KB of the 40 KB share of
+    a SIMD); an explicit value is kept."""
+    kr = _kr()
+
+    def waves(desc, **kw):
+        src = kr.network_check(desc, build=kr.build_options(**kw))
+        return int(re.search(r"#define KR_WAVES_PER_EU (\d+)", src).group(1))
+
+    assert kr.build_options().waves_per_eu == 0
+    assert waves(sy.network_h_o_n(1)) == 1
+    assert waves(sy.network_astro23(2)) == 2
+    assert waves(sy.network_large48(3)) == 1
+    assert waves(sy.network_h_o_n(1), layout=kr.KR_LAYOUT_WAVE) == 2
+    assert waves(sy.network_astro23(2), waves_per_eu=3) == 3
+    assert waves(sy.network_astro23(2), layout=kr.KR_LAYOUT_LANE) == 1
+    # one kernel for several networks takes the smallest choice
+    src = kr.multi_check([sy.network_astro23(2), sy.network_large48(3)])
+    assert "#define KR_WAVES_PER_EU 1" in src
+    with pytest.raises(kr.KrError):
+        kr.network_check(sy.network_h_o_n(1), build=kr.build_options(waves_per_eu=9))
