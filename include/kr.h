@@ -122,7 +122,8 @@ void kr_network_destroy(kr_network *net);
  *                 0 (default) chooses per network: 1 for the lane layout,
  *                 for the wavefront layout 2 where its LDS block leaves
  *                 room for two waves per SIMD, else 1; a several-network
- *                 kernel takes the smallest of its networks' choices
+ *                 launch runs lane- and wavefront-layout networks in
+ *                 separate kernels when their choices differ
  *   pivot_tau     threshold of the LU's partial pivoting, (0, 1]: the
  *                 diagonal is kept unless its scaled magnitude is below
  *                 pivot_tau times the best candidate's (lane-per-cell
@@ -310,8 +311,11 @@ typedef struct {
 int kr_multi_create(const kr_network *const *nets, int32_t n_nets,
                     const kr_build_opts *opt, kr_multi **out);
 void kr_multi_destroy(kr_multi *m);
-/* Integrates batches[k] with network k, all in one persistent launch.
- * use_graph != 0: the launch ([reset work counters] -> [integrate]) is
+/* Integrates batches[k] with network k in one launch: one persistent
+ * kernel for all networks, or one per occupancy group (lane- and
+ * wavefront-layout networks compiled for different waves per SIMD), run in
+ * order on the stream.  use_graph != 0: the launch ([order kernels] ->
+ * [reset work counters] -> [integrate]) is
  * captured into a hipGraph on first use and replayed on later calls with
  * the same arguments (re-captured when they change).  Options apply to all
  * batches; the learned guess is not supported here (KR_EINVAL).  Calls on

@@ -967,10 +967,13 @@ struct kr_multi {
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
   std::string source;
   hipModule_t module = nullptr;
-  hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr;
+  /* one persistent kernel per group of networks compiled for the same
+   * occupancy target (KrGroups) */
+  std::vector<std::vector<int>> groups;
+  hipFunction_t f_fp64[2] = {}, f_fp32[2] = {}, f_reset = nullptr;
   hipFunction_t f_keys[KR_MAX_NETS] = {}, f_scan = nullptr, f_scatter = nullptr;
   OrderBufs ord[KR_MAX_NETS];
-  int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
+  int device = -1, cu_count = 0, occ_fp64[2] = {}, occ_fp32[2] = {};
   unsigned long long *d_counters = nullptr; /* one per network */
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
@@ -979,13 +982,37 @@ struct kr_multi {
   long long graph_launches = 0, graph_captures = 0;
 };
 
-/* One kernel serves all networks of a multi launch: the smallest of their
- * automatic targets (a lane-layout network makes it one wave). */
+/* Networks of a multi launch grouped by occupancy target: one persistent
+ * kernel drains all queues when every network wants the same target (or an
+ * explicit waves_per_eu sets it); otherwise the lane-layout networks (one
+ * wave per SIMD) and the wavefront-layout networks (two where their LDS
+ * blocks allow) get a kernel each, run one after the other.  Returns the
+ * groups with their targets. */
+static std::vector<std::pair<int, std::vector<int>>> multi_groups(const std::vector<const kr_network *> &nets,
+                                                                  const kr_build_opts &o) {
+  int w[2] = {8, 8};
+  std::vector<int> members[2];
+  for (size_t k = 0; k < nets.size(); ++k) {
+    const int g = nets[k]->wide ? 1 : 0;
+    const kr_build_opts ok{o.waves_per_eu, o.pivot_tau, g ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE};
+    w[g] = std::min(w[g], auto_waves_per_eu(nets[k], ok));
+    members[g].push_back((int)k);
+  }
+  std::vector<std::pair<int, std::vector<int>>> out;
+  if (members[0].empty() || members[1].empty() || w[0] == w[1]) {
+    std::vector<int> all;
+    for (size_t k = 0; k < nets.size(); ++k) all.push_back((int)k);
+    out.push_back({std::min(w[0], w[1]), all});
+  } else {
+    out.push_back({w[0], members[0]});
+    out.push_back({w[1], members[1]});
+  }
+  return out;
+}
+
 static int multi_waves_per_eu(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
-  if (o.waves_per_eu > 0) return o.waves_per_eu;
   int w = 8;
-  for (const kr_network *n : nets) w = std::min(w, auto_waves_per_eu(n, n->wide ? kr_build_opts{0, o.pivot_tau, KR_LAYOUT_WAVE}
-                                                                                 : kr_build_opts{0, o.pivot_tau, KR_LAYOUT_LANE}));
+  for (const auto &g : multi_groups(nets, o)) w = std::min(w, g.first);
   return w;
 }
 
@@ -1002,20 +1029,25 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
            "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";
   }
   s += "struct KrMulti { KrParams net[" + std::to_string(KR_MAX_NETS) + "]; int n_nets; };\n";
-  for (int mixed = 0; mixed < 2; ++mixed) {
-    s += std::string("extern \"C\" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) ") +
-         (mixed ? "kr_integrate_multi_fp32lu" : "kr_integrate_multi_fp64") +
-         "(KrMulti m) {\n"
-         "  /* each wave drains one network's queue after another, starting at a\n"
-         "   * different network so that the queues drain together */\n"
-         "  for (int i = 0; i < m.n_nets; ++i) {\n"
-         "    const int k = (int)((blockIdx.x + i) % (unsigned)m.n_nets);\n"
-         "    switch (k) {\n";
-    for (size_t k = 0; k < nets.size(); ++k)
-      s += "      case " + std::to_string(k) + ": kr_m" + std::to_string(k) +
-           (nets[k]->wide ? "::kr_wintegrate<" : "::kr_integrate_body<") + (mixed ? "true" : "false") +
-           ">(m.net[" + std::to_string(k) + "]); break;\n";
-    s += "      default: break;\n    }\n  }\n}\n";
+  const auto groups = multi_groups(nets, o);
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const std::vector<int> &mem = groups[g].second;
+    for (int mixed = 0; mixed < 2; ++mixed) {
+      s += "extern \"C\" __global__ void __launch_bounds__(64, " + std::to_string(groups[g].first) + ") " +
+           (mixed ? "kr_integrate_multi_fp32lu_" : "kr_integrate_multi_fp64_") + std::to_string(g) +
+           "(KrMulti m) {\n"
+           "  /* each wave drains one network's queue after another, starting at a\n"
+           "   * different network so that the queues drain together */\n"
+           "  for (int i = 0; i < " + std::to_string(mem.size()) + "; ++i) {\n"
+           "    switch ((int)((blockIdx.x + i) % " + std::to_string(mem.size()) + "u)) {\n";
+      for (size_t j = 0; j < mem.size(); ++j) {
+        const int k = mem[j];
+        s += "      case " + std::to_string(j) + ": if (" + std::to_string(k) + " < m.n_nets) kr_m" + std::to_string(k) +
+             (nets[k]->wide ? "::kr_wintegrate<" : "::kr_integrate_body<") + (mixed ? "true" : "false") +
+             ">(m.net[" + std::to_string(k) + "]); break;\n";
+      }
+      s += "      default: break;\n    }\n  }\n}\n";
+    }
   }
   for (size_t k = 0; k < nets.size(); ++k)
     s += "extern \"C\" __global__ void __launch_bounds__(64, 1) kr_order_keys_m" + std::to_string(k) +
@@ -1056,6 +1088,7 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   m->build = bo;
   m->build.waves_per_eu = multi_waves_per_eu(m->nets, bo);
   m->source = multi_source(m->nets, bo);
+  for (const auto &g : multi_groups(m->nets, bo)) m->groups.push_back(g.second);
   std::vector<char> code;
   std::string log;
   rc = compile_source(m->source, code, log);
@@ -1073,15 +1106,18 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
   MULTI_TRY(hipGetDevice(&m->device));
   MULTI_TRY(hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device));
   MULTI_TRY(hipModuleLoadData(&m->module, code.data()));
-  MULTI_TRY(hipModuleGetFunction(&m->f_fp64, m->module, "kr_integrate_multi_fp64"));
-  MULTI_TRY(hipModuleGetFunction(&m->f_fp32, m->module, "kr_integrate_multi_fp32lu"));
+  for (size_t g = 0; g < m->groups.size(); ++g) {
+    const std::string sfx = std::to_string(g);
+    MULTI_TRY(hipModuleGetFunction(&m->f_fp64[g], m->module, ("kr_integrate_multi_fp64_" + sfx).c_str()));
+    MULTI_TRY(hipModuleGetFunction(&m->f_fp32[g], m->module, ("kr_integrate_multi_fp32lu_" + sfx).c_str()));
+    MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64[g], m->f_fp64[g], 64, 0));
+    MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32[g], m->f_fp32[g], 64, 0));
+  }
   MULTI_TRY(hipModuleGetFunction(&m->f_reset, m->module, "kr_reset_counters"));
   MULTI_TRY(hipModuleGetFunction(&m->f_scan, m->module, "kr_order_scan"));
   MULTI_TRY(hipModuleGetFunction(&m->f_scatter, m->module, "kr_order_scatter"));
   for (int k = 0; k < n_nets; ++k)
     MULTI_TRY(hipModuleGetFunction(&m->f_keys[k], m->module, ("kr_order_keys_m" + std::to_string(k)).c_str()));
-  MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64, m->f_fp64, 64, 0));
-  MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32, m->f_fp32, 64, 0));
   MULTI_TRY(hipMalloc(&m->d_counters, sizeof(unsigned long long) * KR_MAX_NETS));
   MULTI_TRY(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
 #undef MULTI_TRY
@@ -1172,14 +1208,17 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
   if (total == 0) return KR_OK;
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t st = (hipStream_t)stream;
-  hipFunction_t f = o.precision == KR_FP64 ? m->f_fp64 : m->f_fp32;
-  const int occ = o.precision == KR_FP64 ? m->occ_fp64 : m->occ_fp32;
-  long long blocks = (long long)m->cu_count * (occ > 0 ? occ : 1);
-  long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
-  for (int k = 0; k < h.n_nets; ++k)
-    need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
-  if (blocks > need) blocks = need;
-  if (blocks < 1) blocks = 1;
+  const int n_groups = (int)m->groups.size();
+  hipFunction_t f[2] = {};
+  long long blocks[2] = {0, 0};
+  for (int g = 0; g < n_groups; ++g) {
+    f[g] = o.precision == KR_FP64 ? m->f_fp64[g] : m->f_fp32[g];
+    const int occ = o.precision == KR_FP64 ? m->occ_fp64[g] : m->occ_fp32[g];
+    long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
+    for (int k : m->groups[g])
+      need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
+    blocks[g] = std::min<long long>((long long)m->cu_count * (occ > 0 ? occ : 1), need);   /* 0: no work */
+  }
   /* largest-work-first order of each batch: buffers reserved here, outside
    * any capture; the order kernels run on the launch stream ahead of the
    * counter reset (and are part of the captured graph) */
@@ -1203,14 +1242,22 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
   int nn = h.n_nets;
   void *rargs[] = {&cnt, &nn};
   void *args[] = {&h};
+  auto launch_groups = [&](hipStream_t s) -> hipError_t {
+    for (int g = 0; g < n_groups; ++g) {
+      if (blocks[g] < 1) continue;
+      const hipError_t e = hipModuleLaunchKernel(f[g], (unsigned)blocks[g], 1, 1, 64, 1, 1, 0, s, args, nullptr);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   if (!use_graph) {
     if ((rc = launch_orders(st))) return rc;
     HIP_TRY(hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
-    HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
+    HIP_TRY(launch_groups(st));
     return KR_OK;
   }
   /* graph of [order kernels] -> [reset the work counters] -> [persistent
-   * integrate], captured once per distinct launch configuration and replayed
+   * integrate, one kernel per group], captured once per distinct launch configuration and replayed
    * on the caller's stream (counters and histograms are cleared by kernels,
    * not memset nodes) */
   std::vector<char> key(sizeof h + sizeof blocks + sizeof f);
@@ -1223,7 +1270,7 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
     HIP_TRY(hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal));
     const int r0 = launch_orders(m->capture);
     hipError_t e1 = hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, m->capture, rargs, nullptr);
-    hipError_t e2 = hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, m->capture, args, nullptr);
+    hipError_t e2 = launch_groups(m->capture);
     hipGraph_t g = nullptr;
     hipError_t e3 = hipStreamEndCapture(m->capture, &g);
     if (r0 != KR_OK || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
