@@ -103,3 +103,37 @@ def test_multi_network_parity_and_graph_replay(oracle_lib):
     multi.close()
     for n in nets:
         n.close()
+
+
+def test_occupancy_groups_give_the_same_results():
+    """Automatic occupancy target (lane-layout networks in one kernel at one
+    wave per SIMD, the 23-species network in a second at two) against one
+    kernel for all three at one wave per SIMD: bitwise the same per-cell
+    results in both precisions, eager and graph-replayed."""
+    kr = _kr()
+    batches = _batches()
+    descs = [d for d, _ in batches]
+    assert "kr_integrate_multi_fp64_1" in kr.multi_check(descs)          # two kernels
+    assert "kr_integrate_multi_fp64_1" not in kr.multi_check(descs[:2])  # lane networks only: one
+    nets = [kr.Network(d) for d in descs]
+    split = kr.Multi(nets)
+    one = kr.Multi(nets, kr.build_options(waves_per_eu=1))
+    dts = [np.minimum(20.0 * kr.fastest_timescale(net, _dev(cs.n), _dev(cs.T)).cpu().numpy(), 1e-4)
+           for (_, cs), net in zip(batches, nets)]
+    for prec in ("fp64", "fp32lu"):
+        opts = kr.default_options(precision=prec)
+        res = []
+        for multi, graph in ((one, False), (split, False), (split, True)):
+            bufs = _buffers(batches, dts)
+            multi.integrate(bufs, rtol=1e-6, opts=opts, use_graph=graph)
+            torch.cuda.synchronize()
+            res.append([{k: v.cpu() for k, v in b.items()} for b in bufs])
+        for got in res[1:]:
+            for a, b, (desc, _) in zip(res[0], got, batches):
+                for key in ("states", "T", "status", "cell_stats"):
+                    assert torch.equal(a[key], b[key]), (prec, desc.name, key)
+        assert all((b["status"] != -7).all() for b in res[0])
+    split.close()
+    one.close()
+    for n in nets:
+        n.close()
