@@ -30,7 +30,7 @@ from . import (KR_LAYOUT_LANE, KR_LAYOUT_WAVE, KR_ORDER_INPUT, KR_ORDER_WORK, Bu
 
 CACHE = os.environ.get("KR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "kr_autotune.json"))
-CANDIDATES = [(1, 0.1), (1, 0.01), (2, 0.1)]
+CANDIDATES = [(0, 0.1), (1, 0.1), (1, 0.01), (2, 0.1)]   # (waves_per_eu, pivot_tau); 0 = automatic
 
 
 def _key(sources, precision):
