@@ -3,8 +3,9 @@
 Tunables (compile-time, `kr_build_opts`): per network, the layout (one cell
 per lane, or one cell per wavefront with the Newton matrix one row per
 lane); for the module, the occupancy target the register allocator budgets
-for (waves per SIMD; the lane's Newton matrix lives in VGPRs, so a higher
-target trades registers for scratch spills) and the threshold of the LU's
+for (waves per SIMD, or 0 for the library's per-layout choice; the lane's
+Newton matrix lives in VGPRs, so a higher target trades registers for
+scratch spills) and the threshold of the LU's
 partial pivoting (a smaller threshold takes fewer row exchanges, which
 execute wave-wide when any lane needs one).  Run-time tunable
 (`kr_options.order`): the order in which cells are handed out (input order,
