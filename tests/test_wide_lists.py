@@ -138,3 +138,18 @@ def test_automatic_occupancy_target():
     assert "#define KR_WAVES_PER_EU 1" in src
     with pytest.raises(kr.KrError):
         kr.network_check(sy.network_h_o_n(1), build=kr.build_options(waves_per_eu=9))
+
+
+def test_multi_kernels_grouped_by_occupancy_target():
+    """Several networks: lane- and wavefront-layout networks with different
+    automatic targets get a kernel each; networks that share a target, one."""
+    kr = _kr()
+
+    def kernels(descs):
+        src = kr.multi_check(descs)
+        return re.findall(r"__launch_bounds__\(64, (\d+)\) kr_integrate_multi_fp64_(\d+)", src)
+
+    assert kernels([sy.network_h_he(0), sy.network_h_o_n(1), sy.network_astro23(2)]) == [("1", "0"), ("2", "1")]
+    assert kernels([sy.network_h_he(0), sy.network_h_o_n(1)]) == [("1", "0")]
+    assert kernels([sy.network_astro23(2), sy.network_large48(3)]) == [("1", "0")]
+    assert kernels([sy.network_astro23(2)]) == [("2", "0")]
