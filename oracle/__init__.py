@@ -17,7 +17,8 @@ _SRC = os.path.join(_HERE, "kr_oracle.c")
 _LIB = os.path.join(_HERE, "libkr_oracle.so")
 _lib = None
 
-ADAPTIVE, FIXED = 0, 1
+ADAPTIVE, FIXED, REPLAY = 0, 1, 2
+POST_CLIPPED, POST_BROKEN_UP = 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -28,6 +29,11 @@ def build(force: bool = True) -> str:
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+class Extras(C.Structure):
+    _fields_ = [("h_hint", C.c_void_p), ("h_log", C.c_void_p), ("h_log_ld", C.c_int64),
+                ("h_log_cap", C.c_int32), ("h_log_n", C.c_void_p), ("post", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -70,6 +76,10 @@ def lib():
         L.kro_integrate.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Opts),
                                     C.c_void_p, C.c_void_p, C.c_int]
+        L.kro_integrate_ex.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Opts),
+                                       C.c_void_p, C.c_void_p, C.POINTER(Extras), C.c_int]
+        L.kro_postprocess_flags.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.kro_be_substep.argtypes = [C.c_void_p, C.POINTER(Opts), C.c_void_p, C.c_void_p,
                                      C.c_double, C.c_void_p, C.POINTER(C.c_int32)]
         L.kro_element_residual.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
@@ -178,6 +188,13 @@ class OracleNet:
         lib().kro_postprocess(self.h, E0.ctypes.data, n.ctypes.data)
         return n
 
+    def postprocess_flags(self, E0, n):
+        """(post-processed copy of n, KRO_POST_* flags)."""
+        E0 = np.ascontiguousarray(E0, np.float64)
+        n = np.array(n, np.float64)
+        flags = lib().kro_postprocess_flags(self.h, E0.ctypes.data, n.ctypes.data)
+        return n, flags
+
     def fastest_timescale(self, y) -> float:
         y = np.ascontiguousarray(y, np.float64)
         return lib().kro_fastest_timescale(self.h, y.ctypes.data)
@@ -200,6 +217,49 @@ class OracleNet:
         if rc != 0:
             raise ValueError("oracle rejected the integrate arguments")
         return n, T, status, stats
+
+    def integrate_ex(self, n, T, rho=None, dt=None, dt_scalar=0.0, opts=None, nthreads=0,
+                     h_hint=None, log_cap=0, replay=None, replay_n=None):
+        """kro_integrate_ex on copies of the batch.  h_hint: per-cell first
+        substep (in/out copy).  log_cap > 0 records the accepted substep
+        lengths (first log_cap per cell).  replay, replay_n: the substep
+        lengths [cap, n_cells] and counts to replay (sets mode KRO_REPLAY).
+        Returns a dict with n, T, status, stats, h_hint, h_log, h_log_n,
+        post."""
+        o = opts or default_opts()
+        n = np.array(n, np.float64, order="C")
+        T = np.array(T, np.float64)
+        ncell = T.shape[0]
+        status = np.zeros(ncell, np.int32)
+        stats = np.zeros((ncell, 4), np.int32)
+        post = np.zeros(ncell, np.int32)
+        rho_a = None if rho is None else np.ascontiguousarray(rho, np.float64)
+        dt_a = None if dt is None else np.ascontiguousarray(dt, np.float64)
+        ex = Extras()
+        hint = None if h_hint is None else np.array(h_hint, np.float64)
+        ex.h_hint = None if hint is None else hint.ctypes.data
+        if replay is not None:
+            o = Opts.from_buffer_copy(o)
+            o.mode = REPLAY
+            log = np.array(replay, np.float64, order="C").reshape(-1, ncell)
+            log_n = np.array(replay_n, np.int32)
+        else:
+            log = np.zeros((max(log_cap, 0), ncell))
+            log_n = np.zeros(ncell, np.int32)
+        ex.h_log = log.ctypes.data if log.size else None
+        ex.h_log_ld = ncell
+        ex.h_log_cap = log.shape[0]
+        ex.h_log_n = log_n.ctypes.data
+        ex.post = post.ctypes.data
+        rc = lib().kro_integrate_ex(self.h, ncell, n.ctypes.data, ncell, T.ctypes.data,
+                                    None if rho_a is None else rho_a.ctypes.data,
+                                    None if dt_a is None else dt_a.ctypes.data, float(dt_scalar),
+                                    C.byref(o), status.ctypes.data, stats.ctypes.data, C.byref(ex),
+                                    int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle rejected the integrate arguments")
+        return {"n": n, "T": T, "status": status, "stats": stats, "h_hint": hint,
+                "h_log": log, "h_log_n": log_n, "post": post}
 
     def element_residual(self, before, after):
         before = np.ascontiguousarray(before, np.float64)

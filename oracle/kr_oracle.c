@@ -421,25 +421,49 @@ typedef struct {
   double h0, safety, growth;
 } attempt_params;
 
+/* Record of one attempt: the accepted substep lengths in order (the first
+ * cap of them are stored), their number, and the controller's proposed
+ * length of the substep after the last accepted one. */
+typedef struct {
+  double *h;             /* [cap] with stride ld, or NULL */
+  int64_t ld;
+  int32_t cap, n;
+  double h_next;
+} substep_log;
+
+static void log_substep(substep_log *lg, double h) {
+  if (lg->h && lg->n < lg->cap) lg->h[lg->n * lg->ld] = h;
+  lg->n++;
+}
+
 /* One attempt over [0, dt].  Adaptive: after each converged substep the
  * local error estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i
  * (w_i from both end points) decides; accepted when err <= 1, after which
  * h *= min(growth, max(0.2, safety/sqrt(max(err,1e-10)))); a rejected step
  * uses h *= max(0.2, safety/sqrt(err)); a Newton failure quarters h.  The
  * step is clipped to land on dt exactly.  Fails when h < 1e-12 dt or the
- * number of substep attempts reaches max_substeps. */
+ * number of substep attempts reaches max_substeps.  The proposed next
+ * length after the last substep is the same update of the accepted length;
+ * when that substep was clipped to land on dt, the unclipped length is kept
+ * if it is larger.  Fixed mode: n_fixed substeps of dt / n_fixed.  Replay
+ * mode: the n_replay given lengths in order, no error control. */
 static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *y0,
                              const double *atol, double dt, attempt_params ap,
-                             double *y_out, int32_t *st) {
+                             const double *replay, int64_t replay_ld, int32_t n_replay,
+                             double *y_out, int32_t *st, substep_log *lg) {
   const int N = n->S + 1;
   double yn[KRO_MAXN], y[KRO_MAXN], gn[KRO_MAXN], g[KRO_MAXN];
   memcpy(yn, y0, sizeof(double) * (size_t)N);
-  if (o->mode == KRO_FIXED) {
-    double h = dt / (double)o->n_fixed;
-    for (int k = 0; k < o->n_fixed; ++k) {
+  lg->n = 0;
+  lg->h_next = 0.0;
+  if (o->mode == KRO_FIXED || o->mode == KRO_REPLAY) {
+    const int m = o->mode == KRO_FIXED ? o->n_fixed : n_replay;
+    for (int k = 0; k < m; ++k) {
+      double h = o->mode == KRO_FIXED ? dt / (double)o->n_fixed : replay[k * replay_ld];
       if (kro_be_substep(n, o, yn, atol, h, y, &st[1]) != 0) { st[3]++; return -1; }
       memcpy(yn, y, sizeof(double) * (size_t)N);
       st[0]++;
+      log_substep(lg, h);
     }
     memcpy(y_out, yn, sizeof(double) * (size_t)N);
     return 0;
@@ -450,6 +474,7 @@ static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *
   for (;;) {
     if (attempts >= o->max_substeps) return -1;
     int final = 0;
+    double h_free = h;             /* the controller's length before the clip */
     if (h >= dt - t) { h = dt - t; final = 1; }
     else if (h < 1e-12 * dt) return -1;
     attempts++;
@@ -470,9 +495,14 @@ static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *
       memcpy(yn, y, sizeof(double) * (size_t)N);
       memcpy(gn, g, sizeof(double) * (size_t)N);
       st[0]++;
-      if (final) break;
+      log_substep(lg, h);
+      double h_new = h * fmin(ap.growth, fmax(0.2, ap.safety / sqrt(fmax(err, 1e-10))));
+      if (final) {
+        lg->h_next = h_free > h_new ? h_free : h_new;
+        break;
+      }
       t += h;
-      h *= fmin(ap.growth, fmax(0.2, ap.safety / sqrt(fmax(err, 1e-10))));
+      h = h_new;
     } else {
       st[2]++;
       h *= fmax(0.2, ap.safety / sqrt(err));
@@ -535,10 +565,11 @@ void kro_element_residual(const kro_net *n, int64_t n_cells, const double *befor
  * most abundant species that carries the row with the reservoir's sign is
  * broken up into the reservoirs of all its rows, just enough to bring the
  * reservoir to zero (moving to the next most abundant if one is used up). */
-void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
+int kro_postprocess_flags(const kro_net *n, const double *E0, double *nn) {
   const int S = n->S;
+  int flags = 0;
   for (int s = 0; s < S; ++s)
-    if (nn[s] < 0.0) nn[s] = 0.0;
+    if (nn[s] < 0.0) { nn[s] = 0.0; flags |= KRO_POST_CLIPPED; }
   for (int v = 0; v < n->n_rows; ++v) {
     double E = 0.0;
     for (int s = 0; s < S; ++s) E += n->comp[v * S + s] * nn[s];
@@ -560,6 +591,7 @@ void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
       }
       if (best < 0) break;
       used[best] = 1;
+      flags |= KRO_POST_BROKEN_UP;
       /* converting x of species `best` changes the reservoir of row v by
        * x * N_v,best / N_v,rs; the x that brings it to zero */
       double need = -nn[rs] * n->comp[v * S + rs] / n->comp[v * S + best];
@@ -572,6 +604,11 @@ void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
       if (x == need) nn[rs] = 0.0;   /* drop the rounding residue */
     }
   }
+  return flags;
+}
+
+void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
+  (void)kro_postprocess_flags(n, E0, nn);
 }
 
 double kro_fastest_timescale(const kro_net *n, const double *y) {
@@ -601,10 +638,24 @@ static int cell_ok(const kro_net *n, const double *before, const double *y, doub
   return cell_element_residual(n, before, y) <= 1e-10;
 }
 
+/* The per-cell extras of kro_integrate_ex for one cell (pointers already
+ * offset to the cell; any may be NULL). */
+typedef struct {
+  double *h_hint;       /* in/out */
+  double *h_log;        /* [cap] with stride log_ld */
+  int64_t log_ld;
+  int32_t cap;
+  int32_t *h_log_n;
+  int32_t *post;
+} cell_extras;
+
 static int32_t integrate_cell(const kro_net *n, const kro_opts *o, double *nn,
-                              double *T, double rho, double dt, int32_t *st) {
-  const int S = n->S, N = S + 1;
+                              double *T, double rho, double dt, int32_t *st,
+                              const cell_extras *ex) {
+  const int S = n->S;
   double y0[KRO_MAXN], y[KRO_MAXN], atol[KRO_MAXN], E0[KRO_MAXN];
+  if (ex->h_log_n && o->mode != KRO_REPLAY) *ex->h_log_n = 0;
+  if (ex->post) *ex->post = 0;
   /* non-finite input: leave the cell as it came */
   int bad = !isfinite(*T) || !isfinite(dt) || !(dt >= 0.0);
   for (int s = 0; s < S; ++s) bad |= !isfinite(nn[s]);
@@ -624,30 +675,58 @@ static int32_t integrate_cell(const kro_net *n, const kro_opts *o, double *nn,
   for (int s = 0; s < S; ++s) atol[s] = o->floor * n_nuc;
   atol[S] = 0.0;
 
-  /* attempt 0, then the retry with a reduced initial step and tighter step
-   * control, then reversion to the pre-evolution values (Sec. 2.2.3) */
-  attempt_params ap[2] = {{dt, 0.9, 5.0}, {dt / 100.0, 0.5, 2.0}};
+  /* replay: the recorded substep lengths are the input; otherwise the
+   * accepted lengths are recorded (entries past the final count keep
+   * whatever an earlier attempt wrote) */
+  const double *replay = NULL;
+  int32_t n_replay = 0;
+  substep_log lg = {NULL, ex->log_ld, 0, 0, 0.0};
+  if (o->mode == KRO_REPLAY) {
+    if (!ex->h_log || !ex->h_log_n || *ex->h_log_n < 0 || *ex->h_log_n > ex->cap) return 2;
+    n_replay = *ex->h_log_n;
+    replay = ex->h_log;
+  } else if (ex->h_log) {
+    lg.h = ex->h_log;
+    lg.cap = ex->cap;
+  }
+
+  /* attempt 0 (first substep: the caller's hint when positive, else dt),
+   * then the retry with a reduced initial step and tighter step control,
+   * then reversion to the pre-evolution values (Sec. 2.2.3) */
+  double h0 = dt;
+  if (ex->h_hint && *ex->h_hint > 0.0 && isfinite(*ex->h_hint)) h0 = *ex->h_hint;
+  attempt_params ap[2] = {{h0, 0.9, 5.0}, {dt / 100.0, 0.5, 2.0}};
   int32_t status = 2;
   for (int a = 0; a < 2; ++a) {
-    if (integrate_attempt(n, o, y0, atol, dt, ap[a], y, st) == 0 && cell_ok(n, y0, y, n_nuc)) {
+    if (integrate_attempt(n, o, y0, atol, dt, ap[a], replay, ex->log_ld, n_replay, y, st, &lg) == 0 &&
+        cell_ok(n, y0, y, n_nuc)) {
       status = a;
       break;
     }
-    if (o->mode == KRO_FIXED) break;   /* a fixed sequence has no retry */
+    if (o->mode != KRO_ADAPTIVE) break;   /* a given sequence has no retry */
   }
   if (status == 2) return 2;
-  kro_postprocess(n, E0, y);
+  int flags = kro_postprocess_flags(n, E0, y);
   for (int s = 0; s < S; ++s) nn[s] = y[s];
   *T = y[S];
-  (void)N;
+  if (ex->post) *ex->post = flags;
+  if (o->mode != KRO_REPLAY && ex->h_log_n) *ex->h_log_n = lg.n;
+  if (ex->h_hint && o->mode == KRO_ADAPTIVE) *ex->h_hint = lg.h_next;
   return status;
 }
 
-int kro_integrate(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
-                  double *T, const double *rho, const double *dt, double dt_scalar,
-                  const kro_opts *o, int32_t *status, int32_t *cell_stats, int nthreads) {
+int kro_integrate_ex(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
+                     double *T, const double *rho, const double *dt, double dt_scalar,
+                     const kro_opts *o, int32_t *status, int32_t *cell_stats,
+                     const kro_extras *ex, int nthreads) {
   if (!n || !states || !T || ld < n_cells || n_cells < 0 || !o) return -1;
   if (o->mode == KRO_FIXED && o->n_fixed < 1) return -1;
+  if (o->mode != KRO_ADAPTIVE && o->mode != KRO_FIXED && o->mode != KRO_REPLAY) return -1;
+  kro_extras none;
+  memset(&none, 0, sizeof none);
+  if (!ex) ex = &none;
+  if (ex->h_log && (ex->h_log_ld < n_cells || ex->h_log_cap < 0)) return -1;
+  if (o->mode == KRO_REPLAY && (!ex->h_log || !ex->h_log_n)) return -1;
 #ifdef _OPENMP
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
@@ -658,7 +737,10 @@ int kro_integrate(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
     for (int s = 0; s < n->S; ++s) nn[s] = states[s * ld + c];
     double Tc = T[c];
     double step = dt ? dt[c] : dt_scalar;
-    int32_t code = integrate_cell(n, o, nn, &Tc, rho ? rho[c] : 0.0, step, st);
+    cell_extras ce = {ex->h_hint ? ex->h_hint + c : NULL, ex->h_log ? ex->h_log + c : NULL,
+                      ex->h_log_ld, ex->h_log_cap, ex->h_log_n ? ex->h_log_n + c : NULL,
+                      ex->post ? ex->post + c : NULL};
+    int32_t code = integrate_cell(n, o, nn, &Tc, rho ? rho[c] : 0.0, step, st, &ce);
     if (code != 2) {
       for (int s = 0; s < n->S; ++s) states[s * ld + c] = nn[s];
       T[c] = Tc;
@@ -668,4 +750,11 @@ int kro_integrate(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
   }
   (void)nthreads;
   return 0;
+}
+
+int kro_integrate(const kro_net *n, int64_t n_cells, double *states, int64_t ld,
+                  double *T, const double *rho, const double *dt, double dt_scalar,
+                  const kro_opts *o, int32_t *status, int32_t *cell_stats, int nthreads) {
+  return kro_integrate_ex(n, n_cells, states, ld, T, rho, dt, dt_scalar, o, status, cell_stats,
+                          NULL, nthreads);
 }

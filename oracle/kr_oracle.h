@@ -57,7 +57,10 @@ void kro_lu_solve(int N, const double *a, const int32_t *p, double *b);
 /* Brute-force Gaussian elimination with full (row and column) pivoting. */
 int kro_gauss_full_pivot(int N, const double *a, const double *b, double *x);
 
-enum { KRO_ADAPTIVE = 0, KRO_FIXED = 1 };
+/* Substep control: adaptive (error controller), fixed (n_fixed equal
+ * substeps), or replay (a given sequence of substep lengths per cell, no
+ * error control; a Newton failure reverts the cell). */
+enum { KRO_ADAPTIVE = 0, KRO_FIXED = 1, KRO_REPLAY = 2 };
 
 typedef struct {
   double rtol;        /* relative tolerance (error control and Newton) */
@@ -66,7 +69,7 @@ typedef struct {
   double rho_floor;   /* density floor for pre-processing (0: none) */
   int32_t max_newton;
   int32_t max_substeps;
-  int32_t mode;       /* KRO_ADAPTIVE or KRO_FIXED */
+  int32_t mode;       /* KRO_ADAPTIVE, KRO_FIXED or KRO_REPLAY */
   int32_t n_fixed;    /* substeps in fixed mode */
 } kro_opts;
 
@@ -81,6 +84,34 @@ int kro_integrate(const kro_net *net, int64_t n_cells, double *states,
                   int64_t ld, double *T, const double *rho, const double *dt,
                   double dt_scalar, const kro_opts *o, int32_t *status,
                   int32_t *cell_stats, int nthreads);
+
+/* Per-cell extras of kro_integrate_ex (every pointer may be NULL):
+ *   h_hint   [n_cells] in/out: first substep length of the first attempt
+ *            when positive and finite (else dt); on return the controller's
+ *            proposed length after the last accepted substep (adaptive mode,
+ *            cells not reverted; others keep their value)
+ *   h_log    [h_log_cap][h_log_ld]: the accepted substep lengths, in order,
+ *            of the attempt that produced the result (out), or the lengths
+ *            to replay (in, mode KRO_REPLAY)
+ *   h_log_n  [n_cells]: their number (out: may exceed h_log_cap, 0 for
+ *            reverted cells; in for KRO_REPLAY, <= h_log_cap)
+ *   post     [n_cells] out: post-processing flags (KRO_POST_*) */
+typedef struct {
+  double *h_hint;
+  double *h_log;
+  int64_t h_log_ld;
+  int32_t h_log_cap;
+  int32_t *h_log_n;
+  int32_t *post;
+} kro_extras;
+
+enum { KRO_POST_CLIPPED = 1,      /* stage 1 set a negative abundance to 0 */
+       KRO_POST_BROKEN_UP = 2 };  /* stage 3 broke up a species */
+
+int kro_integrate_ex(const kro_net *net, int64_t n_cells, double *states,
+                     int64_t ld, double *T, const double *rho, const double *dt,
+                     double dt_scalar, const kro_opts *o, int32_t *status,
+                     int32_t *cell_stats, const kro_extras *ex, int nthreads);
 
 /* One backward-Euler substep of length h from yn (plain initial guess);
  * returns 0 on convergence (y holds the root) or -1.  *iters counts
@@ -98,6 +129,8 @@ void kro_element_residual(const kro_net *net, int64_t n_cells,
 /* Post-processing stages 1-3 on one cell's abundances, given the conserved
  * totals E0[n_rows] of the initial state. */
 void kro_postprocess(const kro_net *net, const double *E0, double *n);
+/* The same, returning which stages changed anything (KRO_POST_*). */
+int kro_postprocess_flags(const kro_net *net, const double *E0, double *n);
 
 /* Fastest self-coupling timescale at y: 1 / max(max_s |d f_s/d n_s|,
  * |dQ/dT| / c_V), capped at 1e7 s (also returned when it is undefined). */

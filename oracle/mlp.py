@@ -12,6 +12,14 @@ exact FP64 gradient of the same function (pinned by finite differences).
 Parameter layout: for each linear layer, W [fan_out][fan_in] row-major then
 b [fan_out], flattened in layer order.  Normalisation block: mu_in[16],
 sd_in[16], mu_out[16], sd_out[16].
+
+The map between a cell and the network (the learned Newton start of one
+backward-Euler substep; the paper names a learned solver as the route to
+acceleration, Sec. 5): inputs are log10 max(n_s / n_nuc, 1e-20) for every
+species, log10 T and log10 h (n_nuc the nuclei density, sum over species of
+atoms times abundance); outputs are the change of those species logarithms
+and of log10 T over the substep; the starting point maps back as
+n_nuc 10^(x_s + dx_s) and T 10^(dlog10 T).  All in FP64 here.
 """
 from __future__ import annotations
 
@@ -111,3 +119,54 @@ def adam_step(w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1 - beta1 ** step)
     vh = v / (1 - beta2 ** step)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# the cell <-> network map (features, targets, starting point)
+# --------------------------------------------------------------------------
+
+FRACTION_FLOOR = 1e-20
+
+
+def nuclei(atoms, n):
+    """n_nuc per cell: sum_s atoms_s n_s for n [S, cells]."""
+    return np.asarray(atoms, np.float64) @ np.asarray(n, np.float64)
+
+
+def log_fractions(atoms, n):
+    """log10 max(n_s / n_nuc, 1e-20), [S, cells]."""
+    n = np.asarray(n, np.float64)
+    return np.log10(np.maximum(n / nuclei(atoms, n)[None, :], FRACTION_FLOOR))
+
+
+def features(atoms, n, T, h):
+    """Raw inputs [cells, S + 2] (FP64) of cells n [S, cells], T [cells] and
+    substep lengths h [cells] (or a scalar)."""
+    lf = log_fractions(atoms, n)
+    T = np.asarray(T, np.float64)
+    h = np.broadcast_to(np.asarray(h, np.float64), T.shape)
+    return np.concatenate([lf.T, np.log10(T)[:, None], np.log10(h)[:, None]], axis=1)
+
+
+def targets(atoms, n_before, T_before, n_after, T_after):
+    """Raw targets [cells, S + 1]: change of the species logarithms and of
+    log10 T from before to after."""
+    d = log_fractions(atoms, n_after) - log_fractions(atoms, n_before)
+    dT = np.log10(np.asarray(T_after, np.float64)) - np.log10(np.asarray(T_before, np.float64))
+    return np.concatenate([d.T, dT[:, None]], axis=1)
+
+
+def starting_point(atoms, n, T, out, norm):
+    """The Newton starting point [S + 1, cells] from the network's
+    standardised outputs out [cells, S + 1]: the predicted change
+    dx = out * sd_out + mu_out applied to the log fractions and to log10 T."""
+    n = np.asarray(n, np.float64)
+    S = n.shape[0]
+    out = np.asarray(out, np.float64)
+    norm = np.asarray(norm, np.float64)
+    dx = out * norm[48:48 + S + 1][None, :] + norm[32:32 + S + 1][None, :]
+    nn = nuclei(atoms, n)
+    y = np.empty((S + 1, n.shape[1]))
+    y[:S] = nn[None, :] * 10.0 ** (log_fractions(atoms, n) + dx[:, :S].T)
+    y[S] = np.asarray(T, np.float64) * 10.0 ** dx[:, S]
+    return y

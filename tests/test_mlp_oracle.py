@@ -2,6 +2,8 @@
 independent conversion, GELU against torch's tanh-approximate GELU, the
 analytic gradient against finite differences (rounding off), and the Adam
 step against torch.optim.Adam."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -92,3 +94,63 @@ def test_adam_matches_torch():
         wt.grad = torch.tensor(g)
         opt.step()
         np.testing.assert_allclose(w, wt.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# the cell <-> network map
+# --------------------------------------------------------------------------
+
+def test_features_hand_worked():
+    """atoms (1, 2): n = (1e3, 499500) has n_nuc = 1e3 + 2 * 499500 = 1e6,
+    so the fractions are 1e-3 (log -3) and 0.4995; a missing species sits on
+    the 1e-20 floor (log -20); T = 1e3 K gives 3, h = 1e-4 s gives -4."""
+    atoms = np.array([1.0, 2.0])
+    n = np.array([[1e3, 0.0], [499500.0, 5e5]])
+    X = mlp.features(atoms, n, np.array([1e3, 10.0]), np.array([1e-4, 1.0]))
+    assert X.shape == (2, 4)
+    assert X[0, 0] == -3.0 and X[0, 1] == pytest.approx(math.log10(0.4995), abs=1e-15)
+    assert X[0, 2] == 3.0 and X[0, 3] == -4.0
+    # second cell: all nuclei in the diatomic species (fraction 1/2), the
+    # atom is absent
+    assert X[1, 0] == -20.0 and X[1, 1] == pytest.approx(math.log10(0.5), abs=1e-15)
+    assert X[1, 2] == 1.0 and X[1, 3] == 0.0
+    # a scalar step applies to every cell
+    np.testing.assert_array_equal(mlp.features(atoms, n, np.array([1e3, 10.0]), 1e-4)[:, 3], -4.0)
+
+
+def test_targets_hand_worked():
+    """Same nuclei (1e6) before and after: the atom falls from 1e3 to 1e2
+    (change -1), T doubles (change log10 2)."""
+    atoms = np.array([1.0, 2.0])
+    nb = np.array([[1e3], [499500.0]])
+    na = np.array([[1e2], [499950.0]])
+    Y = mlp.targets(atoms, nb, np.array([1e3]), na, np.array([2e3]))
+    assert Y[0, 0] == pytest.approx(-1.0, abs=1e-15)
+    assert Y[0, 1] == pytest.approx(math.log10(0.49995) - math.log10(0.4995), abs=1e-15)
+    assert Y[0, 2] == pytest.approx(math.log10(2.0), abs=1e-15)
+
+
+def test_starting_point_identity_and_round_trip():
+    """A zero predicted change returns the state (species on the floor come
+    back at 1e-20 n_nuc); the change between two states, fed back through
+    the output normalisation, lands on the second state."""
+    atoms = np.array([1.0, 2.0])
+    nb = np.array([[1e3, 0.0], [499500.0, 5e5]])
+    Tb = np.array([1e3, 10.0])
+    norm = np.zeros(64)
+    norm[48:] = 1.0
+    y = mlp.starting_point(atoms, nb, Tb, np.zeros((2, 3)), norm)
+    np.testing.assert_allclose(y[:, 0], [1e3, 499500.0, 1e3], rtol=1e-14)
+    np.testing.assert_allclose(y[:, 1], [1e-20 * 1e6, 5e5, 10.0], rtol=1e-14)
+    na = np.array([[1e2, 3e2], [499950.0, 499850.0]])
+    Ta = np.array([2e3, 12.5])
+    Y = mlp.targets(atoms, nb, Tb, na, Ta)
+    # through a non-trivial output normalisation: out = (Y - mu) / sd
+    norm[32:35] = [0.3, -0.2, 0.1]
+    norm[48:51] = [2.0, 0.5, 4.0]
+    out = (Y - norm[32:35]) / norm[48:51]
+    y = mlp.starting_point(atoms, nb, Tb, out, norm)
+    # the atom of cell 1 starts on the floor, so its change is measured from
+    # 1e-20 n_nuc: the round trip is exact for it as well
+    np.testing.assert_allclose(y[:2], na, rtol=1e-12)
+    np.testing.assert_allclose(y[2], Ta, rtol=1e-13)
