@@ -196,6 +196,27 @@ enum { KR_ADAPTIVE = 0, KR_FIXED_STEP = 1 }; /* substep control */
  * default KR_ORDER_INPUT; the autotuner measures both. */
 enum { KR_ORDER_INPUT = 0, KR_ORDER_WORK = 1 };
 
+/* Totals of one kr_chem_integrate call (requested through kr_options.stats;
+ * the call then synchronises its stream).  Counts cover both attempts of a
+ * retried cell. */
+typedef struct {
+  int64_t cells;             /* cells finished (every status) */
+  int64_t substeps;          /* accepted substeps */
+  int64_t newton_iterations;
+  int64_t rejected;          /* substeps rejected by the error control */
+  int64_t newton_failures;
+  int64_t retried;           /* cells with status 1 */
+  int64_t reverted;          /* cells with status 2 (the paper's "terminate"
+                                decision is the caller's: check this) */
+  int64_t refinement_sweeps; /* FP32 solves in refinement sweeps */
+  int64_t fp64_fallbacks;    /* systems refinement did not settle (FP64 LU) */
+  int64_t guess_fallbacks;   /* learned starts that Newton abandoned */
+  double max_element_residual; /* over the cells not reverted, after
+                                  post-processing, relative to the
+                                  pre-processed input (see
+                                  kr_element_residual) */
+} kr_stats;
+
 typedef struct {
   int32_t precision;    /* KR_FP64 (default) or KR_FP32LU_REFINE: LU in FP32,
                            residual, iterative refinement and the element
@@ -225,6 +246,28 @@ typedef struct {
                            [3] FP32 solves in refinement sweeps (FP32 LU
                            form), [4] linear systems that refinement did
                            not settle and FP64 LU solved, [5..7] reserved */
+  double *h_hint;       /* device [n_cells] in/out, or NULL.  In: the first
+                           substep length of a cell's first attempt, used
+                           when positive and finite (else dt), so that a
+                           simulation loop carries each cell's step from one
+                           call (fluid step, Sec. 2.2.2) to the next.  Out
+                           (adaptive mode, cells not reverted): the
+                           controller's proposed length after the last
+                           accepted substep -- its update of that substep,
+                           or the length before that substep was clipped to
+                           land on dt if larger.  Other cells keep it. */
+  double *h_log;        /* device [h_log_cap][h_log_ld], or NULL: the
+                           accepted substep lengths, in order, of the
+                           attempt that produced each cell's result (the
+                           first h_log_cap of them; entries past the count
+                           are unspecified) */
+  int64_t h_log_ld;     /* >= n_cells when h_log is given */
+  int32_t h_log_cap;    /* >= 0 */
+  int32_t reserved;
+  int32_t *h_log_n;     /* device [n_cells] or NULL: the number of accepted
+                           substeps of that attempt (may exceed h_log_cap;
+                           0 for reverted cells and cells with dt = 0) */
+  kr_stats *stats;      /* host, or NULL: totals of this call (synchronises) */
 } kr_options;
 
 void kr_default_options(kr_options *opt);
@@ -275,6 +318,21 @@ int kr_work_order(const kr_network *net, int64_t n_cells, const double *states, 
 int kr_element_residual(const kr_network *net, int64_t n_cells,
                         const double *before, const double *after, int64_t ld,
                         double *resid, double *max_out, kr_stream_t stream);
+
+/* Post-processing alone (Sec. 2.2.3), the three stages kr_chem_integrate
+ * applies to each integrated cell: (1) negative abundances to zero; (2) each
+ * conserved row's reservoir species absorbs the difference between the
+ * row's total in `before` (after pre-processing: negatives clipped) and in
+ * `after`; (3) a reservoir left negative is refilled by breaking up, just
+ * enough, the most abundant species that carries its row with its sign
+ * (into the reservoirs of all that species' rows), then the next one.
+ *   before  device [n_species][ld] (read only)
+ *   after   device [n_species][ld], post-processed in place
+ *   flags   device [n_cells] int32 or NULL: bit 0 a clip, bit 1 a break-up
+ * Non-finite values propagate.  Temperatures are not involved.
+ * Errors: KR_EINVAL, KR_EDEVICE. */
+int kr_postprocess(const kr_network *net, int64_t n_cells, const double *before,
+                   double *after, int64_t ld, int32_t *flags, kr_stream_t stream);
 
 /* Fastest self-coupling timescale of each cell at its (pre-processed) input
  * state, out[c] = 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s

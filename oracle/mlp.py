@@ -94,6 +94,26 @@ class MLP:
         out, _ = self.forward(w, norm, X)
         return float(np.mean((out - self.targets(norm, Y)) ** 2))
 
+    def gradient_scales(self, w, norm, X, Y):
+        """Per-entry scale of the gradient's rounding error: the gradient's
+        sums taken over absolute values (|bf16(dz)|^T |a| for weights,
+        sum |dz| for biases), same layout as the gradient.  An entry's
+        accumulation error is a small multiple of its scale whatever the
+        cancellation between the summed terms."""
+        out, (P, acts, zs) = self.forward(w, norm, X)
+        t = self.targets(norm, Y)
+        B = out.shape[0]
+        d = 2.0 * (out - t) / (B * self.n_out)
+        scales = [None] * (self.layers + 1)
+        dz = d
+        for l in range(self.layers, -1, -1):
+            W, _ = P[l]
+            dzr = self.rnd(dz)
+            scales[l] = (np.abs(dzr).T @ np.abs(acts[l]), np.abs(dz).sum(axis=0))
+            if l > 0:
+                dz = (dzr @ self.rnd(W)) * gelu_grad(zs[l - 1])
+        return flatten(scales)
+
     def gradients(self, w, norm, X, Y):
         """(loss, flat gradient) of the mean squared error."""
         out, (P, acts, zs) = self.forward(w, norm, X)

@@ -32,7 +32,7 @@ KR_WIDE_MIN_SPECIES = 16
 
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns", "kr_network_layout",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
-            "kr_default_options", "kr_chem_integrate", "kr_element_residual",
+            "kr_default_options", "kr_chem_integrate", "kr_element_residual", "kr_postprocess",
             "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
             "kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
             "kr_guess_set_normalization", "kr_guess_features", "kr_guess_targets",
@@ -55,12 +55,27 @@ class _Desc(C.Structure):
                 ("T_min", C.c_double), ("T_max", C.c_double)]
 
 
+class Stats(C.Structure):
+    """kr_stats: totals of one kr_chem_integrate call."""
+    _fields_ = [("cells", C.c_int64), ("substeps", C.c_int64), ("newton_iterations", C.c_int64),
+                ("rejected", C.c_int64), ("newton_failures", C.c_int64), ("retried", C.c_int64),
+                ("reverted", C.c_int64), ("refinement_sweeps", C.c_int64),
+                ("fp64_fallbacks", C.c_int64), ("guess_fallbacks", C.c_int64),
+                ("max_element_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Options(C.Structure):
     """kr_options; defaults from kr_default_options."""
     _fields_ = [("precision", C.c_int32), ("mode", C.c_int32), ("n_fixed", C.c_int32),
                 ("max_newton", C.c_int32), ("max_substeps", C.c_int32), ("order", C.c_int32),
                 ("floor", C.c_double), ("newton_tol", C.c_double), ("rho_floor", C.c_double),
-                ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p)]
+                ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p),
+                ("h_hint", C.c_void_p), ("h_log", C.c_void_p), ("h_log_ld", C.c_int64),
+                ("h_log_cap", C.c_int32), ("reserved", C.c_int32), ("h_log_n", C.c_void_p),
+                ("stats", C.POINTER(Stats))]
 
 
 class BuildOpts(C.Structure):
@@ -110,6 +125,8 @@ def lib():
         L.kr_element_residual.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                           C.c_int64, C.c_void_p, C.POINTER(C.c_double),
                                           C.c_void_p]
+        L.kr_postprocess.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_void_p, C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
         vp, i64 = C.c_void_p, C.c_int64
         L.kr_default_build_options.argtypes = [C.POINTER(BuildOpts)]
@@ -271,13 +288,40 @@ def _stream_ptr(stream):
 
 def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
                    rtol: float = 1e-6, opts: Options | None = None, status=None,
-                   cell_stats=None, stream=None) -> None:
+                   cell_stats=None, stream=None, h_hint=None, h_log=None, h_log_n=None,
+                   stats: bool = False):
     """kr_chem_integrate on device tensors.
 
     states: float64 [S, ld] with unit stride along cells (row stride = ld);
     T, rho, dt: float64 [n_cells]; status: int32 [n_cells];
-    cell_stats: int32 [n_cells, 4].  Asynchronous on the stream."""
+    cell_stats: int32 [n_cells, 4]; h_hint: float64 [n_cells] in/out;
+    h_log: float64 [cap, ld] (unit stride along cells) with h_log_n int32
+    [n_cells].  Asynchronous on the stream unless stats=True, which returns
+    the call's kr_stats totals as a dict (and synchronises)."""
     import torch
+    if h_hint is not None or h_log is not None or h_log_n is not None or stats:
+        o = Options.from_buffer_copy(opts if opts is not None else default_options())
+        n_cells = int(T.numel())
+        if h_hint is not None:
+            if h_hint.numel() != n_cells or not h_hint.is_contiguous():
+                raise ValueError("h_hint must be float64 [n_cells]")
+            o.h_hint = _dev_ptr(h_hint, torch.float64, "h_hint")
+        if h_log is not None:
+            if h_log.dim() != 2 or h_log.stride(1) != 1 or h_log.shape[1] < n_cells:
+                raise ValueError("h_log must be [cap, ld >= n_cells] with unit stride along cells")
+            o.h_log = _dev_ptr(h_log, torch.float64, "h_log")
+            o.h_log_ld = int(h_log.stride(0)) if h_log.shape[0] > 1 else int(h_log.shape[1])
+            o.h_log_cap = int(h_log.shape[0])
+        if h_log_n is not None:
+            if h_log_n.numel() != n_cells:
+                raise ValueError("h_log_n must be int32 [n_cells]")
+            o.h_log_n = _dev_ptr(h_log_n, torch.int32, "h_log_n")
+        st = Stats()
+        if stats:
+            o.stats = C.pointer(st)
+        chem_integrate(net, states, T, rho=rho, dt=dt, dt_scalar=dt_scalar, rtol=rtol, opts=o,
+                       status=status, cell_stats=cell_stats, stream=stream)
+        return st.as_dict() if stats else None
     n_cells = int(T.numel())
     if states.dim() != 2 or states.shape[0] != net.n_species or states.stride(1) != 1:
         raise ValueError("states must be [n_species, ld] with unit stride along cells")
@@ -297,6 +341,21 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
         _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar), float(rtol), C.byref(o),
         _dev_ptr(status, torch.int32, "status"), _dev_ptr(cell_stats, torch.int32, "cell_stats"),
         _stream_ptr(stream)))
+
+
+def postprocess(net: Network, before, after, flags=None, stream=None) -> None:
+    """kr_postprocess: the three post-processing stages (Sec. 2.2.3) of
+    `after` in place, with the conserved totals of `before` (both float64
+    [S, ld], unit stride along cells, same ld); flags int32 [n_cells] or
+    None."""
+    import torch
+    if after.dim() != 2 or after.stride(1) != 1 or before.stride() != after.stride() or \
+            before.shape != after.shape:
+        raise ValueError("before/after must be [n_species, ld] with the same layout")
+    n = int(after.shape[1]) if flags is None else int(flags.numel())
+    _check(lib().kr_postprocess(net.handle, n, _dev_ptr(before, torch.float64, "before"),
+                                _dev_ptr(after, torch.float64, "after"), int(after.stride(0)),
+                                _dev_ptr(flags, torch.int32, "flags"), _stream_ptr(stream)))
 
 
 def work_order(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
@@ -359,9 +418,11 @@ class Multi:
         return int(launches), int(cap.value)
 
     def integrate(self, batches, rtol=1e-6, opts: Options | None = None, use_graph=False,
-                  stream=None):
+                  stream=None, stats: bool = False):
         """batches: list of dicts with states [S_k, ld], T, and optional
-        rho, dt, dt_scalar, status, cell_stats (device tensors)."""
+        rho, dt, dt_scalar, status, cell_stats (device tensors).  stats=True
+        returns the launch's kr_stats totals (all networks) as a dict and
+        synchronises."""
         import torch
         arr = (Batch * len(batches))()
         for k, b in enumerate(batches):
@@ -375,9 +436,13 @@ class Multi:
                            _dev_ptr(b.get("dt"), torch.float64, "dt"), float(b.get("dt_scalar", 0.0)),
                            _dev_ptr(b.get("status"), torch.int32, "status"),
                            _dev_ptr(b.get("cell_stats"), torch.int32, "cell_stats"))
-        o = opts if opts is not None else default_options()
+        o = Options.from_buffer_copy(opts if opts is not None else default_options())
+        st = Stats()
+        if stats:
+            o.stats = C.pointer(st)
         _check(lib().kr_chem_integrate_multi(self._h, arr, float(rtol), C.byref(o),
                                              int(bool(use_graph)), _stream_ptr(stream)))
+        return st.as_dict() if stats else None
 
 
 def element_residual(net: Network, before, after, resid=None, want_max: bool = False,

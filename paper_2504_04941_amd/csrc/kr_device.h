@@ -309,11 +309,18 @@ __device__ __forceinline__ double kr_element_resid(const double (&y0)[KR_N], con
  * reservoir left negative is refilled by breaking up the most abundant
  * species carrying that row (with the reservoir's sign) into the reservoirs
  * of all its rows, just enough.  All indexing is static: data-dependent
- * choices are applied through predicated updates. */
-__device__ __forceinline__ void kr_postprocess(const double (&E0)[KR_NROWS > 0 ? KR_NROWS : 1],
-                                               double (&y)[KR_N]) {
+ * choices are applied through predicated updates, and the break-up loop
+ * runs a wave-uniform number of trips (while any lane still has a negative
+ * reservoir), each lane's trip predicated.  Returns which stages changed
+ * anything: 1 a clip, 2 a break-up. */
+__device__ __forceinline__ int kr_postprocess(const double (&E0)[KR_NROWS > 0 ? KR_NROWS : 1],
+                                              double (&y)[KR_N]) {
+  int flags = 0;
 #pragma unroll
-  for (int s = 0; s < KR_S; ++s) y[s] = y[s] < 0.0 ? 0.0 : y[s];
+  for (int s = 0; s < KR_S; ++s) {
+    flags |= y[s] < 0.0 ? 1 : 0;
+    y[s] = y[s] < 0.0 ? 0.0 : y[s];
+  }
 #pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) {
     double E = 0.0;
@@ -327,7 +334,10 @@ __device__ __forceinline__ void kr_postprocess(const double (&E0)[KR_NROWS > 0 ?
     const int rs = kr_res[v];
     const int sr = kr_comp[v][rs] > 0 ? 1 : -1;
     unsigned long long used = 0ull;
-    for (int it = 0; it < KR_S && y[rs] < 0.0; ++it) {
+#pragma unroll 1
+    for (int it = 0; it < KR_S; ++it) {
+      const bool neg = y[rs] < 0.0;
+      if (!__any(neg)) break;                       /* wave-uniform exit */
       int best = -1;
       double bval = 0.0;
 #pragma unroll
@@ -338,34 +348,42 @@ __device__ __forceinline__ void kr_postprocess(const double (&E0)[KR_NROWS > 0 ?
         best = cand ? s : best;
         bval = cand ? y[s] : bval;
       }
-      if (best < 0) break;
-      used |= 1ull << best;
-      double na = 0.0;
+      /* this lane's trip acts only while its reservoir is negative and a
+       * species is left to break up */
+      const bool act = neg && best >= 0;
+      double na = 1.0;
 #pragma unroll
       for (int s = 0; s < KR_S; ++s) na = (s == best) ? (double)kr_comp[v][s] : na;
       const double need = -y[rs] * kr_comp[v][rs] / na;
-      const double x = need < bval ? need : bval;
+      const double x = act ? (need < bval ? need : bval) : 0.0;
+      used |= act ? (1ull << (best & 63)) : 0ull;
+      flags |= act ? 2 : 0;
 #pragma unroll
       for (int s = 0; s < KR_S; ++s)
-        if (s == best) y[s] -= x;
+        if (s == best && act) y[s] -= x;
 #pragma unroll
       for (int u = 0; u < KR_NROWS; ++u) {
         double au = 0.0;
 #pragma unroll
         for (int s = 0; s < KR_S; ++s) au = (s == best) ? (double)kr_comp[u][s] : au;
-        y[kr_res[u]] += x * au / kr_comp[u][kr_res[u]];
+        if (act) y[kr_res[u]] += x * au / kr_comp[u][kr_res[u]];
       }
-      if (x == need) y[rs] = 0.0;
+      if (act && x == need) y[rs] = 0.0;
     }
   }
+  return flags;
 }
 
-/* Weighted element projection of a Newton update (FP32 form): removes the
- * part of d_S that changes conserved-row totals, d <- d - W N^T (N W N^T)^-1
- * N d with W = diag(max(|y_s|, atol)).  The exact Newton update of a
- * conserving network already satisfies N d = 0; this restores it after the
- * FP32 factorisation.  (The paper's projector P = V V^T is the W = I case.) */
-__device__ __forceinline__ void kr_project(const double (&y)[KR_N], double atol, double (&d)[KR_N]) {
+/* Weighted element projection of a Newton update (FP32 form): corrects d_S
+ * so that the new iterate y + d carries the conserved totals of the substep
+ * start y_n, d <- d - W N^T (N W N^T)^-1 (N d + N (y - y_n)) with W =
+ * diag(max(|y_s|, atol)).  The exact Newton update of a conserving network
+ * satisfies N (y + d) = N y_n (the rows of N annihilate the rates), whatever
+ * the starting point -- a learned guess need not conserve; this restores it
+ * after the FP32 factorisation.  (The paper's projector P = V V^T is the
+ * W = I case, applied to a d whose start already conserves.) */
+__device__ __forceinline__ void kr_project(const double (&y)[KR_N], const double (&yn)[KR_N], double atol,
+                                           double (&d)[KR_N]) {
   if (KR_NROWS == 0) return;
   constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
   double W[KR_S];
@@ -377,7 +395,7 @@ __device__ __forceinline__ void kr_project(const double (&y)[KR_N], double atol,
     double t = 0.0;
 #pragma unroll
     for (int s = 0; s < KR_S; ++s)
-      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * d[s];
+      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * (d[s] + (y[s] - yn[s]));
     r[a] = t;
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
@@ -431,8 +449,12 @@ __device__ __forceinline__ void kr_project(const double (&y)[KR_N], double atol,
 struct KrLane {
   long long cell;
   KrSlot y, yn, gn;             /* iterate, substep start and its rates: LDS */
+  KrSlot hx;                    /* LDS: [0] the controller's length before the
+                                   last substep was clipped to land on dt,
+                                   then the proposed next length */
   double h, t, dt, atol, eps_n, prev, safety, growth;
   int phase, attempt, k, grow, attempts, fin;
+  int acc0;                     /* accepted substeps before this attempt */
   int gstate;                   /* 1 guess pending, 2 Newton running from it */
   int acc, iters, rej, nfail;
 };
@@ -445,20 +467,46 @@ __device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLane &L, c
   if (p.mode == 1) {
     L.h = L.dt / (double)p.n_fixed;
   } else if (L.attempt == 0) {
-    L.h = L.dt; L.safety = 0.9; L.growth = 5.0;
+    /* the caller's first-substep length when positive and finite (a cell
+     * carries its step across calls), else dt */
+    double h0 = L.dt;
+    if (p.h_hint) {
+      const double hh = p.h_hint[L.cell];
+      h0 = (hh > 0.0 && kr_finite(hh)) ? hh : h0;
+    }
+    L.h = h0; L.safety = 0.9; L.growth = 5.0;
   } else {
     L.h = L.dt / 100.0; L.safety = 0.5; L.growth = 2.0;
   }
   L.attempts = 0;
   L.fin = 0;
+  L.acc0 = L.acc;
   L.phase = KR_PH_FRESH;
 }
 
-__device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLane &L, int code) {
+/* Status, statistics, substep-log count and per-call totals of a finished
+ * cell (nlog: accepted substeps of the attempt that produced the result, 0
+ * for a reverted cell or one with nothing to integrate; resid: its element
+ * residual after post-processing, 0 if it has none). */
+__device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLane &L, int code, int nlog,
+                                                 double resid) {
   if (p.status) p.status[L.cell] = code;
   if (p.cell_stats) {
     int *st = p.cell_stats + 4 * L.cell;
     st[0] = L.acc; st[1] = L.iters; st[2] = L.rej; st[3] = L.nfail;
+  }
+  if (p.h_log_n) p.h_log_n[L.cell] = nlog;
+  if (p.totals) {
+    unsigned long long *t = p.totals;
+    atomicAdd(&t[KR_TOT_CELLS], 1ull);
+    atomicAdd(&t[KR_TOT_SUBSTEPS], (unsigned long long)L.acc);
+    atomicAdd(&t[KR_TOT_ITERS], (unsigned long long)L.iters);
+    atomicAdd(&t[KR_TOT_REJECTED], (unsigned long long)L.rej);
+    atomicAdd(&t[KR_TOT_NFAIL], (unsigned long long)L.nfail);
+    if (code == 1) atomicAdd(&t[KR_TOT_RETRIED], 1ull);
+    if (code == 2) atomicAdd(&t[KR_TOT_REVERTED], 1ull);
+    /* non-negative doubles order like their bit patterns */
+    if (resid > 0.0) atomicMax(&t[KR_TOT_MAXRESID], (unsigned long long)__double_as_longlong(resid));
   }
 }
 
@@ -472,7 +520,7 @@ __device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) 
     L.gstate = 0;
     kr_start_attempt(p, L, y0);
   } else {
-    kr_write_outcome(p, L, 2);
+    kr_write_outcome(p, L, 2, 0, 0.0);
     L.phase = KR_PH_NONE;
   }
 }
@@ -503,7 +551,8 @@ __device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
 #pragma unroll
   for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = y[s];
   p.T[L.cell] = y[KR_S];
-  kr_write_outcome(p, L, L.attempt);
+  if (p.h_hint && p.mode == 0) p.h_hint[L.cell] = L.hx[0];
+  kr_write_outcome(p, L, L.attempt, L.acc - L.acc0, p.totals ? kr_element_resid(y0, y) : 0.0);
   L.phase = KR_PH_NONE;
 }
 
@@ -521,7 +570,7 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
   L.gstate = p.guess ? 1 : 0;
   double y0[KR_N], dt;
   if (!kr_load_input(p, L.cell, y0, dt)) {        /* non-finite input: revert */
-    kr_write_outcome(p, L, 2);
+    kr_write_outcome(p, L, 2, 0, 0.0);
     L.phase = KR_PH_NONE;
     return true;
   }
@@ -530,7 +579,7 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
 #pragma unroll
     for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = y0[s];
     p.T[L.cell] = y0[KR_S];
-    kr_write_outcome(p, L, 0);
+    kr_write_outcome(p, L, 0, 0, 0.0);
     L.phase = KR_PH_NONE;
     return true;
   }
@@ -568,19 +617,21 @@ __device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
 
 template <bool MIXED>
 __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
-  __shared__ double s_y[KR_N * 64], s_yn[KR_N * 64], s_gn[KR_N * 64];
+  __shared__ double s_y[KR_N * 64], s_yn[KR_N * 64], s_gn[KR_N * 64], s_hx[64];
   KrLane L;
   L.cell = -1;
   L.phase = KR_PH_NONE;
   L.y.base = s_y + threadIdx.x;
   L.yn.base = s_yn + threadIdx.x;
   L.gn.base = s_gn + threadIdx.x;
+  L.hx.base = s_hx + threadIdx.x;
+  L.hx[0] = 0.0;
   bool exhausted = false;
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) { L.y[i] = 1.0; L.yn[i] = 1.0; L.gn[i] = 0.0; }
   L.h = L.t = L.dt = L.atol = L.eps_n = L.prev = 0.0;
   L.safety = 0.9; L.growth = 5.0;
-  L.attempt = L.k = L.grow = L.attempts = L.fin = L.gstate = 0;
+  L.attempt = L.k = L.grow = L.attempts = L.fin = L.gstate = L.acc0 = 0;
   L.acc = L.iters = L.rej = L.nfail = 0;
   unsigned long long *swaps = p.counters ? &p.counters[2] : nullptr;
 
@@ -607,6 +658,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) L.yn[i] = yv[i];
         L.eps_n = yv[KR_S] * cv;
+        if (p.h_log && L.acc - L.acc0 < p.h_log_cap) p.h_log[(long long)(L.acc - L.acc0) * p.h_log_ld + L.cell] = L.h;
         L.acc++;
         if (L.acc >= p.n_fixed) kr_finish_cell(p, L);
         else L.phase = KR_PH_START;
@@ -631,12 +683,18 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
             L.gn[i] = i < KR_S ? g[i] : g[KR_S] * icv;
           }
           L.eps_n = yv[KR_S] * cv;
+          if (p.h_log && L.acc - L.acc0 < p.h_log_cap) p.h_log[(long long)(L.acc - L.acc0) * p.h_log_ld + L.cell] = L.h;
           L.acc++;
+          const double hnew = L.h * fmin(L.growth, fmax(0.2, L.safety / sqrt(fmax(err, 1e-10))));
           if (L.fin) {
+            /* proposed next length: the controller's update of this
+             * substep, or the unclipped length if that was larger */
+            const double hf = L.hx[0];
+            L.hx[0] = hf > hnew ? hf : hnew;
             kr_finish_cell(p, L);
           } else {
             L.t += L.h;
-            L.h *= fmin(L.growth, fmax(0.2, L.safety / sqrt(fmax(err, 1e-10))));
+            L.h = hnew;
             L.phase = KR_PH_START;
           }
         } else {
@@ -660,7 +718,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
           go = false;
         } else {
           L.fin = 0;
-          if (L.h >= L.dt - L.t) { L.h = L.dt - L.t; L.fin = 1; }
+          if (L.h >= L.dt - L.t) { L.hx[0] = L.h; L.h = L.dt - L.t; L.fin = 1; }
           else if (L.h < 1e-12 * L.dt) go = false;
         }
       }
@@ -800,10 +858,10 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
             for (int i = 0; i < KR_N; ++i) d[i] = b[i];
           }
         }
-        double yc[KR_N];
+        double yc[KR_N], ync[KR_N];
 #pragma unroll
-        for (int i = 0; i < KR_N; ++i) yc[i] = L.y[i];
-        kr_project(yc, L.atol, d);
+        for (int i = 0; i < KR_N; ++i) { yc[i] = L.y[i]; ync[i] = L.yn[i]; }
+        kr_project(yc, ync, L.atol, d);
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) b[i] = d[i];
       }
@@ -893,7 +951,45 @@ __device__ __forceinline__ void kr_timescale_body(const KrParams &p, double *out
   }
 }
 
+/* Post-processing alone (Sec. 2.2.3) of the states in p.states, with the
+ * conserved totals of `before` after pre-processing (negatives clipped); T
+ * is not touched.  flags[c] (or null): 1 a clip, 2 a break-up.  All lanes
+ * run every trip (cells past the end are predicated off). */
+__device__ __forceinline__ void kr_post_body(const KrParams &p, const double *before, int *flags) {
+  for (long long c0 = blockIdx.x * 64ll; c0 < p.n_cells; c0 += (long long)gridDim.x * 64ll) {
+    const long long c = c0 + threadIdx.x;
+    const bool in = c < p.n_cells;
+    double y0[KR_N], y[KR_N];
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) {
+      const double b = in ? before[(long long)s * p.ld + c] : 0.0;
+      y0[s] = b > 0.0 ? b : 0.0;
+      y[s] = in ? p.states[(long long)s * p.ld + c] : 0.0;
+    }
+    y0[KR_S] = y[KR_S] = 1.0;
+    double E0[KR_NROWS > 0 ? KR_NROWS : 1];
+#pragma unroll
+    for (int v = 0; v < KR_NROWS; ++v) {
+      double t = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s)
+        if (kr_comp[v][s] != 0) t += kr_comp[v][s] * y0[s];
+      E0[v] = t;
+    }
+    const int f = kr_postprocess(E0, y);
+    if (in) {
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + c] = y[s];
+      if (flags) flags[c] = f;
+    }
+  }
+}
+
 #ifndef KR_NO_KERNELS
+extern "C" __global__ void __launch_bounds__(64, 1) kr_post(KrParams p, const double *before, int *flags) {
+  kr_post_body(p, before, flags);
+}
+
 extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_timescale(KrParams p, double *out) {
   kr_timescale_body(p, out);
 }

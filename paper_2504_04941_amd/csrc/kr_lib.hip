@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -61,9 +62,24 @@ static int fail(int code, const char *fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  try {
+    g_err = buf;
+  } catch (...) {
+    /* no room for the message: the code still says what happened */
+  }
   return code;
 }
+
+/* Closes the try block of every extern "C" entry point: no C++ exception
+ * crosses the ABI (host containers of the network compiler and the graph
+ * cache can throw std::bad_alloc). */
+#define KR_CATCH                                                             \
+  catch (const std::bad_alloc &) {                                           \
+    return fail(KR_ENOMEM, "out of host memory");                            \
+  }                                                                          \
+  catch (...) {                                                              \
+    return fail(KR_EDEVICE, "unexpected host exception");                    \
+  }
 
 #define HIP_TRY(expr)                                                        \
   do {                                                                       \
@@ -102,13 +118,14 @@ struct kr_network {
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
-  hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr;
+  hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
   bool wide = false;            /* one wavefront per cell */
   OrderBufs ord;
   unsigned long long *d_counter = nullptr;
   unsigned long long *d_max = nullptr;
+  unsigned long long *d_totals = nullptr;   /* [16]: totals (KR_TOT_*), then statistics counters */
   int32_t *d_comp = nullptr;
 };
 
@@ -521,10 +538,13 @@ static int default_waves_per_eu() {
 }
 
 extern "C" void kr_default_build_options(kr_build_opts *o) {
-  if (!o) return;
-  o->waves_per_eu = default_waves_per_eu();
-  o->pivot_tau = 0.1f;
-  o->layout = KR_LAYOUT_AUTO;
+  try {
+    if (!o) return;
+    o->waves_per_eu = default_waves_per_eu();
+    o->pivot_tau = 0.1f;
+    o->layout = KR_LAYOUT_AUTO;
+  } catch (...) {
+  }
 }
 
 static int check_build_options(const kr_build_opts *o) {
@@ -581,6 +601,7 @@ static void release(kr_network *n) {
   order_free(n->ord);
   if (n->d_counter) (void)hipFree(n->d_counter);
   if (n->d_max) (void)hipFree(n->d_max);
+  if (n->d_totals) (void)hipFree(n->d_totals);
   if (n->d_comp) (void)hipFree(n->d_comp);
   if (n->module) (void)hipModuleUnload(n->module);
   delete n;
@@ -588,86 +609,107 @@ static void release(kr_network *n) {
 
 extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_opts *bopt,
                                     kr_network **out) {
-  if (!out) return fail(KR_EINVAL, "null output handle");
-  *out = nullptr;
-  kr_build_opts bo;
-  kr_default_build_options(&bo);
-  if (bopt) bo = *bopt;
-  int rc = check_build_options(&bo);
-  if (rc != KR_OK) return rc;
-  kr_network *n = new (std::nothrow) kr_network;
-  if (!n) return fail(KR_ENOMEM, "out of host memory");
-  rc = build_tables(desc, n);
-  if (rc != KR_OK) { delete n; return rc; }
-  n->build = bo;
-  n->build.waves_per_eu = auto_waves_per_eu(n, bo);
-  n->wide = use_wide(n, bo);
-  if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
-  n->source = full_source(n, bo);
-  std::vector<char> code;
-  std::string log;
-  rc = compile_source(n->source, code, log);
-  if (rc != KR_OK) { delete n; return rc; }
-  hipError_t e;
-#define CREATE_TRY(expr)                                                              \
-  do {                                                                                \
-    e = (expr);                                                                       \
-    if (e != hipSuccess) {                                                            \
-      rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                   \
-      release(n);                                                                     \
-      return rc;                                                                      \
-    }                                                                                 \
-  } while (0)
-  CREATE_TRY(hipGetDevice(&n->device));
-  CREATE_TRY(hipDeviceGetAttribute(&n->cu_count, hipDeviceAttributeMultiprocessorCount, n->device));
-  CREATE_TRY(hipModuleLoadData(&n->module, code.data()));
-  CREATE_TRY(hipModuleGetFunction(&n->f_fp64, n->module, "kr_integrate_fp64"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_fp32, n->module, "kr_integrate_fp32lu"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_reset, n->module, "kr_reset_counter"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_tau, n->module, "kr_timescale"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_keys, n->module, "kr_order_keys"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_scan, n->module, "kr_order_scan"));
-  CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
-  CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
-  CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
-  CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
-  CREATE_TRY(hipMalloc(&n->d_max, sizeof(unsigned long long)));
-  const size_t cb = sizeof(int32_t) * (n->comp.size() ? n->comp.size() : 1);
-  CREATE_TRY(hipMalloc(&n->d_comp, cb));
-  if (!n->comp.empty())
-    CREATE_TRY(hipMemcpy(n->d_comp, n->comp.data(), sizeof(int32_t) * n->comp.size(), hipMemcpyHostToDevice));
-#undef CREATE_TRY
-  *out = n;
-  return KR_OK;
+  try {
+    if (!out) return fail(KR_EINVAL, "null output handle");
+    *out = nullptr;
+    kr_build_opts bo;
+    kr_default_build_options(&bo);
+    if (bopt) bo = *bopt;
+    int rc = check_build_options(&bo);
+    if (rc != KR_OK) return rc;
+    kr_network *n = new (std::nothrow) kr_network;
+    if (!n) return fail(KR_ENOMEM, "out of host memory");
+    rc = build_tables(desc, n);
+    if (rc != KR_OK) { delete n; return rc; }
+    n->build = bo;
+    n->build.waves_per_eu = auto_waves_per_eu(n, bo);
+    n->wide = use_wide(n, bo);
+    if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
+    n->source = full_source(n, bo);
+    std::vector<char> code;
+    std::string log;
+    rc = compile_source(n->source, code, log);
+    if (rc != KR_OK) { delete n; return rc; }
+    hipError_t e;
+  #define CREATE_TRY(expr)                                                              \
+    do {                                                                                \
+      e = (expr);                                                                       \
+      if (e != hipSuccess) {                                                            \
+        rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                   \
+        release(n);                                                                     \
+        return rc;                                                                      \
+      }                                                                                 \
+    } while (0)
+    CREATE_TRY(hipGetDevice(&n->device));
+    CREATE_TRY(hipDeviceGetAttribute(&n->cu_count, hipDeviceAttributeMultiprocessorCount, n->device));
+    CREATE_TRY(hipModuleLoadData(&n->module, code.data()));
+    CREATE_TRY(hipModuleGetFunction(&n->f_fp64, n->module, "kr_integrate_fp64"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_fp32, n->module, "kr_integrate_fp32lu"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_reset, n->module, "kr_reset_counter"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_tau, n->module, "kr_timescale"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_keys, n->module, "kr_order_keys"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_scan, n->module, "kr_order_scan"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_post, n->module, "kr_post"));
+    CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
+    CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
+    CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
+    CREATE_TRY(hipMalloc(&n->d_max, sizeof(unsigned long long)));
+    CREATE_TRY(hipMalloc(&n->d_totals, 16 * sizeof(unsigned long long)));
+    const size_t cb = sizeof(int32_t) * (n->comp.size() ? n->comp.size() : 1);
+    CREATE_TRY(hipMalloc(&n->d_comp, cb));
+    if (!n->comp.empty())
+      CREATE_TRY(hipMemcpy(n->d_comp, n->comp.data(), sizeof(int32_t) * n->comp.size(), hipMemcpyHostToDevice));
+  #undef CREATE_TRY
+    *out = n;
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_network_create(const kr_network_desc *desc, kr_network **out) {
-  return kr_network_create_ex(desc, nullptr, out);
+  try {
+    return kr_network_create_ex(desc, nullptr, out);
+  } KR_CATCH
 }
 
-extern "C" void kr_network_destroy(kr_network *net) { release(net); }
+extern "C" void kr_network_destroy(kr_network *net) {
+  try {
+    release(net);
+  } catch (...) {
+  }
+}
 
-extern "C" int kr_network_unknowns(const kr_network *net) { return net ? net->S + 1 : KR_EINVAL; }
+extern "C" int kr_network_unknowns(const kr_network *net) {
+  try {
+    return net ? net->S + 1 : KR_EINVAL;
+  } KR_CATCH
+}
 
 extern "C" int kr_network_layout(const kr_network *net) {
-  return net ? (net->wide ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE) : KR_EINVAL;
+  try {
+    return net ? (net->wide ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE) : KR_EINVAL;
+  } KR_CATCH
 }
 
 extern "C" int kr_network_arrhenius(const kr_network *net, double *out) {
-  if (!net || !out) return fail(KR_EINVAL, "null argument");
-  std::memcpy(out, net->par.data(), sizeof(double) * net->par.size());
-  return KR_OK;
+  try {
+    if (!net || !out) return fail(KR_EINVAL, "null argument");
+    std::memcpy(out, net->par.data(), sizeof(double) * net->par.size());
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int64_t kr_network_source(const kr_network *net, char *buf, int64_t buf_len) {
-  if (!net) return fail(KR_EINVAL, "null network");
-  const int64_t need = (int64_t)net->source.size() + 1;
-  if (buf && buf_len > 0) {
-    const int64_t m = buf_len < need ? buf_len - 1 : need - 1;
-    std::memcpy(buf, net->source.data(), (size_t)m);
-    buf[m] = '\0';
-  }
-  return need;
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    const int64_t need = (int64_t)net->source.size() + 1;
+    if (buf && buf_len > 0) {
+      const int64_t m = buf_len < need ? buf_len - 1 : need - 1;
+      std::memcpy(buf, net->source.data(), (size_t)m);
+      buf[m] = '\0';
+    }
+    return need;
+  } KR_CATCH
 }
 
 /* Validation and code generation (and optionally the hipRTC compile) of a
@@ -675,29 +717,33 @@ extern "C" int64_t kr_network_source(const kr_network *net, char *buf, int64_t b
  * hosts without a GPU.  Returns KR_OK or the error create would return. */
 extern "C" int kr_network_check_ex(const kr_network_desc *desc, const kr_build_opts *bopt, int compile,
                                    char *src_buf, int64_t src_len) {
-  kr_network n;
-  int rc = build_tables(desc, &n);
-  if (rc != KR_OK) return rc;
-  kr_build_opts bo;
-  kr_default_build_options(&bo);
-  if (bopt) bo = *bopt;
-  if ((rc = check_build_options(&bo)) != KR_OK) return rc;
-  if (use_wide(&n, bo) && (rc = check_wide(&n)) != KR_OK) return rc;
-  const std::string src = full_source(&n, bo);
-  if (src_buf && src_len > 0) {
-    const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
-    std::memcpy(src_buf, src.data(), m);
-    src_buf[m] = '\0';
-  }
-  if (!compile) return KR_OK;
-  std::vector<char> code;
-  std::string log;
-  return compile_source(src, code, log);
+  try {
+    kr_network n;
+    int rc = build_tables(desc, &n);
+    if (rc != KR_OK) return rc;
+    kr_build_opts bo;
+    kr_default_build_options(&bo);
+    if (bopt) bo = *bopt;
+    if ((rc = check_build_options(&bo)) != KR_OK) return rc;
+    if (use_wide(&n, bo) && (rc = check_wide(&n)) != KR_OK) return rc;
+    const std::string src = full_source(&n, bo);
+    if (src_buf && src_len > 0) {
+      const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
+      std::memcpy(src_buf, src.data(), m);
+      src_buf[m] = '\0';
+    }
+    if (!compile) return KR_OK;
+    std::vector<char> code;
+    std::string log;
+    return compile_source(src, code, log);
+  } KR_CATCH
 }
 
 extern "C" int kr_network_check(const kr_network_desc *desc, int compile, char *src_buf,
                                 int64_t src_len) {
-  return kr_network_check_ex(desc, nullptr, compile, src_buf, src_len);
+  try {
+    return kr_network_check_ex(desc, nullptr, compile, src_buf, src_len);
+  } KR_CATCH
 }
 
 /* ------------------------------------------------------------------------ */
@@ -751,77 +797,136 @@ static int order_launch(hipFunction_t keys, hipFunction_t scan, hipFunction_t sc
   return KR_OK;
 }
 
+__global__ void kr_zero_u64n(unsigned long long *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+__global__ void kr_add_u64n(unsigned long long *dst, const unsigned long long *src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] += src[i];
+}
+
+/* Copies a call's totals block ([0..7] KR_TOT_*, [8..15] its statistics
+ * counters) into *out, adds the counters to the caller's own (if any) and
+ * synchronises the stream. */
+static int finish_stats(const unsigned long long *block, unsigned long long *caller_counters, kr_stats *out,
+                        hipStream_t st) {
+  if (caller_counters) {
+    hipLaunchKernelGGL(kr_add_u64n, dim3(1), dim3(64), 0, st, caller_counters, block + 8, 8);
+    HIP_TRY(hipGetLastError());
+  }
+  unsigned long long h[16];
+  HIP_TRY(hipMemcpyAsync(h, block, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  out->cells = (int64_t)h[KR_TOT_CELLS];
+  out->substeps = (int64_t)h[KR_TOT_SUBSTEPS];
+  out->newton_iterations = (int64_t)h[KR_TOT_ITERS];
+  out->rejected = (int64_t)h[KR_TOT_REJECTED];
+  out->newton_failures = (int64_t)h[KR_TOT_NFAIL];
+  out->retried = (int64_t)h[KR_TOT_RETRIED];
+  out->reverted = (int64_t)h[KR_TOT_REVERTED];
+  out->refinement_sweeps = (int64_t)h[8 + 3];
+  out->fp64_fallbacks = (int64_t)h[8 + 4];
+  out->guess_fallbacks = (int64_t)h[8 + 1];
+  std::memcpy(&out->max_element_residual, &h[KR_TOT_MAXRESID], sizeof(double));
+  return KR_OK;
+}
+
 static bool want_order(const kr_options &o, long long n) {
   return o.order == KR_ORDER_WORK && n > 1 && n <= 0xFFFFFFFFll;
 }
 
 extern "C" void kr_default_options(kr_options *o) {
-  if (!o) return;
-  o->precision = KR_FP64;
-  o->mode = KR_ADAPTIVE;
-  o->n_fixed = 1;
-  o->max_newton = 10;
-  o->max_substeps = 100000;
-  o->order = KR_ORDER_INPUT;
-  o->floor = 1e-20;
-  o->newton_tol = 1e-3;
-  o->rho_floor = 0.0;
-  o->guess = nullptr;
-  o->guess_ld = 0;
-  o->counters = nullptr;
+  try {
+    if (!o) return;
+    o->precision = KR_FP64;
+    o->mode = KR_ADAPTIVE;
+    o->n_fixed = 1;
+    o->max_newton = 10;
+    o->max_substeps = 100000;
+    o->order = KR_ORDER_INPUT;
+    o->floor = 1e-20;
+    o->newton_tol = 1e-3;
+    o->rho_floor = 0.0;
+    o->guess = nullptr;
+    o->guess_ld = 0;
+    o->counters = nullptr;
+    o->h_hint = nullptr;
+    o->h_log = nullptr;
+    o->h_log_ld = 0;
+    o->h_log_cap = 0;
+    o->reserved = 0;
+    o->h_log_n = nullptr;
+    o->stats = nullptr;
+  } catch (...) {
+  }
 }
 
 extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states, int64_t ld,
                                  double *T, const double *rho, const double *dt, double dt_scalar,
                                  double rtol, const kr_options *opt, int32_t *status,
                                  int32_t *cell_stats, kr_stream_t stream) {
-  if (!net) return fail(KR_EINVAL, "null network");
-  if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
-  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
-  kr_options o;
-  kr_default_options(&o);
-  if (opt) o = *opt;
-  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
-      (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
-      o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
-      !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
-    return fail(KR_EINVAL, "bad options");
-  if (n_cells == 0) return KR_OK;
-  if (!states || !T) return fail(KR_EINVAL, "null state arrays");
-  if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
-  HIP_TRY(hipSetDevice(net->device));
-  hipStream_t st = (hipStream_t)stream;
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
+    kr_options o;
+    kr_default_options(&o);
+    if (opt) o = *opt;
+    if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+        (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
+        o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
+        !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
+      return fail(KR_EINVAL, "bad options");
+    if (n_cells == 0) return KR_OK;
+    if (!states || !T) return fail(KR_EINVAL, "null state arrays");
+    if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+    HIP_TRY(hipSetDevice(net->device));
+    hipStream_t st = (hipStream_t)stream;
 
-  KrParams p;
-  p.n_cells = n_cells; p.states = states; p.ld = ld; p.T = T; p.rho = rho; p.dt = dt;
-  p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
-  p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
-  p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
-  p.counter = net->d_counter;
-  if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
-  if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
-  p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
-  p.order = nullptr;
-  if (want_order(o, n_cells)) {
-    kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
-    int rc = order_reserve(mnet->ord, n_cells);
-    if (rc == KR_OK)
-      rc = order_launch(net->f_keys, net->f_scan, net->f_scatter, net->ord, net->wide, net->cu_count, p, st);
-    if (rc != KR_OK) return rc;
-  }
+    KrParams p;
+    p.n_cells = n_cells; p.states = states; p.ld = ld; p.T = T; p.rho = rho; p.dt = dt;
+    p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
+    p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
+    p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
+    p.counter = net->d_counter;
+    if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
+    if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
+    p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
+    p.order = nullptr;
+    if (o.h_log && (o.h_log_ld < n_cells || o.h_log_cap < 0)) return fail(KR_EINVAL, "h_log_ld < n_cells or h_log_cap < 0");
+    p.h_hint = o.h_hint; p.h_log = o.h_log; p.h_log_ld = o.h_log_ld; p.h_log_cap = o.h_log_cap;
+    p.h_log_n = o.h_log_n;
+    p.totals = nullptr;
+    if (o.stats) {
+      /* totals and this call's statistics counters in the network's block,
+       * cleared by a kernel on the stream */
+      hipLaunchKernelGGL(kr_zero_u64n, dim3(1), dim3(64), 0, st, net->d_totals, 16);
+      HIP_TRY(hipGetLastError());
+      p.totals = net->d_totals;
+      p.counters = net->d_totals + 8;
+    }
+    if (want_order(o, n_cells)) {
+      kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
+      int rc = order_reserve(mnet->ord, n_cells);
+      if (rc == KR_OK)
+        rc = order_launch(net->f_keys, net->f_scan, net->f_scatter, net->ord, net->wide, net->cu_count, p, st);
+      if (rc != KR_OK) return rc;
+    }
 
-  unsigned long long *cnt = net->d_counter;
-  void *rargs[] = {&cnt};
-  HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
-  hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
-  const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
-  long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
-  const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
-  if (blocks > need) blocks = need;
-  if (blocks < 1) blocks = 1;
-  void *args[] = {&p};
-  HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
-  return KR_OK;
+    unsigned long long *cnt = net->d_counter;
+    void *rargs[] = {&cnt};
+    HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
+    hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
+    const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
+    long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
+    const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    void *args[] = {&p};
+    HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
+    if (o.stats) return finish_stats(net->d_totals, o.counters, o.stats, st);
+    return KR_OK;
+  } KR_CATCH
 }
 
 /* ------------------------------------------------------------------------ */
@@ -879,56 +984,79 @@ __global__ void kr_zero_doubles(double *p, int n) {
 extern "C" int kr_element_residual(const kr_network *net, int64_t n_cells, const double *before,
                                    const double *after, int64_t ld, double *resid, double *max_out,
                                    kr_stream_t stream) {
-  if (!net) return fail(KR_EINVAL, "null network");
-  if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld");
-  if (n_cells > 0 && (!before || !after)) return fail(KR_EINVAL, "null state arrays");
-  HIP_TRY(hipSetDevice(net->device));
-  hipStream_t st = (hipStream_t)stream;
-  if (max_out) {
-    hipLaunchKernelGGL(kr_zero_u64, dim3(1), dim3(64), 0, st, net->d_max);
-    HIP_TRY(hipGetLastError());
-  }
-  if (n_cells > 0) {
-    long long blocks = (n_cells + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(kr_element_residual_kernel, dim3((unsigned)blocks), dim3(256), 0, st, net->S,
-                       net->n_rows, net->n_elem, net->d_comp, (long long)n_cells, before, after,
-                       (long long)ld, resid, max_out ? net->d_max : nullptr);
-    HIP_TRY(hipGetLastError());
-  }
-  if (max_out) {
-    unsigned long long bits = 0;
-    HIP_TRY(hipMemcpyAsync(&bits, net->d_max, sizeof bits, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    std::memcpy(max_out, &bits, sizeof bits);
-  }
-  return KR_OK;
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld");
+    if (n_cells > 0 && (!before || !after)) return fail(KR_EINVAL, "null state arrays");
+    HIP_TRY(hipSetDevice(net->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (max_out) {
+      hipLaunchKernelGGL(kr_zero_u64, dim3(1), dim3(64), 0, st, net->d_max);
+      HIP_TRY(hipGetLastError());
+    }
+    if (n_cells > 0) {
+      long long blocks = (n_cells + 255) / 256;
+      if (blocks > 4096) blocks = 4096;
+      hipLaunchKernelGGL(kr_element_residual_kernel, dim3((unsigned)blocks), dim3(256), 0, st, net->S,
+                         net->n_rows, net->n_elem, net->d_comp, (long long)n_cells, before, after,
+                         (long long)ld, resid, max_out ? net->d_max : nullptr);
+      HIP_TRY(hipGetLastError());
+    }
+    if (max_out) {
+      unsigned long long bits = 0;
+      HIP_TRY(hipMemcpyAsync(&bits, net->d_max, sizeof bits, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      std::memcpy(max_out, &bits, sizeof bits);
+    }
+    return KR_OK;
+  } KR_CATCH
+}
+
+extern "C" int kr_postprocess(const kr_network *net, int64_t n_cells, const double *before, double *after,
+                              int64_t ld, int32_t *flags, kr_stream_t stream) {
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld");
+    if (n_cells == 0) return KR_OK;
+    if (!before || !after) return fail(KR_EINVAL, "null state arrays");
+    HIP_TRY(hipSetDevice(net->device));
+    KrParams p{};
+    p.n_cells = n_cells; p.states = after; p.ld = ld;
+    const long long need = net->wide ? n_cells : (n_cells + 63) / 64;
+    const long long blocks = std::min<long long>(need, (long long)net->cu_count * 8);
+    void *args[] = {&p, &before, &flags};
+    HIP_TRY(hipModuleLaunchKernel(net->f_post, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
+                                  nullptr));
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_work_order(const kr_network *net, int64_t n_cells, const double *states, int64_t ld,
                              const double *T, const double *rho, const double *dt, double dt_scalar,
                              const kr_options *opt, uint32_t *order, kr_stream_t stream) {
-  if (!net) return fail(KR_EINVAL, "null network");
-  if (n_cells < 0 || ld < n_cells || n_cells > 0xFFFFFFFFll)
-    return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
-  if (n_cells == 0) return KR_OK;
-  if (!states || !T || !order) return fail(KR_EINVAL, "null array");
-  if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
-  kr_options o;
-  kr_default_options(&o);
-  if (opt) o = *opt;
-  if (!(o.floor >= 0.0) || !(o.rho_floor >= 0.0)) return fail(KR_EINVAL, "bad options");
-  HIP_TRY(hipSetDevice(net->device));
-  KrParams p{};
-  p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.rho = rho; p.dt = dt;
-  p.dt_scalar = dt_scalar; p.floor = o.floor; p.rho_floor = o.rho_floor;
-  kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
-  int rc = order_reserve(mnet->ord, n_cells);
-  if (rc != KR_OK) return rc;
-  OrderBufs b = net->ord;
-  b.order = order;
-  return order_launch(net->f_keys, net->f_scan, net->f_scatter, b, net->wide, net->cu_count, p,
-                      (hipStream_t)stream);
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (n_cells < 0 || ld < n_cells || n_cells > 0xFFFFFFFFll)
+      return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
+    if (n_cells == 0) return KR_OK;
+    if (!states || !T || !order) return fail(KR_EINVAL, "null array");
+    if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+    kr_options o;
+    kr_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.floor >= 0.0) || !(o.rho_floor >= 0.0)) return fail(KR_EINVAL, "bad options");
+    HIP_TRY(hipSetDevice(net->device));
+    KrParams p{};
+    p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.rho = rho; p.dt = dt;
+    p.dt_scalar = dt_scalar; p.floor = o.floor; p.rho_floor = o.rho_floor;
+    kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
+    int rc = order_reserve(mnet->ord, n_cells);
+    if (rc != KR_OK) return rc;
+    OrderBufs b = net->ord;
+    b.order = order;
+    return order_launch(net->f_keys, net->f_scan, net->f_scatter, b, net->wide, net->cu_count, p,
+                        (hipStream_t)stream);
+  } KR_CATCH
 }
 
 /* ------------------------------------------------------------------------ */
@@ -937,18 +1065,20 @@ extern "C" int kr_work_order(const kr_network *net, int64_t n_cells, const doubl
 
 extern "C" int kr_fastest_timescale(const kr_network *net, int64_t n_cells, const double *states,
                                     int64_t ld, const double *T, double *out, kr_stream_t stream) {
-  if (!net || n_cells < 0 || ld < n_cells || (n_cells && (!states || !T || !out)))
-    return fail(KR_EINVAL, "bad timescale arguments");
-  if (!n_cells) return KR_OK;
-  HIP_TRY(hipSetDevice(net->device));
-  KrParams p{};
-  p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.dt_scalar = 1.0;
-  long long blocks = std::min<long long>(net->wide ? n_cells : (n_cells + 63) / 64,
-                                        (long long)net->cu_count * (net->wide ? 4 : 16));
-  void *args[] = {&p, &out};
-  HIP_TRY(hipModuleLaunchKernel(net->f_tau, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
-                                nullptr));
-  return KR_OK;
+  try {
+    if (!net || n_cells < 0 || ld < n_cells || (n_cells && (!states || !T || !out)))
+      return fail(KR_EINVAL, "bad timescale arguments");
+    if (!n_cells) return KR_OK;
+    HIP_TRY(hipSetDevice(net->device));
+    KrParams p{};
+    p.n_cells = n_cells; p.states = (double *)states; p.ld = ld; p.T = (double *)T; p.dt_scalar = 1.0;
+    long long blocks = std::min<long long>(net->wide ? n_cells : (n_cells + 63) / 64,
+                                          (long long)net->cu_count * (net->wide ? 4 : 16));
+    void *args[] = {&p, &out};
+    HIP_TRY(hipModuleLaunchKernel(net->f_tau, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
+                                  nullptr));
+    return KR_OK;
+  } KR_CATCH
 }
 
 /* ------------------------------------------------------------------------ */
@@ -975,6 +1105,7 @@ struct kr_multi {
   OrderBufs ord[KR_MAX_NETS];
   int device = -1, cu_count = 0, occ_fp64[2] = {}, occ_fp32[2] = {};
   unsigned long long *d_counters = nullptr; /* one per network */
+  unsigned long long *d_totals = nullptr;   /* [16] per-call totals and statistics counters */
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1064,6 +1195,7 @@ static void release_multi(kr_multi *m) {
   if (m->graph) (void)hipGraphDestroy(m->graph);
   if (m->capture) (void)hipStreamDestroy(m->capture);
   if (m->d_counters) (void)hipFree(m->d_counters);
+  if (m->d_totals) (void)hipFree(m->d_totals);
   for (int k = 0; k < KR_MAX_NETS; ++k) order_free(m->ord[k]);
   if (m->module) (void)hipModuleUnload(m->module);
   delete m;
@@ -1071,97 +1203,109 @@ static void release_multi(kr_multi *m) {
 
 extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, const kr_build_opts *bopt,
                                kr_multi **out) {
-  if (!out) return fail(KR_EINVAL, "null output handle");
-  *out = nullptr;
-  if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
-  for (int k = 0; k < n_nets; ++k) {
-    if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
-  }
-  kr_build_opts bo;
-  kr_default_build_options(&bo);
-  if (bopt) bo = *bopt;
-  int rc = check_build_options(&bo);
-  if (rc != KR_OK) return rc;
-  kr_multi *m = new (std::nothrow) kr_multi;
-  if (!m) return fail(KR_ENOMEM, "out of host memory");
-  m->nets.assign(nets, nets + n_nets);
-  m->build = bo;
-  m->build.waves_per_eu = multi_waves_per_eu(m->nets, bo);
-  m->source = multi_source(m->nets, bo);
-  for (const auto &g : multi_groups(m->nets, bo)) m->groups.push_back(g.second);
-  std::vector<char> code;
-  std::string log;
-  rc = compile_source(m->source, code, log);
-  if (rc != KR_OK) { delete m; return rc; }
-  hipError_t e;
-#define MULTI_TRY(expr)                                                              \
-  do {                                                                               \
-    e = (expr);                                                                      \
-    if (e != hipSuccess) {                                                           \
-      rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                  \
-      release_multi(m);                                                              \
-      return rc;                                                                     \
-    }                                                                                \
-  } while (0)
-  MULTI_TRY(hipGetDevice(&m->device));
-  MULTI_TRY(hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device));
-  MULTI_TRY(hipModuleLoadData(&m->module, code.data()));
-  for (size_t g = 0; g < m->groups.size(); ++g) {
-    const std::string sfx = std::to_string(g);
-    MULTI_TRY(hipModuleGetFunction(&m->f_fp64[g], m->module, ("kr_integrate_multi_fp64_" + sfx).c_str()));
-    MULTI_TRY(hipModuleGetFunction(&m->f_fp32[g], m->module, ("kr_integrate_multi_fp32lu_" + sfx).c_str()));
-    MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64[g], m->f_fp64[g], 64, 0));
-    MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32[g], m->f_fp32[g], 64, 0));
-  }
-  MULTI_TRY(hipModuleGetFunction(&m->f_reset, m->module, "kr_reset_counters"));
-  MULTI_TRY(hipModuleGetFunction(&m->f_scan, m->module, "kr_order_scan"));
-  MULTI_TRY(hipModuleGetFunction(&m->f_scatter, m->module, "kr_order_scatter"));
-  for (int k = 0; k < n_nets; ++k)
-    MULTI_TRY(hipModuleGetFunction(&m->f_keys[k], m->module, ("kr_order_keys_m" + std::to_string(k)).c_str()));
-  MULTI_TRY(hipMalloc(&m->d_counters, sizeof(unsigned long long) * KR_MAX_NETS));
-  MULTI_TRY(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
-#undef MULTI_TRY
-  *out = m;
-  return KR_OK;
+  try {
+    if (!out) return fail(KR_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
+    for (int k = 0; k < n_nets; ++k) {
+      if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
+    }
+    kr_build_opts bo;
+    kr_default_build_options(&bo);
+    if (bopt) bo = *bopt;
+    int rc = check_build_options(&bo);
+    if (rc != KR_OK) return rc;
+    kr_multi *m = new (std::nothrow) kr_multi;
+    if (!m) return fail(KR_ENOMEM, "out of host memory");
+    m->nets.assign(nets, nets + n_nets);
+    m->build = bo;
+    m->build.waves_per_eu = multi_waves_per_eu(m->nets, bo);
+    m->source = multi_source(m->nets, bo);
+    for (const auto &g : multi_groups(m->nets, bo)) m->groups.push_back(g.second);
+    std::vector<char> code;
+    std::string log;
+    rc = compile_source(m->source, code, log);
+    if (rc != KR_OK) { delete m; return rc; }
+    hipError_t e;
+  #define MULTI_TRY(expr)                                                              \
+    do {                                                                               \
+      e = (expr);                                                                      \
+      if (e != hipSuccess) {                                                           \
+        rc = fail(KR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e));                  \
+        release_multi(m);                                                              \
+        return rc;                                                                     \
+      }                                                                                \
+    } while (0)
+    MULTI_TRY(hipGetDevice(&m->device));
+    MULTI_TRY(hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device));
+    MULTI_TRY(hipModuleLoadData(&m->module, code.data()));
+    for (size_t g = 0; g < m->groups.size(); ++g) {
+      const std::string sfx = std::to_string(g);
+      MULTI_TRY(hipModuleGetFunction(&m->f_fp64[g], m->module, ("kr_integrate_multi_fp64_" + sfx).c_str()));
+      MULTI_TRY(hipModuleGetFunction(&m->f_fp32[g], m->module, ("kr_integrate_multi_fp32lu_" + sfx).c_str()));
+      MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp64[g], m->f_fp64[g], 64, 0));
+      MULTI_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&m->occ_fp32[g], m->f_fp32[g], 64, 0));
+    }
+    MULTI_TRY(hipModuleGetFunction(&m->f_reset, m->module, "kr_reset_counters"));
+    MULTI_TRY(hipModuleGetFunction(&m->f_scan, m->module, "kr_order_scan"));
+    MULTI_TRY(hipModuleGetFunction(&m->f_scatter, m->module, "kr_order_scatter"));
+    for (int k = 0; k < n_nets; ++k)
+      MULTI_TRY(hipModuleGetFunction(&m->f_keys[k], m->module, ("kr_order_keys_m" + std::to_string(k)).c_str()));
+    MULTI_TRY(hipMalloc(&m->d_counters, sizeof(unsigned long long) * KR_MAX_NETS));
+    MULTI_TRY(hipMalloc(&m->d_totals, sizeof(unsigned long long) * 16));
+    MULTI_TRY(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
+  #undef MULTI_TRY
+    *out = m;
+    return KR_OK;
+  } KR_CATCH
 }
 
-extern "C" void kr_multi_destroy(kr_multi *m) { release_multi(m); }
+extern "C" void kr_multi_destroy(kr_multi *m) {
+  try {
+    release_multi(m);
+  } catch (...) {
+  }
+}
 
 extern "C" int kr_multi_check(const kr_network_desc *const *descs, int32_t n_nets, int compile, char *src_buf,
                               int64_t src_len) {
-  if (!descs || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
-  std::vector<kr_network> tabs(n_nets);
-  std::vector<const kr_network *> ptrs;
-  for (int k = 0; k < n_nets; ++k) {
-    int rc = build_tables(descs[k], &tabs[k]);
-    if (rc != KR_OK) return rc;
-    ptrs.push_back(&tabs[k]);
-  }
-  kr_build_opts bo;
-  kr_default_build_options(&bo);
-  for (int k = 0; k < n_nets; ++k) {
-    tabs[k].wide = use_wide(&tabs[k], bo);
-    if (tabs[k].wide) {
-      int rc = check_wide(&tabs[k]);
+  try {
+    if (!descs || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
+    std::vector<kr_network> tabs(n_nets);
+    std::vector<const kr_network *> ptrs;
+    for (int k = 0; k < n_nets; ++k) {
+      int rc = build_tables(descs[k], &tabs[k]);
       if (rc != KR_OK) return rc;
+      ptrs.push_back(&tabs[k]);
     }
-  }
-  const std::string src = multi_source(ptrs, bo);
-  if (src_buf && src_len > 0) {
-    const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
-    std::memcpy(src_buf, src.data(), m);
-    src_buf[m] = '\0';
-  }
-  if (!compile) return KR_OK;
-  std::vector<char> code;
-  std::string log;
-  return compile_source(src, code, log);
+    kr_build_opts bo;
+    kr_default_build_options(&bo);
+    for (int k = 0; k < n_nets; ++k) {
+      tabs[k].wide = use_wide(&tabs[k], bo);
+      if (tabs[k].wide) {
+        int rc = check_wide(&tabs[k]);
+        if (rc != KR_OK) return rc;
+      }
+    }
+    const std::string src = multi_source(ptrs, bo);
+    if (src_buf && src_len > 0) {
+      const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
+      std::memcpy(src_buf, src.data(), m);
+      src_buf[m] = '\0';
+    }
+    if (!compile) return KR_OK;
+    std::vector<char> code;
+    std::string log;
+    return compile_source(src, code, log);
+  } KR_CATCH
 }
 
 extern "C" int64_t kr_multi_graph_stats(const kr_multi *m, int64_t *captures) {
-  if (!m) return fail(KR_EINVAL, "null handle");
-  if (captures) *captures = m->graph_captures;
-  return m->graph_launches;
+  try {
+    if (!m) return fail(KR_EINVAL, "null handle");
+    if (captures) *captures = m->graph_captures;
+    return m->graph_launches;
+  } KR_CATCH
 }
 
 static int fill_params(const kr_network *net, const kr_batch &b, double rtol, const kr_options &o,
@@ -1190,102 +1334,118 @@ static int validate_options(const kr_options &o) {
 
 extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, double rtol,
                                        const kr_options *opt, int32_t use_graph, kr_stream_t stream) {
-  if (!m || !batches) return fail(KR_EINVAL, "null argument");
-  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
-  kr_options o;
-  kr_default_options(&o);
-  if (opt) o = *opt;
-  int rc = validate_options(o);
-  if (rc) return rc;
-  if (o.guess) return fail(KR_EINVAL, "a learned guess is not supported in multi-network launches");
-  KrMultiHost h{};
-  long long total = 0;
-  h.n_nets = (int)m->nets.size();
-  for (int k = 0; k < h.n_nets; ++k) {
-    if ((rc = fill_params(m->nets[k], batches[k], rtol, o, m->d_counters + k, h.net[k]))) return rc;
-    total += batches[k].n_cells;
-  }
-  if (total == 0) return KR_OK;
-  HIP_TRY(hipSetDevice(m->device));
-  hipStream_t st = (hipStream_t)stream;
-  const int n_groups = (int)m->groups.size();
-  hipFunction_t f[2] = {};
-  long long blocks[2] = {0, 0};
-  for (int g = 0; g < n_groups; ++g) {
-    f[g] = o.precision == KR_FP64 ? m->f_fp64[g] : m->f_fp32[g];
-    const int occ = o.precision == KR_FP64 ? m->occ_fp64[g] : m->occ_fp32[g];
-    long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
-    for (int k : m->groups[g])
-      need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
-    blocks[g] = std::min<long long>((long long)m->cu_count * (occ > 0 ? occ : 1), need);   /* 0: no work */
-  }
-  /* largest-work-first order of each batch: buffers reserved here, outside
-   * any capture; the order kernels run on the launch stream ahead of the
-   * counter reset (and are part of the captured graph) */
-  bool ordered[KR_MAX_NETS] = {};
-  for (int k = 0; k < h.n_nets; ++k) {
-    if (!want_order(o, batches[k].n_cells)) continue;
-    if ((rc = order_reserve(m->ord[k], batches[k].n_cells))) return rc;
-    ordered[k] = true;
-    h.net[k].order = m->ord[k].order;
-  }
-  auto launch_orders = [&](hipStream_t s) -> int {
+  try {
+    if (!m || !batches) return fail(KR_EINVAL, "null argument");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
+    kr_options o;
+    kr_default_options(&o);
+    if (opt) o = *opt;
+    int rc = validate_options(o);
+    if (rc) return rc;
+    if (o.guess) return fail(KR_EINVAL, "a learned guess is not supported in multi-network launches");
+    if (o.h_hint || o.h_log || o.h_log_n)
+      return fail(KR_EINVAL, "per-cell step hints and substep logs are not supported in multi-network launches");
+    KrMultiHost h{};
+    long long total = 0;
+    h.n_nets = (int)m->nets.size();
     for (int k = 0; k < h.n_nets; ++k) {
-      if (!ordered[k]) continue;
-      KrParams pk = h.net[k];
-      int r = order_launch(m->f_keys[k], m->f_scan, m->f_scatter, m->ord[k], m->nets[k]->wide, m->cu_count, pk, s);
-      if (r != KR_OK) return r;
+      if ((rc = fill_params(m->nets[k], batches[k], rtol, o, m->d_counters + k, h.net[k]))) return rc;
+      total += batches[k].n_cells;
     }
-    return KR_OK;
-  };
-  unsigned long long *cnt = m->d_counters;
-  int nn = h.n_nets;
-  void *rargs[] = {&cnt, &nn};
-  void *args[] = {&h};
-  auto launch_groups = [&](hipStream_t s) -> hipError_t {
+    if (total == 0) return KR_OK;
+    HIP_TRY(hipSetDevice(m->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (o.stats) {
+      /* all networks add to one totals block, cleared ahead of the launch (a
+       * kernel on the stream, outside any captured graph) */
+      hipLaunchKernelGGL(kr_zero_u64n, dim3(1), dim3(64), 0, st, m->d_totals, 16);
+      HIP_TRY(hipGetLastError());
+      for (int k = 0; k < h.n_nets; ++k) {
+        h.net[k].totals = m->d_totals;
+        h.net[k].counters = m->d_totals + 8;
+      }
+    }
+    const int n_groups = (int)m->groups.size();
+    hipFunction_t f[2] = {};
+    long long blocks[2] = {0, 0};
     for (int g = 0; g < n_groups; ++g) {
-      if (blocks[g] < 1) continue;
-      const hipError_t e = hipModuleLaunchKernel(f[g], (unsigned)blocks[g], 1, 1, 64, 1, 1, 0, s, args, nullptr);
-      if (e != hipSuccess) return e;
+      f[g] = o.precision == KR_FP64 ? m->f_fp64[g] : m->f_fp32[g];
+      const int occ = o.precision == KR_FP64 ? m->occ_fp64[g] : m->occ_fp32[g];
+      long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
+      for (int k : m->groups[g])
+        need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
+      blocks[g] = std::min<long long>((long long)m->cu_count * (occ > 0 ? occ : 1), need);   /* 0: no work */
     }
-    return hipSuccess;
-  };
-  if (!use_graph) {
-    if ((rc = launch_orders(st))) return rc;
-    HIP_TRY(hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
-    HIP_TRY(launch_groups(st));
+    /* largest-work-first order of each batch: buffers reserved here, outside
+     * any capture; the order kernels run on the launch stream ahead of the
+     * counter reset (and are part of the captured graph) */
+    bool ordered[KR_MAX_NETS] = {};
+    for (int k = 0; k < h.n_nets; ++k) {
+      if (!want_order(o, batches[k].n_cells)) continue;
+      if ((rc = order_reserve(m->ord[k], batches[k].n_cells))) return rc;
+      ordered[k] = true;
+      h.net[k].order = m->ord[k].order;
+    }
+    auto launch_orders = [&](hipStream_t s) -> int {
+      for (int k = 0; k < h.n_nets; ++k) {
+        if (!ordered[k]) continue;
+        KrParams pk = h.net[k];
+        int r = order_launch(m->f_keys[k], m->f_scan, m->f_scatter, m->ord[k], m->nets[k]->wide, m->cu_count, pk, s);
+        if (r != KR_OK) return r;
+      }
+      return KR_OK;
+    };
+    unsigned long long *cnt = m->d_counters;
+    int nn = h.n_nets;
+    void *rargs[] = {&cnt, &nn};
+    void *args[] = {&h};
+    auto launch_groups = [&](hipStream_t s) -> hipError_t {
+      for (int g = 0; g < n_groups; ++g) {
+        if (blocks[g] < 1) continue;
+        const hipError_t e = hipModuleLaunchKernel(f[g], (unsigned)blocks[g], 1, 1, 64, 1, 1, 0, s, args, nullptr);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    if (!use_graph) {
+      if ((rc = launch_orders(st))) return rc;
+      HIP_TRY(hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
+      HIP_TRY(launch_groups(st));
+      if (o.stats) return finish_stats(m->d_totals, o.counters, o.stats, st);
+      return KR_OK;
+    }
+    /* graph of [order kernels] -> [reset the work counters] -> [persistent
+     * integrate, one kernel per group], captured once per distinct launch configuration and replayed
+     * on the caller's stream (counters and histograms are cleared by kernels,
+     * not memset nodes) */
+    std::vector<char> key(sizeof h + sizeof blocks + sizeof f);
+    std::memcpy(key.data(), &h, sizeof h);
+    std::memcpy(key.data() + sizeof h, &blocks, sizeof blocks);
+    std::memcpy(key.data() + sizeof h + sizeof blocks, &f, sizeof f);
+    if (!m->exec || key != m->key) {
+      if (m->exec) { (void)hipGraphExecDestroy(m->exec); m->exec = nullptr; }
+      if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
+      HIP_TRY(hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal));
+      const int r0 = launch_orders(m->capture);
+      hipError_t e1 = hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, m->capture, rargs, nullptr);
+      hipError_t e2 = launch_groups(m->capture);
+      hipGraph_t g = nullptr;
+      hipError_t e3 = hipStreamEndCapture(m->capture, &g);
+      if (r0 != KR_OK || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(r0 != KR_OK ? r0 : KR_EDEVICE, "graph capture failed: order %d / %s / %s / %s", r0,
+                    hipGetErrorString(e1), hipGetErrorString(e2), hipGetErrorString(e3));
+      }
+      m->graph = g;
+      HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
+      m->key = key;
+      m->graph_captures++;
+    }
+    HIP_TRY(hipGraphLaunch(m->exec, st));
+    m->graph_launches++;
+    if (o.stats) return finish_stats(m->d_totals, o.counters, o.stats, st);
     return KR_OK;
-  }
-  /* graph of [order kernels] -> [reset the work counters] -> [persistent
-   * integrate, one kernel per group], captured once per distinct launch configuration and replayed
-   * on the caller's stream (counters and histograms are cleared by kernels,
-   * not memset nodes) */
-  std::vector<char> key(sizeof h + sizeof blocks + sizeof f);
-  std::memcpy(key.data(), &h, sizeof h);
-  std::memcpy(key.data() + sizeof h, &blocks, sizeof blocks);
-  std::memcpy(key.data() + sizeof h + sizeof blocks, &f, sizeof f);
-  if (!m->exec || key != m->key) {
-    if (m->exec) { (void)hipGraphExecDestroy(m->exec); m->exec = nullptr; }
-    if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
-    HIP_TRY(hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal));
-    const int r0 = launch_orders(m->capture);
-    hipError_t e1 = hipModuleLaunchKernel(m->f_reset, 1, 1, 1, 64, 1, 1, 0, m->capture, rargs, nullptr);
-    hipError_t e2 = launch_groups(m->capture);
-    hipGraph_t g = nullptr;
-    hipError_t e3 = hipStreamEndCapture(m->capture, &g);
-    if (r0 != KR_OK || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(r0 != KR_OK ? r0 : KR_EDEVICE, "graph capture failed: order %d / %s / %s / %s", r0,
-                  hipGetErrorString(e1), hipGetErrorString(e2), hipGetErrorString(e3));
-    }
-    m->graph = g;
-    HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
-    m->key = key;
-    m->graph_captures++;
-  }
-  HIP_TRY(hipGraphLaunch(m->exec, st));
-  m->graph_launches++;
-  return KR_OK;
+  } KR_CATCH
 }
 
 /* ------------------------------------------------------------------------ */

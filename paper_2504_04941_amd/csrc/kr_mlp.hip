@@ -458,246 +458,277 @@ static int guess_make_batch(kr_guess *q, int B, long n, int sample, unsigned lon
 
 extern "C" int kr_guess_create(const kr_network *net, int32_t hidden, int32_t layers, uint64_t seed,
                                kr_guess **out) {
-  if (!net || !out || hidden < 1 || hidden > 4096 || layers < 1 || layers > 16)
-    return fail(KR_EINVAL, "bad guess model arguments");
-  if (net->S + 2 > 16) return fail(KR_EINVAL, "the guess model supports at most 14 species");
-  *out = nullptr;
-  kr_guess *q = new (std::nothrow) kr_guess;
-  if (!q) return fail(KR_ENOMEM, "out of host memory");
-  q->S = net->S; q->nin = net->S + 2; q->nout = net->S + 1; q->hidden = hidden; q->layers = layers;
-  q->device = net->device;
-  long off = 0;
-  for (int l = 0; l <= layers; ++l) {
-    const long fi = l == 0 ? q->nin : hidden, fo = l == layers ? q->nout : hidden;
-    q->w_off.push_back(off); off += fi * fo;
-    q->b_off.push_back(off); off += fo;
-    q->fan_in.push_back(fi); q->fan_out.push_back(fo);
-  }
-  q->nparams = off;
-  /* PyTorch-Linear-style uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a
-   * splitmix64 stream of the seed */
-  std::vector<float> w0(off);
-  unsigned long long st = seed;
-  for (int l = 0; l <= layers; ++l) {
-    const double bound = 1.0 / std::sqrt((double)q->fan_in[l]);
-    for (long i = q->w_off[l]; i < q->b_off[l] + q->fan_out[l]; ++i) {
-      st += 0x9e3779b97f4a7c15ull;
-      unsigned long long z = st;
-      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-      z ^= z >> 31;
-      const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
-      w0[i] = (float)((2.0 * u - 1.0) * bound);
+  try {
+    if (!net || !out || hidden < 1 || hidden > 4096 || layers < 1 || layers > 16)
+      return fail(KR_EINVAL, "bad guess model arguments");
+    if (net->S + 2 > 16) return fail(KR_EINVAL, "the guess model supports at most 14 species");
+    *out = nullptr;
+    kr_guess *q = new (std::nothrow) kr_guess;
+    if (!q) return fail(KR_ENOMEM, "out of host memory");
+    q->S = net->S; q->nin = net->S + 2; q->nout = net->S + 1; q->hidden = hidden; q->layers = layers;
+    q->device = net->device;
+    long off = 0;
+    for (int l = 0; l <= layers; ++l) {
+      const long fi = l == 0 ? q->nin : hidden, fo = l == layers ? q->nout : hidden;
+      q->w_off.push_back(off); off += fi * fo;
+      q->b_off.push_back(off); off += fo;
+      q->fan_in.push_back(fi); q->fan_out.push_back(fo);
     }
-  }
-  std::vector<float> nm(64, 0.0f);
-  for (int j = 0; j < 16; ++j) { nm[16 + j] = 1.0f; nm[48 + j] = 1.0f; }
-  std::vector<double> atoms(q->S, 0.0);
-  for (int s = 0; s < q->S; ++s)
-    for (int v = 0; v < net->n_elem; ++v) atoms[s] += net->comp[(size_t)v * net->S + s];
-  int rc = KR_OK;
-  hipError_t e = hipSuccess;
-  if ((e = hipSetDevice(q->device)) != hipSuccess ||
-      (e = hipMalloc(&q->w, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMalloc(&q->g, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMalloc(&q->m, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMalloc(&q->v, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMalloc(&q->wb, sizeof(kr_bf16) * off)) != hipSuccess ||
-      (e = hipMalloc(&q->norm, sizeof(float) * 64)) != hipSuccess ||
-      (e = hipMalloc(&q->atoms, sizeof(double) * q->S)) != hipSuccess ||
-      (e = hipMalloc(&q->dacc, sizeof(double) * 64)) != hipSuccess ||
-      (e = hipMemcpy(q->w, w0.data(), sizeof(float) * off, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemset(q->m, 0, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMemset(q->v, 0, sizeof(float) * off)) != hipSuccess ||
-      (e = hipMemcpy(q->norm, nm.data(), sizeof(float) * 64, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(q->atoms, atoms.data(), sizeof(double) * q->S, hipMemcpyHostToDevice)) != hipSuccess)
-    rc = fail(KR_EDEVICE, "guess model allocation: %s", hipGetErrorString(e));
-  if (rc == KR_OK) {
-    hipLaunchKernelGGL(kr_round_bf16, dim3(256), dim3(256), 0, 0, (long)off, q->w, q->wb);
-    if ((e = hipDeviceSynchronize()) != hipSuccess) rc = fail(KR_EDEVICE, "guess init: %s", hipGetErrorString(e));
-  }
-  if (rc != KR_OK) {
-    kr_guess_destroy(q);
-    return rc;
-  }
-  *out = q;
-  return KR_OK;
+    q->nparams = off;
+    /* PyTorch-Linear-style uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a
+     * splitmix64 stream of the seed */
+    std::vector<float> w0(off);
+    unsigned long long st = seed;
+    for (int l = 0; l <= layers; ++l) {
+      const double bound = 1.0 / std::sqrt((double)q->fan_in[l]);
+      for (long i = q->w_off[l]; i < q->b_off[l] + q->fan_out[l]; ++i) {
+        st += 0x9e3779b97f4a7c15ull;
+        unsigned long long z = st;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        w0[i] = (float)((2.0 * u - 1.0) * bound);
+      }
+    }
+    std::vector<float> nm(64, 0.0f);
+    for (int j = 0; j < 16; ++j) { nm[16 + j] = 1.0f; nm[48 + j] = 1.0f; }
+    std::vector<double> atoms(q->S, 0.0);
+    for (int s = 0; s < q->S; ++s)
+      for (int v = 0; v < net->n_elem; ++v) atoms[s] += net->comp[(size_t)v * net->S + s];
+    int rc = KR_OK;
+    hipError_t e = hipSuccess;
+    if ((e = hipSetDevice(q->device)) != hipSuccess ||
+        (e = hipMalloc(&q->w, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMalloc(&q->g, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMalloc(&q->m, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMalloc(&q->v, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMalloc(&q->wb, sizeof(kr_bf16) * off)) != hipSuccess ||
+        (e = hipMalloc(&q->norm, sizeof(float) * 64)) != hipSuccess ||
+        (e = hipMalloc(&q->atoms, sizeof(double) * q->S)) != hipSuccess ||
+        (e = hipMalloc(&q->dacc, sizeof(double) * 64)) != hipSuccess ||
+        (e = hipMemcpy(q->w, w0.data(), sizeof(float) * off, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(q->m, 0, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMemset(q->v, 0, sizeof(float) * off)) != hipSuccess ||
+        (e = hipMemcpy(q->norm, nm.data(), sizeof(float) * 64, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(q->atoms, atoms.data(), sizeof(double) * q->S, hipMemcpyHostToDevice)) != hipSuccess)
+      rc = fail(KR_EDEVICE, "guess model allocation: %s", hipGetErrorString(e));
+    if (rc == KR_OK) {
+      hipLaunchKernelGGL(kr_round_bf16, dim3(256), dim3(256), 0, 0, (long)off, q->w, q->wb);
+      if ((e = hipDeviceSynchronize()) != hipSuccess) rc = fail(KR_EDEVICE, "guess init: %s", hipGetErrorString(e));
+    }
+    if (rc != KR_OK) {
+      kr_guess_destroy(q);
+      return rc;
+    }
+    *out = q;
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" void kr_guess_destroy(kr_guess *q) {
-  if (!q) return;
-  guess_free_buffers(q);
-  void *bufs[] = {q->w, q->g, q->m, q->v, q->wb, q->norm, q->atoms, q->dacc};
-  for (void *p : bufs)
-    if (p) (void)hipFree(p);
-  delete q;
+  try {
+    if (!q) return;
+    guess_free_buffers(q);
+    void *bufs[] = {q->w, q->g, q->m, q->v, q->wb, q->norm, q->atoms, q->dacc};
+    for (void *p : bufs)
+      if (p) (void)hipFree(p);
+    delete q;
+  } catch (...) {
+  }
 }
 
-extern "C" int64_t kr_guess_num_params(const kr_guess *q) { return q ? q->nparams : KR_EINVAL; }
+extern "C" int64_t kr_guess_num_params(const kr_guess *q) {
+  try {
+    return q ? q->nparams : KR_EINVAL;
+  } KR_CATCH
+}
 
 extern "C" int kr_guess_get_params(const kr_guess *q, float *host) {
-  if (!q || !host) return fail(KR_EINVAL, "null argument");
-  HIP_TRY(hipMemcpy(host, q->w, sizeof(float) * q->nparams, hipMemcpyDeviceToHost));
-  return KR_OK;
+  try {
+    if (!q || !host) return fail(KR_EINVAL, "null argument");
+    HIP_TRY(hipMemcpy(host, q->w, sizeof(float) * q->nparams, hipMemcpyDeviceToHost));
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_set_params(kr_guess *q, const float *host) {
-  if (!q || !host) return fail(KR_EINVAL, "null argument");
-  HIP_TRY(hipMemcpy(q->w, host, sizeof(float) * q->nparams, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(kr_round_bf16, dim3(256), dim3(256), 0, 0, q->nparams, q->w, q->wb);
-  HIP_TRY(hipDeviceSynchronize());
-  return KR_OK;
+  try {
+    if (!q || !host) return fail(KR_EINVAL, "null argument");
+    HIP_TRY(hipMemcpy(q->w, host, sizeof(float) * q->nparams, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(kr_round_bf16, dim3(256), dim3(256), 0, 0, q->nparams, q->w, q->wb);
+    HIP_TRY(hipDeviceSynchronize());
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_get_normalization(const kr_guess *q, float *norm64) {
-  if (!q || !norm64) return fail(KR_EINVAL, "null argument");
-  HIP_TRY(hipMemcpy(norm64, q->norm, sizeof(float) * 64, hipMemcpyDeviceToHost));
-  return KR_OK;
+  try {
+    if (!q || !norm64) return fail(KR_EINVAL, "null argument");
+    HIP_TRY(hipMemcpy(norm64, q->norm, sizeof(float) * 64, hipMemcpyDeviceToHost));
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_set_normalization(kr_guess *q, const float *norm64) {
-  if (!q || !norm64) return fail(KR_EINVAL, "null argument");
-  for (int j = 0; j < 16; ++j)
-    if (!(norm64[16 + j] > 0.0f) || !(norm64[48 + j] > 0.0f)) return fail(KR_EINVAL, "standard deviations must be > 0");
-  HIP_TRY(hipMemcpy(q->norm, norm64, sizeof(float) * 64, hipMemcpyHostToDevice));
-  return KR_OK;
+  try {
+    if (!q || !norm64) return fail(KR_EINVAL, "null argument");
+    for (int j = 0; j < 16; ++j)
+      if (!(norm64[16 + j] > 0.0f) || !(norm64[48 + j] > 0.0f)) return fail(KR_EINVAL, "standard deviations must be > 0");
+    HIP_TRY(hipMemcpy(q->norm, norm64, sizeof(float) * 64, hipMemcpyHostToDevice));
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_features(const kr_guess *q, int64_t n, const double *states, int64_t ld, const double *T,
                                  const double *dt, double dt_scalar, float *X, kr_stream_t stream) {
-  if (!q || n < 0 || ld < n || (n && (!states || !T || !X))) return fail(KR_EINVAL, "bad feature arguments");
-  if (!n) return KR_OK;
-  long blocks = std::min<long>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(kr_guess_features_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, q->S, q->atoms,
-                     (long)n, states, (long)ld, T, dt, dt_scalar, X);
-  HIP_TRY(hipGetLastError());
-  return KR_OK;
+  try {
+    if (!q || n < 0 || ld < n || (n && (!states || !T || !X))) return fail(KR_EINVAL, "bad feature arguments");
+    if (!n) return KR_OK;
+    long blocks = std::min<long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(kr_guess_features_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, q->S, q->atoms,
+                       (long)n, states, (long)ld, T, dt, dt_scalar, X);
+    HIP_TRY(hipGetLastError());
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_targets(const kr_guess *q, int64_t n, const double *before, const double *T_before,
                                 const double *after, const double *T_after, int64_t ld, float *Y,
                                 kr_stream_t stream) {
-  if (!q || n < 0 || ld < n || (n && (!before || !after || !T_before || !T_after || !Y)))
-    return fail(KR_EINVAL, "bad target arguments");
-  if (!n) return KR_OK;
-  long blocks = std::min<long>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(kr_guess_targets_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, q->S, q->atoms,
-                     (long)n, before, T_before, after, T_after, (long)ld, Y);
-  HIP_TRY(hipGetLastError());
-  return KR_OK;
+  try {
+    if (!q || n < 0 || ld < n || (n && (!before || !after || !T_before || !T_after || !Y)))
+      return fail(KR_EINVAL, "bad target arguments");
+    if (!n) return KR_OK;
+    long blocks = std::min<long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(kr_guess_targets_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, q->S, q->atoms,
+                       (long)n, before, T_before, after, T_after, (long)ld, Y);
+    HIP_TRY(hipGetLastError());
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_fit_normalization(kr_guess *q, int64_t n, const float *X, const float *Y,
                                           kr_stream_t stream) {
-  if (!q || n < 2 || !X || !Y) return fail(KR_EINVAL, "bad normalisation arguments");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(q->device));
-  const float *src[2] = {X, Y};
-  const int wid[2] = {q->nin, q->nout};
-  for (int t = 0; t < 2; ++t) {
-    hipLaunchKernelGGL(kr_zero_doubles, dim3(1), dim3(64), 0, st, q->dacc, 32);
-    hipLaunchKernelGGL(kr_col_moments, dim3(1024), dim3(256), 0, st, (long)n, wid[t], src[t], q->dacc);
-    hipLaunchKernelGGL(kr_finish_moments, dim3(1), dim3(64), 0, st, (long)n, wid[t], q->dacc,
-                       q->norm + 32 * t, q->norm + 32 * t + 16);
-    HIP_TRY(hipGetLastError());
-  }
-  return KR_OK;
+  try {
+    if (!q || n < 2 || !X || !Y) return fail(KR_EINVAL, "bad normalisation arguments");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(q->device));
+    const float *src[2] = {X, Y};
+    const int wid[2] = {q->nin, q->nout};
+    for (int t = 0; t < 2; ++t) {
+      hipLaunchKernelGGL(kr_zero_doubles, dim3(1), dim3(64), 0, st, q->dacc, 32);
+      hipLaunchKernelGGL(kr_col_moments, dim3(1024), dim3(256), 0, st, (long)n, wid[t], src[t], q->dacc);
+      hipLaunchKernelGGL(kr_finish_moments, dim3(1), dim3(64), 0, st, (long)n, wid[t], q->dacc,
+                         q->norm + 32 * t, q->norm + 32 * t + 16);
+      HIP_TRY(hipGetLastError());
+    }
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_gradients(kr_guess *q, int32_t B, const float *X, const float *Y, float *grads,
                                   double *loss, kr_stream_t stream) {
-  if (!q || B < 1 || !X || !Y) return fail(KR_EINVAL, "bad gradient arguments");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(q->device));
-  int rc = guess_reserve(q, B);
-  if (rc) return rc;
-  if ((rc = guess_make_batch(q, B, B, 0, 0, 0, X, Y, st))) return rc;
-  if ((rc = guess_forward(q, B, st))) return rc;
-  if ((rc = guess_backward(q, B, st))) return rc;
-  if (grads) HIP_TRY(hipMemcpyAsync(grads, q->g, sizeof(float) * q->nparams, hipMemcpyDeviceToDevice, st));
-  if (loss) {
-    double s = 0.0;
-    HIP_TRY(hipMemcpyAsync(&s, q->dacc + 40, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    *loss = s / ((double)B * q->nout);
-  }
-  return KR_OK;
+  try {
+    if (!q || B < 1 || !X || !Y) return fail(KR_EINVAL, "bad gradient arguments");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(q->device));
+    int rc = guess_reserve(q, B);
+    if (rc) return rc;
+    if ((rc = guess_make_batch(q, B, B, 0, 0, 0, X, Y, st))) return rc;
+    if ((rc = guess_forward(q, B, st))) return rc;
+    if ((rc = guess_backward(q, B, st))) return rc;
+    if (grads) HIP_TRY(hipMemcpyAsync(grads, q->g, sizeof(float) * q->nparams, hipMemcpyDeviceToDevice, st));
+    if (loss) {
+      double s = 0.0;
+      HIP_TRY(hipMemcpyAsync(&s, q->dacc + 40, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      *loss = s / ((double)B * q->nout);
+    }
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_train(kr_guess *q, int64_t n, const float *X, const float *Y, const kr_train_opts *o,
                               double *last_loss, kr_stream_t stream) {
-  if (!q || !o || n < 1 || !X || !Y || o->batch < 1 || o->steps < 0 || !(o->lr > 0.0f))
-    return fail(KR_EINVAL, "bad training arguments");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(q->device));
-  int rc = guess_reserve(q, o->batch);
-  if (rc) return rc;
-  const double pi = 3.14159265358979323846;
-  for (int64_t t = 0; t < o->steps; ++t) {
-    /* seed 0: consecutive blocks of rows (deterministic, for checks);
-     * otherwise rows drawn uniformly with replacement */
-    const unsigned long long seed = o->seed * 0x9e3779b97f4a7c15ull + (unsigned long long)(q->step + 1);
-    long row0 = 0;
-    if (o->seed == 0 && n >= o->batch) row0 = (long)((q->step * (int64_t)o->batch) % (n - o->batch + 1));
-    if (o->seed == 0 && n < o->batch) return fail(KR_EINVAL, "sequential batches need n >= batch");
-    if ((rc = guess_make_batch(q, o->batch, n, o->seed != 0, seed, row0, X, Y, st))) return rc;
-    if ((rc = guess_forward(q, o->batch, st))) return rc;
-    if ((rc = guess_backward(q, o->batch, st))) return rc;
-    q->step++;
-    /* cosine decay from lr to lr_min over this call's steps */
-    const double frac = o->steps > 1 ? (double)t / (double)(o->steps - 1) : 1.0;
-    const float lr = (float)(o->lr_min + 0.5 * (o->lr - o->lr_min) * (1.0 + std::cos(pi * frac)));
-    const float c1 = (float)(1.0 - std::pow((double)o->beta1, (double)q->step));
-    const float c2 = (float)(1.0 - std::pow((double)o->beta2, (double)q->step));
-    hipLaunchKernelGGL(kr_adam, dim3(512), dim3(256), 0, st, q->nparams, q->w, q->wb, q->g, q->m, q->v, lr,
-                       o->beta1, o->beta2, o->eps, c1, c2);
-    HIP_TRY(hipGetLastError());
-  }
-  if (last_loss) {
-    double s = 0.0;
-    HIP_TRY(hipMemcpyAsync(&s, q->dacc + 40, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    *last_loss = s / ((double)o->batch * q->nout);
-  }
-  return KR_OK;
+  try {
+    if (!q || !o || n < 1 || !X || !Y || o->batch < 1 || o->steps < 0 || !(o->lr > 0.0f))
+      return fail(KR_EINVAL, "bad training arguments");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(q->device));
+    int rc = guess_reserve(q, o->batch);
+    if (rc) return rc;
+    const double pi = 3.14159265358979323846;
+    for (int64_t t = 0; t < o->steps; ++t) {
+      /* seed 0: consecutive blocks of rows (deterministic, for checks);
+       * otherwise rows drawn uniformly with replacement */
+      const unsigned long long seed = o->seed * 0x9e3779b97f4a7c15ull + (unsigned long long)(q->step + 1);
+      long row0 = 0;
+      if (o->seed == 0 && n >= o->batch) row0 = (long)((q->step * (int64_t)o->batch) % (n - o->batch + 1));
+      if (o->seed == 0 && n < o->batch) return fail(KR_EINVAL, "sequential batches need n >= batch");
+      if ((rc = guess_make_batch(q, o->batch, n, o->seed != 0, seed, row0, X, Y, st))) return rc;
+      if ((rc = guess_forward(q, o->batch, st))) return rc;
+      if ((rc = guess_backward(q, o->batch, st))) return rc;
+      q->step++;
+      /* cosine decay from lr to lr_min over this call's steps */
+      const double frac = o->steps > 1 ? (double)t / (double)(o->steps - 1) : 1.0;
+      const float lr = (float)(o->lr_min + 0.5 * (o->lr - o->lr_min) * (1.0 + std::cos(pi * frac)));
+      const float c1 = (float)(1.0 - std::pow((double)o->beta1, (double)q->step));
+      const float c2 = (float)(1.0 - std::pow((double)o->beta2, (double)q->step));
+      hipLaunchKernelGGL(kr_adam, dim3(512), dim3(256), 0, st, q->nparams, q->w, q->wb, q->g, q->m, q->v, lr,
+                         o->beta1, o->beta2, o->eps, c1, c2);
+      HIP_TRY(hipGetLastError());
+    }
+    if (last_loss) {
+      double s = 0.0;
+      HIP_TRY(hipMemcpyAsync(&s, q->dacc + 40, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      *last_loss = s / ((double)o->batch * q->nout);
+    }
+    return KR_OK;
+  } KR_CATCH
 }
 
 /* outputs (standardised) for n rows of raw features */
 extern "C" int kr_guess_forward(kr_guess *q, int64_t n, const float *X, float *out, kr_stream_t stream) {
-  if (!q || n < 0 || (n && (!X || !out))) return fail(KR_EINVAL, "bad forward arguments");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(q->device));
-  const int chunk = 65536;
-  int rc = guess_reserve(q, (int)std::min<int64_t>(n, chunk));
-  if (rc) return rc;
-  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
-    const int B = (int)std::min<int64_t>(chunk, n - r0);
-    if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X, nullptr, st))) return rc;
-    if ((rc = guess_forward(q, B, st))) return rc;
-    HIP_TRY(hipMemcpyAsync(out + (size_t)r0 * q->nout, q->out, sizeof(float) * B * q->nout,
-                           hipMemcpyDeviceToDevice, st));
-  }
-  return KR_OK;
+  try {
+    if (!q || n < 0 || (n && (!X || !out))) return fail(KR_EINVAL, "bad forward arguments");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(q->device));
+    const int chunk = 65536;
+    int rc = guess_reserve(q, (int)std::min<int64_t>(n, chunk));
+    if (rc) return rc;
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+      const int B = (int)std::min<int64_t>(chunk, n - r0);
+      if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X, nullptr, st))) return rc;
+      if ((rc = guess_forward(q, B, st))) return rc;
+      HIP_TRY(hipMemcpyAsync(out + (size_t)r0 * q->nout, q->out, sizeof(float) * B * q->nout,
+                             hipMemcpyDeviceToDevice, st));
+    }
+    return KR_OK;
+  } KR_CATCH
 }
 
 extern "C" int kr_guess_predict(kr_guess *q, int64_t n, const double *states, int64_t ld, const double *T,
                                 const double *dt, double dt_scalar, float *X_scratch, double *guess,
                                 int64_t guess_ld, kr_stream_t stream) {
-  if (!q || n < 0 || ld < n || guess_ld < n || (n && (!states || !T || !X_scratch || !guess)))
-    return fail(KR_EINVAL, "bad predict arguments");
-  if (!n) return KR_OK;
-  hipStream_t st = (hipStream_t)stream;
-  int rc = kr_guess_features(q, n, states, ld, T, dt, dt_scalar, X_scratch, stream);
-  if (rc) return rc;
-  const int chunk = 65536;
-  if ((rc = guess_reserve(q, (int)std::min<int64_t>(n, chunk)))) return rc;
-  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
-    const int B = (int)std::min<int64_t>(chunk, n - r0);
-    if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X_scratch, nullptr, st))) return rc;
-    if ((rc = guess_forward(q, B, st))) return rc;
-    hipLaunchKernelGGL(kr_guess_apply_kernel, dim3((B + 255) / 256), dim3(256), 0, st, q->S, q->atoms, (long)n,
-                       (long)r0, states, (long)ld, T, q->out, q->norm + 32, q->norm + 48, guess, (long)guess_ld);
-    HIP_TRY(hipGetLastError());
-  }
-  return KR_OK;
+  try {
+    if (!q || n < 0 || ld < n || guess_ld < n || (n && (!states || !T || !X_scratch || !guess)))
+      return fail(KR_EINVAL, "bad predict arguments");
+    if (!n) return KR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = kr_guess_features(q, n, states, ld, T, dt, dt_scalar, X_scratch, stream);
+    if (rc) return rc;
+    const int chunk = 65536;
+    if ((rc = guess_reserve(q, (int)std::min<int64_t>(n, chunk)))) return rc;
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+      const int B = (int)std::min<int64_t>(chunk, n - r0);
+      if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X_scratch, nullptr, st))) return rc;
+      if ((rc = guess_forward(q, B, st))) return rc;
+      hipLaunchKernelGGL(kr_guess_apply_kernel, dim3((B + 255) / 256), dim3(256), 0, st, q->S, q->atoms, (long)n,
+                         (long)r0, states, (long)ld, T, q->out, q->norm + 32, q->norm + 48, guess, (long)guess_ld);
+      HIP_TRY(hipGetLastError());
+    }
+    return KR_OK;
+  } KR_CATCH
 }

@@ -30,6 +30,20 @@ struct KrParams {
   unsigned long long *counters; /* [8] statistics (see kr_options), or null */
   const unsigned *order;  /* [n_cells] cell handed out at each claim, or null
                              for the input order */
+  double *h_hint;        /* [n_cells] in: first substep of the first attempt
+                            (used when positive and finite); out: the
+                            controller's proposed next length; or null */
+  double *h_log;         /* [h_log_cap][h_log_ld] accepted substep lengths of
+                            the attempt that produced the result, or null */
+  long long h_log_ld;
+  int h_log_cap;
+  int *h_log_n;          /* [n_cells] number of accepted substeps logged, or null */
+  unsigned long long *totals; /* [8] per-call totals (see KR_TOT_*), or null */
 };
+
+/* Per-call totals accumulated by the integrators (each wave flushes its own
+ * sums once, when the queue is empty). */
+enum { KR_TOT_CELLS = 0, KR_TOT_SUBSTEPS = 1, KR_TOT_ITERS = 2, KR_TOT_REJECTED = 3,
+       KR_TOT_NFAIL = 4, KR_TOT_RETRIED = 5, KR_TOT_REVERTED = 6, KR_TOT_MAXRESID = 7 };
 
 #endif

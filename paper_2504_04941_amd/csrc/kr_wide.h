@@ -404,10 +404,13 @@ __device__ __forceinline__ double kr_wweight(const KrWCell &C, double yn, double
   return a + C.rtol * fmax(fabs(yn), fabs(y));
 }
 
-/* Weighted element projection of a Newton update (FP32 form): d_S <- d_S -
- * W N^T (N W N^T)^-1 N d_S with W = diag(max(|y_s|, atol)).  The row sums are
- * wave reductions; the small Gram system is solved alike in every lane. */
-__device__ __forceinline__ double kr_wproject(double yl, double atol, double d) {
+/* Weighted element projection of a Newton update (FP32 form): corrects d_S
+ * so that y + d carries the conserved totals of the substep start y_n,
+ * d_S <- d_S - W N^T (N W N^T)^-1 (N d + N (y - y_n)) with W =
+ * diag(max(|y_s|, atol)) (the exact Newton update satisfies N (y + d) =
+ * N y_n from any starting point).  The row sums are wave reductions; the
+ * small Gram system is solved alike in every lane. */
+__device__ __forceinline__ double kr_wproject(double yl, double ynl, double atol, double d) {
   if (KR_NROWS == 0) return d;
   constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
   const int lane = threadIdx.x;
@@ -416,7 +419,7 @@ __device__ __forceinline__ double kr_wproject(double yl, double atol, double d) 
 #pragma unroll
   for (int a = 0; a < V; ++a) {
     const double na = lane < KR_S ? (double)kr_comp[a][lane] : 0.0;
-    r[a] = kr_u(kr_wsum(na * d));
+    r[a] = kr_u(kr_wsum(na * (d + (yl - ynl))));
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
       const double nb = lane < KR_S ? (double)kr_comp[b][lane] : 0.0;
@@ -538,7 +541,7 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
         ok = kr_wlu(a, pc64, dinv64);
         d = ok ? kr_wsolve(a, pc64, dinv64, b) : 0.0;
       }
-      if (ok) d = kr_wproject(y, C.atol, d);
+      if (ok) d = kr_wproject(y, yn, C.atol, d);
     }
     if (!ok) return false;
     const double yi = y + d;
@@ -557,18 +560,29 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
   return false;
 }
 
+/* Records the k-th accepted substep length of the running attempt (every
+ * lane stores the same value). */
+__device__ __forceinline__ void kr_wlog(const KrParams &p, const KrWCell &C, int k, double h) {
+  if (p.h_log && k < p.h_log_cap) p.h_log[(long long)k * p.h_log_ld + C.c] = h;
+}
+
 /* One attempt over [0, dt] from y0 (lane-distributed).  Adaptive: error
  * estimate err = max_i |(h/2)(g_i(y_new) - g_i(y_old))| / w_i (a running
  * maximum that skips 0/0); accepted when err <= 1, then h *= min(growth,
  * max(0.2, safety / sqrt(max(err, 1e-10)))); rejected: h *= max(0.2, safety /
- * sqrt(err)); Newton failure: h /= 4.  The last substep lands on dt.  Fails
- * when h < 1e-12 dt or after max_substeps substep attempts.  On success y
- * holds the end point. */
+ * sqrt(err)); Newton failure: h /= 4.  The first substep is h0 (the caller's
+ * hint or dt; dt/100 on the retry); the last lands on dt.  Fails when h <
+ * 1e-12 dt or after max_substeps substep attempts.  On success y holds the
+ * end point, nacc the accepted substeps and hnext the proposed length after
+ * the last one (the controller's update, or the unclipped length if larger). */
 template <bool MIXED>
 __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCell &C, double y0,
-                                            int attempt, double &y) {
+                                            int attempt, double hint, double &y, int &nacc,
+                                            double &hnext) {
   const int lane = threadIdx.x;
   double yn = y0;
+  nacc = 0;
+  hnext = 0.0;
   C.eps_n = kr_bcast(y0, KR_S) * kr_u(kr_wheatcap(y0));
   if (kr_ui(p.mode) == 1) {
     const int nf = kr_ui(p.n_fixed);
@@ -577,22 +591,24 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
       if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) { C.nfail++; return false; }
       yn = y;
       C.eps_n = kr_bcast(yn, KR_S) * kr_u(kr_wheatcap(yn));
+      kr_wlog(p, C, k, h);
       C.acc++;
     }
+    nacc = nf;
     y = yn;
     return true;
   }
-  const double h0 = attempt == 0 ? C.dt : C.dt / 100.0;
+  const double h0 = attempt == 0 ? ((hint > 0.0 && kr_finite(hint)) ? hint : C.dt) : C.dt / 100.0;
   const double safety = attempt == 0 ? 0.9 : 0.5;
   const double growth = attempt == 0 ? 5.0 : 2.0;
   const int max_substeps = kr_ui(p.max_substeps);
   kr_wrhs(w, yn);
   double gn = kr_wrate(w, kr_u(kr_wheatcap(yn)));
-  double t = 0.0, h = h0;
+  double t = 0.0, h = h0, hfree = 0.0;
   bool done = false;
   for (int attempts = 0; attempts < max_substeps; ++attempts) {
     bool fin = false;
-    if (h >= C.dt - t) { h = C.dt - t; fin = true; }
+    if (h >= C.dt - t) { hfree = h; h = C.dt - t; fin = true; }
     else if (h < 1e-12 * C.dt) break;
     if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) {
       C.nfail++;
@@ -608,10 +624,13 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
       yn = y;
       gn = g;
       C.eps_n = kr_bcast(y, KR_S) * cv;
+      kr_wlog(p, C, nacc, h);
+      nacc++;
       C.acc++;
-      if (fin) { done = true; break; }
+      const double hnew = h * fmin(growth, fmax(0.2, safety / sqrt(fmax(err, 1e-10))));
+      if (fin) { hnext = hfree > hnew ? hfree : hnew; done = true; break; }
       t += h;
-      h *= fmin(growth, fmax(0.2, safety / sqrt(fmax(err, 1e-10))));
+      h = hnew;
     } else {
       C.rej++;
       h *= fmax(0.2, safety / sqrt(err));
@@ -663,12 +682,14 @@ __device__ __forceinline__ int kr_wargmaxd(double v, bool cand) {
 }
 
 /* The three post-processing stages of Sec. 2.2.3 on the lane-distributed
- * end point y, with the initial row totals from y0. */
-__device__ __forceinline__ double kr_wpost(double y, double y0) {
+ * end point y, with the initial row totals from y0.  flags (wave-uniform):
+ * 1 a clip, 2 a break-up. */
+__device__ __forceinline__ double kr_wpost(double y, double y0, int &flags) {
   const int lane = threadIdx.x;
   double E0[KR_NROWS > 0 ? KR_NROWS : 1];
 #pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) E0[v] = kr_wrow(v, y0);
+  flags = kr_uany(lane < KR_S && y < 0.0) ? 1 : 0;
   if (lane < KR_S && y < 0.0) y = 0.0;
 #pragma unroll
   for (int v = 0; v < KR_NROWS; ++v) {
@@ -688,6 +709,7 @@ __device__ __forceinline__ double kr_wpost(double y, double y0) {
       const bool cand = lane < KR_S && lane != rs && !used && a != 0 && (a > 0 ? 1 : -1) == sign_r && y > 0.0;
       const int best = kr_wargmaxd(y, cand);
       if (best < 0) break;
+      flags |= 2;
       if (lane == best) used = true;
       const double yb = kr_bcast(y, best);
       const double need = -yr * kr_comp[v][rs] / kr_comp[v][best];
@@ -704,14 +726,32 @@ __device__ __forceinline__ double kr_wpost(double y, double y0) {
   return y;
 }
 
-/* Status and statistics of the cell.  Every lane stores the same (uniform)
- * values: no branch on the lane index, which the optimiser would otherwise
- * thread into the loop exits and so turn the uniform loops divergent. */
-__device__ __forceinline__ void kr_wstats(const KrParams &p, const KrWCell &C, int code) {
+/* Status, statistics, substep-log count (nlog) and per-call totals of the
+ * cell (resid: element residual after post-processing).  Every lane stores
+ * the same (uniform) values, and every lane adds to the totals (lanes other
+ * than 0 add zero): no branch on the lane index, which the optimiser would
+ * otherwise thread into the loop exits and so turn the uniform loops
+ * divergent. */
+__device__ __forceinline__ void kr_wstats(const KrParams &p, const KrWCell &C, int code, int nlog,
+                                          double resid) {
+  const int lane = threadIdx.x;
   if (p.status) p.status[C.c] = code;
   if (p.cell_stats) {
     int *st = p.cell_stats + 4 * C.c;
     st[0] = C.acc; st[1] = C.iters; st[2] = C.rej; st[3] = C.nfail;
+  }
+  if (p.h_log_n) p.h_log_n[C.c] = nlog;
+  if (p.totals) {
+    unsigned long long *t = p.totals;
+    const bool l0 = lane == 0;
+    atomicAdd(&t[KR_TOT_CELLS], l0 ? 1ull : 0ull);
+    atomicAdd(&t[KR_TOT_SUBSTEPS], l0 ? (unsigned long long)C.acc : 0ull);
+    atomicAdd(&t[KR_TOT_ITERS], l0 ? (unsigned long long)C.iters : 0ull);
+    atomicAdd(&t[KR_TOT_REJECTED], l0 ? (unsigned long long)C.rej : 0ull);
+    atomicAdd(&t[KR_TOT_NFAIL], l0 ? (unsigned long long)C.nfail : 0ull);
+    atomicAdd(&t[KR_TOT_RETRIED], l0 && code == 1 ? 1ull : 0ull);
+    atomicAdd(&t[KR_TOT_REVERTED], l0 && code == 2 ? 1ull : 0ull);
+    atomicMax(&t[KR_TOT_MAXRESID], l0 && resid > 0.0 ? (unsigned long long)__double_as_longlong(resid) : 0ull);
   }
 }
 
@@ -758,20 +798,21 @@ __device__ __forceinline__ void kr_wcell(const KrParams &p, KrWave &w, long long
   double dt;
   bool bad;
   const double y0 = kr_wload(p, c, dt, bad);
-  if (kr_uany(bad)) { kr_wstats(p, C, 2); return; }
+  if (kr_uany(bad)) { kr_wstats(p, C, 2, 0, 0.0); return; }
   if (dt == 0.0) {
     kr_wstore(p, c, y0);
-    kr_wstats(p, C, 0);
+    kr_wstats(p, C, 0, 0, 0.0);
     return;
   }
   C.dt = dt;
   const double nn = kr_u(kr_wsum(lane < KR_S ? kr_atoms[lane] * y0 : 0.0));
   C.atol = p.floor * nn;
   const int mode = kr_ui(p.mode);
-  int status = 2;
-  double y = y0;
+  const double hint = p.h_hint ? kr_u(p.h_hint[c]) : 0.0;
+  int status = 2, nacc = 0;
+  double y = y0, hnext = 0.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    bool ok = kr_wattempt<MIXED>(p, w, C, y0, attempt, y);
+    bool ok = kr_wattempt<MIXED>(p, w, C, y0, attempt, hint, y, nacc, hnext);
     if (ok) {
       const bool badv = lane < KR_N && !kr_finite(y);
       const bool neg = lane < KR_S && y < -1e-10 * nn;
@@ -780,10 +821,12 @@ __device__ __forceinline__ void kr_wcell(const KrParams &p, KrWave &w, long long
     if (ok) { status = attempt; break; }
     if (mode == 1) break;
   }
-  if (status == 2) { kr_wstats(p, C, 2); return; }
-  y = kr_wpost(y, y0);
+  if (status == 2) { kr_wstats(p, C, 2, 0, 0.0); return; }
+  int flags;
+  y = kr_wpost(y, y0, flags);
   kr_wstore(p, c, y);
-  kr_wstats(p, C, status);
+  if (p.h_hint && mode == 0) p.h_hint[c] = hnext;
+  kr_wstats(p, C, status, nacc, p.totals ? kr_wresid(y, y0, nn) : 0.0);
 }
 
 /* Claims cells one at a time for the wave; zeroes the Jacobian workspace
@@ -876,7 +919,30 @@ __device__ __forceinline__ void kr_worder_keys(const KrParams &p, unsigned char 
 #define KR_WAVES_PER_EU 1
 #endif
 
+/* Post-processing alone (Sec. 2.2.3) of the states in p.states, one cell per
+ * wave, with the conserved totals of `before` after pre-processing
+ * (negatives clipped); T is not touched.  flags[c] (or null): 1 a clip, 2 a
+ * break-up. */
+__device__ __forceinline__ void kr_wpost_cells(const KrParams &p, const double *before, int *flags) {
+  const int lane = threadIdx.x;
+  for (long long c = blockIdx.x; c < p.n_cells; c += gridDim.x) {
+    const int sl = lane < KR_S ? lane : KR_S - 1;
+    const double b = before[(long long)sl * p.ld + c];
+    const double y0 = lane < KR_S && b > 0.0 ? b : 0.0;
+    double y = lane < KR_S ? p.states[(long long)sl * p.ld + c] : 0.0;
+    int f;
+    y = kr_wpost(y, y0, f);
+    const double last = kr_bcast(y, KR_S - 1);
+    p.states[(long long)sl * p.ld + c] = lane < KR_S ? y : last;
+    if (flags) flags[c] = f;
+  }
+}
+
 #ifndef KR_NO_KERNELS
+extern "C" __global__ void __launch_bounds__(64, 1) kr_post(KrParams p, const double *before, int *flags) {
+  kr_wpost_cells(p, before, flags);
+}
+
 extern "C" __global__ void __launch_bounds__(64, 1) kr_timescale(KrParams p, double *out) {
   kr_wtimescale(p, out);
 }

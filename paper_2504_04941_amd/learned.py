@@ -69,9 +69,10 @@ def train(model: GuessModel, X, Y, steps: int, batch: int = 4096, lr: float = 1e
 
 
 def newton_counts(knet: Network, model: GuessModel | None, desc, n: int, salt: int,
-                  h=None, stream=None):
-    """Single-substep solves of n held-out cells with and without the guess:
-    returns dict(status, cell_stats, counters, states, T) for the run."""
+                  h=None, stream=None, precision: int = 0):
+    """Single-substep solves of n held-out cells with and without the guess
+    (precision: KR_FP64 or KR_FP32LU_REFINE): returns dict(status,
+    cell_stats, counters, states, T) for the run."""
     import torch
     dev = torch.device("cuda")
     cs = sy.cells_h_o_n(desc, n, 1, salt=salt)
@@ -84,9 +85,9 @@ def newton_counts(knet: Network, model: GuessModel | None, desc, n: int, salt: i
     counters = torch.zeros(8, dtype=torch.int64, device=dev)
     if model is not None:
         guess = model.predict(states, T, dt=h, stream=stream)
-        opts = guess_options(guess, counters, mode=KR_FIXED_STEP, n_fixed=1)
+        opts = guess_options(guess, counters, mode=KR_FIXED_STEP, n_fixed=1, precision=precision)
     else:
-        opts = default_options(mode=KR_FIXED_STEP, n_fixed=1)
+        opts = default_options(mode=KR_FIXED_STEP, n_fixed=1, precision=precision)
         opts.counters = counters.data_ptr()
     chem_integrate(knet, states, T, dt=h, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
                    stream=stream)

@@ -1,7 +1,10 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times: the whole batch runs on the GPU, and the oracle integrates a
 seeded sample of its cells one by one (the oracle cannot afford the whole
-batch).  Gates as for the small batches."""
+batch: 4096 cells of the small networks, 512 of the 48-species network,
+whose cells cost the oracle ~0.1 s each).  Gates as for the small batches on
+the sample; on the whole batch, every status is valid, reverted cells are
+rare, and the element residual of every cell not reverted is below 1e-12."""
 import numpy as np
 import pytest
 
@@ -11,7 +14,8 @@ from tests.test_parity_gpu import assert_parity
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SAMPLE = 24
+SAMPLE = 4096
+SAMPLE_LARGE = 512
 
 
 def _kr():
@@ -24,15 +28,33 @@ def _sub(cs, idx, dt=None):
                          None if dt is None else dt[idx].copy(), cs.dt_scalar)
 
 
-def _sample(n, seed):
-    return np.sort(np.random.default_rng(seed).choice(n, size=SAMPLE, replace=False))
+def _sample(n, seed, size=SAMPLE):
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(size, n), replace=False))
 
 
-def _check(oracle_lib, desc, cs, idx, n_g, T_g, st_g, stats_g, tol, label, dt=None, dt_scalar=0.0):
+def _whole_batch(kr, net, cs, n_dev, st, label):
+    """Every status valid, reverted cells rare, element residual of every
+    cell not reverted below 1e-12 (kr_element_residual on the whole batch)."""
+    resid = torch.empty(cs.n_cells, dtype=torch.float64, device="cuda")
+    kr.element_residual(net, torch.tensor(cs.n, device="cuda"), n_dev, resid=resid)
+    torch.cuda.synchronize()
+    r = resid.cpu().numpy()
+    hist = np.bincount(st, minlength=3)
+    print(f"{label}: status histogram {hist.tolist()}", flush=True)
+    assert hist.size == 3 and hist.sum() == cs.n_cells
+    assert hist[2] <= 1e-4 * cs.n_cells, hist
+    ok = st != 2
+    assert np.all(r[ok] < 1e-12), f"{label}: element residual {r[ok].max():.3e}"
+    return r
+
+
+def _check(oracle_lib, desc, cs, idx, n_g, T_g, st_g, stats_g, tol, label, dt=None, dt_scalar=0.0,
+           resid=None):
     sub = _sub(cs, idx, dt)
     orc = oracle_lib.OracleNet(desc).integrate(sub.n, sub.T, sub.rho, dt=None if dt is None else dt[idx],
                                                dt_scalar=dt_scalar)
-    gpu = (n_g[:, idx], T_g[idx], st_g[idx], stats_g[idx], np.zeros(len(idx)))
+    gpu = (n_g[:, idx], T_g[idx], st_g[idx], stats_g[idx],
+           np.zeros(len(idx)) if resid is None else resid[idx])
     return assert_parity(gpu, orc, sub, tol, label, desc=desc)
 
 
@@ -47,11 +69,14 @@ def test_h_o_n_2e20_cells(oracle_lib, prec, tol):
     T = torch.tensor(cs.T, device="cuda")
     st = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
     stats = torch.empty((1 << 20, 4), dtype=torch.int32, device="cuda")
-    kr.chem_integrate(net, n, T, dt_scalar=cs.dt_scalar, rtol=1e-6, opts=kr.default_options(precision=prec),
+    kr.chem_integrate(net, n, T, dt_scalar=cs.dt_scalar, rtol=1e-6,
+                      opts=kr.default_options(precision=prec, order=kr.KR_ORDER_WORK),
                       status=st, cell_stats=stats)
     torch.cuda.synchronize()
-    _check(oracle_lib, desc, cs, _sample(1 << 20, 5), n.cpu().numpy(), T.cpu().numpy(), st.cpu().numpy(),
-           stats.cpu().numpy(), tol, f"h_o_n 2^20 prec {prec}", dt_scalar=cs.dt_scalar)
+    stn = st.cpu().numpy()
+    r = _whole_batch(kr, net, cs, n, stn, f"h_o_n 2^20 prec {prec}")
+    _check(oracle_lib, desc, cs, _sample(1 << 20, 5), n.cpu().numpy(), T.cpu().numpy(), stn,
+           stats.cpu().numpy(), tol, f"h_o_n 2^20 prec {prec}", dt_scalar=cs.dt_scalar, resid=r)
     net.close()
 
 
@@ -77,8 +102,10 @@ def test_learned_guess_2e20_cells(oracle_lib):
                       status=st, cell_stats=stats)
     torch.cuda.synchronize()
     assert counters[0].item() == 1 << 20
-    _check(oracle_lib, desc, cs, _sample(1 << 20, 6), n.cpu().numpy(), T.cpu().numpy(), st.cpu().numpy(),
-           stats.cpu().numpy(), 1e-6, "h_o_n 2^20 fp32lu+guess", dt_scalar=cs.dt_scalar)
+    stn = st.cpu().numpy()
+    r = _whole_batch(kr, net, cs, n, stn, "h_o_n 2^20 fp32lu+guess")
+    _check(oracle_lib, desc, cs, _sample(1 << 20, 6), n.cpu().numpy(), T.cpu().numpy(), stn,
+           stats.cpu().numpy(), 1e-6, "h_o_n 2^20 fp32lu+guess", dt_scalar=cs.dt_scalar, resid=r)
     model.close()
     net.close()
 
@@ -108,16 +135,20 @@ def test_uneven_batch_2e22_cells(oracle_lib):
     multi.integrate(bufs, rtol=1e-6, opts=kr.default_options(precision=kr.KR_FP32LU_REFINE), use_graph=True)
     torch.cuda.synchronize()
     for k, (d, cs, dt, b) in enumerate(zip(descs, css, dts, bufs)):
+        stn = b["status"].cpu().numpy()
+        r = _whole_batch(kr, nets[k], cs, b["states"], stn, f"uneven {d.name}")
         _check(oracle_lib, d, cs, _sample(cs.n_cells, 7 + k), b["states"].cpu().numpy(), b["T"].cpu().numpy(),
-               b["status"].cpu().numpy(), b["cell_stats"].cpu().numpy(), 1e-6, f"uneven {d.name}", dt=dt)
+               stn, b["cell_stats"].cpu().numpy(), 1e-6, f"uneven {d.name}", dt=dt, resid=r)
     multi.close()
     for n in nets:
         n.close()
 
 
-def test_large48_2e18_cells(oracle_lib):
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)])
+def test_large48_2e18_cells(oracle_lib, prec, tol):
     """48 species, 2^18 cells, per-cell steps log-uniform in [1e-8, 1e-2] s,
-    plain FP64, one cell per wavefront."""
+    one cell per wavefront, plain FP64 and the FP32 LU form (the
+    configuration's stated form)."""
     kr = _kr()
     desc = sy.network_large48(3)
     cs = sy.cells_large48(desc, 1 << 18, 3)
@@ -127,8 +158,12 @@ def test_large48_2e18_cells(oracle_lib):
     T = torch.tensor(cs.T, device="cuda")
     st = torch.empty(1 << 18, dtype=torch.int32, device="cuda")
     stats = torch.empty((1 << 18, 4), dtype=torch.int32, device="cuda")
-    kr.chem_integrate(net, n, T, dt=torch.tensor(cs.dt, device="cuda"), rtol=1e-6, status=st, cell_stats=stats)
+    kr.chem_integrate(net, n, T, dt=torch.tensor(cs.dt, device="cuda"), rtol=1e-6,
+                      opts=kr.default_options(precision=prec, order=kr.KR_ORDER_WORK),
+                      status=st, cell_stats=stats)
     torch.cuda.synchronize()
-    _check(oracle_lib, desc, cs, _sample(1 << 18, 8), n.cpu().numpy(), T.cpu().numpy(), st.cpu().numpy(),
-           stats.cpu().numpy(), 1e-8, "large48 2^18", dt=cs.dt)
+    stn = st.cpu().numpy()
+    r = _whole_batch(kr, net, cs, n, stn, f"large48 2^18 prec {prec}")
+    _check(oracle_lib, desc, cs, _sample(1 << 18, 8, SAMPLE_LARGE), n.cpu().numpy(), T.cpu().numpy(), stn,
+           stats.cpu().numpy(), tol, f"large48 2^18 prec {prec}", dt=cs.dt, resid=r)
     net.close()

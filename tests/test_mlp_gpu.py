@@ -81,9 +81,20 @@ def test_gradients_match_reference(setup, B):
     ref_loss, ref = mlp.MLP(11, 10, 256, 3).gradients(model.get_params().astype(np.float64),
                                                       norm.astype(np.float64), X, Y)
     assert loss == pytest.approx(ref_loss, rel=1e-4)
+    scale = mlp.MLP(11, 10, 256, 3).gradient_scales(model.get_params().astype(np.float64),
+                                                    norm.astype(np.float64), X, Y)
+    # element by element, against each entry's own scale (its sum taken over
+    # absolute terms): FP32 accumulation over B rows contributes ~B 2^-24 of
+    # the scale, and a BF16 rounding of an activation or of dz that lands on
+    # the other side of a rounding boundary (the FP32 intermediate differs
+    # from the FP64 one in its last bits) one BF16 ulp, 2^-8, of one term
+    tol = 2.0 ** -7
     for ws, bs, fo, fi in model.layer_slices():
         for sl in (ws, bs):
-            a, b = g[sl], ref[sl]
+            a, b, sc = g[sl], ref[sl], scale[sl]
+            err = np.abs(a - b) / np.maximum(sc, 1e-30)
+            assert err.max() <= tol, (sl, err.max())
+            assert np.percentile(err, 99.9) <= 1e-3, (sl, np.percentile(err, 99.9))
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
             assert rel < 1e-3, (sl, rel)
 
@@ -155,3 +166,93 @@ def test_guess_keeps_the_plain_result(setup, oracle_lib):
         err = np.maximum(np.abs(ng[s] - n_o[s]) - slack, 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
         assert err.max() <= 1e-6, (s, err.max())
     np.testing.assert_allclose(T.cpu().numpy(), T_o, rtol=1e-6)
+
+
+def test_feature_target_and_start_map(setup):
+    """kr_guess_features / kr_guess_targets / kr_guess_predict against the
+    oracle's map (oracle/mlp.py: features, targets, starting_point), element
+    by element: features and targets are FP64 values rounded once to FP32 on
+    the device, so they equal the oracle's rounded to FP32 (1 ulp where the
+    two FP64 values straddle an FP32 rounding boundary); the starting point
+    is FP64 from the network's FP32 outputs."""
+    kr, desc, knet, model, norm = setup
+    mlp = _oracle_mlp()
+    cs = sy.cells_h_o_n(desc, 300, 1, salt=77)
+    rng = np.random.default_rng(8)
+    n = cs.n.copy()
+    n[rng.integers(9, size=40), rng.integers(300, size=40)] = 0.0     # below the floor
+    h = 10.0 ** rng.uniform(-10, -4, 300)
+    atoms = np.abs(np.asarray(desc.composition)[:desc.n_elem]).sum(axis=0).astype(float)
+    nd, Td, hd = (torch.tensor(a, device="cuda") for a in (n, cs.T, h))
+    X = model.features(nd, Td, dt=hd).cpu().numpy()
+    Xo = mlp.features(atoms, n, cs.T, h)
+    ulp = np.spacing(np.abs(Xo).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(X - Xo.astype(np.float32)) <= ulp)
+    assert np.mean(X == Xo.astype(np.float32)) > 0.999
+    # targets between two states of the same cells
+    n2 = n * np.exp(0.01 * rng.standard_normal(n.shape))
+    T2 = cs.T * (1 + 0.01 * rng.standard_normal(300))
+    Y = model.targets(nd, Td, torch.tensor(n2, device="cuda"), torch.tensor(T2, device="cuda")).cpu().numpy()
+    Yo = mlp.targets(atoms, n, cs.T, n2, T2)
+    ulp = np.spacing(np.abs(Yo).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Y - Yo.astype(np.float32)) <= ulp)
+    # the starting point from the network's own outputs on those features
+    out = model.forward(torch.tensor(X, device="cuda")).cpu().numpy()
+    guess = model.predict(nd, Td, dt=hd).cpu().numpy()
+    yo = mlp.starting_point(atoms, n, cs.T, out, norm.astype(np.float64))
+    np.testing.assert_allclose(guess, yo, rtol=1e-12, atol=0)
+
+
+def test_fp32lu_with_non_conserving_guess(oracle_lib):
+    """Form (1) started from a guess that does not conserve the element
+    totals, in single-substep mode (the guessed substep is accepted): the
+    projection must bring the iterate back to the substep start's totals.
+    Statuses, abundances and element residuals match the plain start and
+    the oracle, in both precisions."""
+    kr = _kr()
+    desc = sy.network_h_o_n(1)
+    knet = kr.Network(desc)
+    cs = sy.cells_h_o_n(desc, 256, 1, salt=55)
+    rng = np.random.default_rng(21)
+    h = 10.0 ** rng.uniform(-10, -6, 256)
+    on = oracle_lib.OracleNet(desc)
+    o = oracle_lib.default_opts()
+    o.mode = oracle_lib.FIXED
+    o.n_fixed = 1
+    n_o, T_o, st_o, _ = on.integrate(cs.n, cs.T, dt=h, opts=o)
+    assert np.all(st_o == 0)
+    # most of the way to the root, each species by its own fraction: the
+    # element totals are off by ~5 % of the substep's change
+    f = 0.95 + 0.05 * rng.standard_normal((10, 256))
+    y0 = np.vstack([cs.n, cs.T[None, :]])
+    yr = np.vstack([n_o, T_o[None, :]])
+    guess = y0 + (yr - y0) * f
+    comp = np.asarray(desc.composition, float)
+    drift = np.abs(comp @ (guess[:9] - cs.n)) / (np.abs(comp) @ cs.n)
+    assert np.median(drift.max(axis=0)) > 1e-10      # the guess does not conserve
+    nnuc = cs.n.sum(axis=0)
+    for prec in (kr.KR_FP64, kr.KR_FP32LU_REFINE):
+        n = torch.tensor(cs.n, device="cuda")
+        T = torch.tensor(cs.T, device="cuda")
+        g = torch.tensor(guess, device="cuda")
+        counters = torch.zeros(8, dtype=torch.int64, device="cuda")
+        status = torch.empty(256, dtype=torch.int32, device="cuda")
+        kr.chem_integrate(knet, n, T, dt=torch.tensor(h, device="cuda"), rtol=1e-6,
+                          opts=kr.guess_options(g, counters, mode=kr.KR_FIXED_STEP, n_fixed=1,
+                                                precision=prec), status=status)
+        resid = torch.zeros(256, dtype=torch.float64, device="cuda")
+        kr.element_residual(knet, torch.tensor(cs.n, device="cuda"), n, resid=resid)
+        torch.cuda.synchronize()
+        c = counters.cpu().numpy()
+        assert c[0] == 256
+        assert c[1] < 0.5 * 256, c            # most guessed substeps are kept
+        np.testing.assert_array_equal(status.cpu().numpy(), st_o)
+        assert resid.cpu().numpy().max() < 1e-12
+        ng = n.cpu().numpy()
+        res = set(int(r) for r in desc.reservoir)
+        for s in range(9):
+            slack = 1e-11 * nnuc if s in res else 0.0
+            err = np.maximum(np.abs(ng[s] - n_o[s]) - slack, 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
+            assert err.max() <= 1e-6, (prec, s, err.max())
+        np.testing.assert_allclose(T.cpu().numpy(), T_o, rtol=1e-6)
+    knet.close()
