@@ -135,18 +135,21 @@ def test_h_hint_in_and_out(oracle_lib, wave):
         # the first accepted length: the hint itself when accepted at once
         if a["h_log"][0, c] == hint[c]:
             assert g["h_log"][0, c] == hint[c]
-        # lengths agree to the rounding of the controller's factors; the last
-        # one, dt - t, also to the rounding of t, a sum of n lengths (n eps dt)
+        # each length is the previous one times a factor of the error
+        # estimate, (h/2)|g(y_new) - g(y_old)|: a difference of rates that can
+        # cancel to a few digits, so the two sides' lengths agree to ~1e-9
+        # and drift further along a sequence; the last one, dt - t, also
+        # carries the rounding of t, a sum of n lengths (n eps dt)
         at = 2.0 * n * np.finfo(float).eps * 1e-4
-        np.testing.assert_allclose(g["h_log"][:n, c], a["h_log"][:n, c], rtol=1e-9, atol=at)
-        assert g["h_hint"][c] == pytest.approx(a["h_hint"][c], rel=1e-9, abs=at)
+        np.testing.assert_allclose(g["h_log"][:n, c], a["h_log"][:n, c], rtol=1e-6, atol=at)
+        assert g["h_hint"][c] == pytest.approx(a["h_hint"][c], rel=1e-6, abs=at)
     # unusable hints act as no hint: the first attempted length is dt
     b = on.integrate_ex(cs.n, cs.T, dt_scalar=1e-4, log_cap=20000)
     for c in list(range(0, 128, 9)) + list(range(4, 128, 9)):
         if same[c]:
             m = g["h_log_n"][c]
             np.testing.assert_allclose(g["h_log"][:m, c], b["h_log"][:b["h_log_n"][c], c],
-                                       rtol=1e-9, atol=2.0 * m * np.finfo(float).eps * 1e-4)
+                                       rtol=1e-6, atol=2.0 * m * np.finfo(float).eps * 1e-4)
 
 
 def test_h_hint_fixed_mode_untouched():
