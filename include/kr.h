@@ -294,6 +294,25 @@ int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states,
                       const kr_options *opt, int32_t *status,
                       int32_t *cell_stats, kr_stream_t stream);
 
+/* kr_chem_integrate for callers that cannot allocate (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and results, but no allocation of any kind.  Its
+ * workspace (work counter, totals, cell-order buffers) is a static device
+ * array of KR_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends;
+ * its device address is looked up when the first network is created on that
+ * GPU.  KR_ORDER_WORK is limited to KR_NOALLOC_MAX_ORDER_CELLS cells
+ * (KR_EINVAL beyond); input order has no size limit.  Every call on one GPU
+ * shares the array: calls that overlap on one GPU (different streams, or
+ * different networks concurrently) race and give wrong results, so
+ * serialise them per GPU.  Errors as kr_chem_integrate. */
+#define KR_NOALLOC_SCRATCH_BYTES (8ll << 20)
+#define KR_NOALLOC_MAX_ORDER_CELLS ((KR_NOALLOC_SCRATCH_BYTES - 4096) / 5)
+int kr_chem_integrate_noalloc(const kr_network *net, int64_t n_cells, double *states,
+                              int64_t ld, double *T, const double *rho,
+                              const double *dt, double dt_scalar, double rtol,
+                              const kr_options *opt, int32_t *status,
+                              int32_t *cell_stats, kr_stream_t stream);
+
 /* The order in which kr_chem_integrate with KR_ORDER_WORK hands out this
  * batch's cells: order[i] = index of the i-th cell handed out, largest
  * expected work first (see KR_ORDER_WORK; cells of one half-octave bucket

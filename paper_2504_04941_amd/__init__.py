@@ -29,6 +29,8 @@ KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
 KR_ORDER_INPUT, KR_ORDER_WORK = 0, 1
 KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
 KR_WIDE_MIN_SPECIES = 16
+KR_NOALLOC_SCRATCH_BYTES = 8 << 20
+KR_NOALLOC_MAX_ORDER_CELLS = (KR_NOALLOC_SCRATCH_BYTES - 4096) // 5
 
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns", "kr_network_layout",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
@@ -125,6 +127,7 @@ def lib():
         L.kr_element_residual.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                           C.c_int64, C.c_void_p, C.POINTER(C.c_double),
                                           C.c_void_p]
+        L.kr_chem_integrate_noalloc.argtypes = L.kr_chem_integrate.argtypes
         L.kr_postprocess.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_void_p, C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
@@ -289,7 +292,7 @@ def _stream_ptr(stream):
 def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
                    rtol: float = 1e-6, opts: Options | None = None, status=None,
                    cell_stats=None, stream=None, h_hint=None, h_log=None, h_log_n=None,
-                   stats: bool = False):
+                   stats: bool = False, noalloc: bool = False):
     """kr_chem_integrate on device tensors.
 
     states: float64 [S, ld] with unit stride along cells (row stride = ld);
@@ -297,7 +300,9 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
     cell_stats: int32 [n_cells, 4]; h_hint: float64 [n_cells] in/out;
     h_log: float64 [cap, ld] (unit stride along cells) with h_log_n int32
     [n_cells].  Asynchronous on the stream unless stats=True, which returns
-    the call's kr_stats totals as a dict (and synchronises)."""
+    the call's kr_stats totals as a dict (and synchronises).  noalloc=True
+    calls kr_chem_integrate_noalloc (no allocation; a static per-GPU
+    workspace)."""
     import torch
     if h_hint is not None or h_log is not None or h_log_n is not None or stats:
         o = Options.from_buffer_copy(opts if opts is not None else default_options())
@@ -320,7 +325,7 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
         if stats:
             o.stats = C.pointer(st)
         chem_integrate(net, states, T, rho=rho, dt=dt, dt_scalar=dt_scalar, rtol=rtol, opts=o,
-                       status=status, cell_stats=cell_stats, stream=stream)
+                       status=status, cell_stats=cell_stats, stream=stream, noalloc=noalloc)
         return st.as_dict() if stats else None
     n_cells = int(T.numel())
     if states.dim() != 2 or states.shape[0] != net.n_species or states.stride(1) != 1:
@@ -335,7 +340,8 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
     if status is not None and status.numel() != n_cells:
         raise ValueError("status must have one entry per cell")
     o = opts if opts is not None else default_options()
-    _check(lib().kr_chem_integrate(
+    fn = lib().kr_chem_integrate_noalloc if noalloc else lib().kr_chem_integrate
+    _check(fn(
         net.handle, n_cells, _dev_ptr(states, torch.float64, "states"), ld,
         _dev_ptr(T, torch.float64, "T"), _dev_ptr(rho, torch.float64, "rho"),
         _dev_ptr(dt, torch.float64, "dt"), float(dt_scalar), float(rtol), C.byref(o),

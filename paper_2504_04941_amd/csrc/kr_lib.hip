@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,7 @@ static const char *kOrderSource =
 
 static const double kBoltzmann = 1.380649e-16; /* erg / K */
 static const int KR_ORDER_NBUCKETS = 256;       /* KR_ORDER_BUCKETS of kr_order.h */
+static const int KR_MAX_DEVICES = 64;           /* devices with a scratch address slot */
 
 /* ------------------------------------------------------------------------ */
 /* errors                                                                    */
@@ -89,6 +91,8 @@ static int fail(int code, const char *fmt, ...) {
   } while (0)
 
 extern "C" const char *kr_last_error(void) { return g_err.c_str(); }
+
+static int scratch_setup(int device);
 
 /* ------------------------------------------------------------------------ */
 /* network                                                                   */
@@ -641,6 +645,10 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
       }                                                                                 \
     } while (0)
     CREATE_TRY(hipGetDevice(&n->device));
+    if ((rc = scratch_setup(n->device)) != KR_OK) {
+      release(n);
+      return rc;
+    }
     CREATE_TRY(hipDeviceGetAttribute(&n->cu_count, hipDeviceAttributeMultiprocessorCount, n->device));
     CREATE_TRY(hipModuleLoadData(&n->module, code.data()));
     CREATE_TRY(hipModuleGetFunction(&n->f_fp64, n->module, "kr_integrate_fp64"));
@@ -861,71 +869,156 @@ extern "C" void kr_default_options(kr_options *o) {
   }
 }
 
+/* Device buffers one integrate call works in: the work counter, the totals
+ * block ([16]: KR_TOT_* then this call's statistics counters) and the
+ * cell-order buffers.  grow_order: the order buffers may be (re)allocated
+ * to fit the batch; otherwise they must already hold order_cap cells. */
+struct Workspace {
+  unsigned long long *counter;
+  unsigned long long *totals;
+  OrderBufs *ord;
+  bool grow_order;
+  bool clear_hist;   /* the order histogram's contents are unknown: clear it */
+};
+
+static int integrate_impl(const kr_network *net, int64_t n_cells, double *states, int64_t ld, double *T,
+                          const double *rho, const double *dt, double dt_scalar, double rtol,
+                          const kr_options *opt, int32_t *status, int32_t *cell_stats, kr_stream_t stream,
+                          Workspace &ws) {
+  if (!net) return fail(KR_EINVAL, "null network");
+  if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
+  kr_options o;
+  kr_default_options(&o);
+  if (opt) o = *opt;
+  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+      (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
+      o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
+      !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
+    return fail(KR_EINVAL, "bad options");
+  if (n_cells == 0) return KR_OK;
+  if (!states || !T) return fail(KR_EINVAL, "null state arrays");
+  if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
+  if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
+  if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
+  if (o.h_log && (o.h_log_ld < n_cells || o.h_log_cap < 0)) return fail(KR_EINVAL, "h_log_ld < n_cells or h_log_cap < 0");
+  const bool ordered = want_order(o, n_cells);
+  if (ordered && !ws.grow_order && n_cells > ws.ord->cap)
+    return fail(KR_EINVAL, "KR_ORDER_WORK batch of %lld cells exceeds the %lld-cell order scratch", (long long)n_cells,
+                ws.ord->cap);
+  HIP_TRY(hipSetDevice(net->device));
+  hipStream_t st = (hipStream_t)stream;
+
+  KrParams p;
+  p.n_cells = n_cells; p.states = states; p.ld = ld; p.T = T; p.rho = rho; p.dt = dt;
+  p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
+  p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
+  p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
+  p.counter = ws.counter;
+  p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
+  p.order = nullptr;
+  p.h_hint = o.h_hint; p.h_log = o.h_log; p.h_log_ld = o.h_log_ld; p.h_log_cap = o.h_log_cap;
+  p.h_log_n = o.h_log_n;
+  p.totals = nullptr;
+  if (o.stats) {
+    /* totals and this call's statistics counters in the workspace's block,
+     * cleared by a kernel on the stream */
+    hipLaunchKernelGGL(kr_zero_u64n, dim3(1), dim3(64), 0, st, ws.totals, 16);
+    HIP_TRY(hipGetLastError());
+    p.totals = ws.totals;
+    p.counters = ws.totals + 8;
+  }
+  if (ordered) {
+    int rc = ws.grow_order ? order_reserve(*ws.ord, n_cells) : KR_OK;
+    if (rc == KR_OK && ws.clear_hist) {
+      hipLaunchKernelGGL(kr_zero_u64n, dim3(1), dim3(64), 0, st, (unsigned long long *)ws.ord->hist,
+                         KR_ORDER_NBUCKETS / 2);
+      if (hipGetLastError() != hipSuccess) rc = fail(KR_EDEVICE, "order histogram clear failed");
+    }
+    if (rc == KR_OK)
+      rc = order_launch(net->f_keys, net->f_scan, net->f_scatter, *ws.ord, net->wide, net->cu_count, p, st);
+    if (rc != KR_OK) return rc;
+  }
+
+  unsigned long long *cnt = ws.counter;
+  void *rargs[] = {&cnt};
+  HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
+  hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
+  const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
+  long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
+  const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
+  if (blocks > need) blocks = need;
+  if (blocks < 1) blocks = 1;
+  void *args[] = {&p};
+  HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
+  if (o.stats) return finish_stats(ws.totals, o.counters, o.stats, st);
+  return KR_OK;
+}
+
 extern "C" int kr_chem_integrate(const kr_network *net, int64_t n_cells, double *states, int64_t ld,
                                  double *T, const double *rho, const double *dt, double dt_scalar,
                                  double rtol, const kr_options *opt, int32_t *status,
                                  int32_t *cell_stats, kr_stream_t stream) {
   try {
     if (!net) return fail(KR_EINVAL, "null network");
-    if (n_cells < 0 || ld < n_cells) return fail(KR_EINVAL, "bad n_cells/ld (%lld, %lld)", (long long)n_cells, (long long)ld);
-    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(KR_EINVAL, "rtol must be > 0");
-    kr_options o;
-    kr_default_options(&o);
-    if (opt) o = *opt;
-    if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
-        (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
-        o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
-        !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
-      return fail(KR_EINVAL, "bad options");
-    if (n_cells == 0) return KR_OK;
-    if (!states || !T) return fail(KR_EINVAL, "null state arrays");
-    if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
-    HIP_TRY(hipSetDevice(net->device));
-    hipStream_t st = (hipStream_t)stream;
+    kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
+    Workspace ws{net->d_counter, net->d_totals, &mnet->ord, true, false};
+    return integrate_impl(net, n_cells, states, ld, T, rho, dt, dt_scalar, rtol, opt, status, cell_stats,
+                          stream, ws);
+  } KR_CATCH
+}
 
-    KrParams p;
-    p.n_cells = n_cells; p.states = states; p.ld = ld; p.T = T; p.rho = rho; p.dt = dt;
-    p.dt_scalar = dt_scalar; p.rtol = rtol; p.floor = o.floor; p.newton_tol = o.newton_tol;
-    p.rho_floor = o.rho_floor; p.max_newton = o.max_newton; p.max_substeps = o.max_substeps;
-    p.mode = o.mode; p.n_fixed = o.n_fixed; p.status = status; p.cell_stats = cell_stats;
-    p.counter = net->d_counter;
-    if (o.guess && o.guess_ld < n_cells) return fail(KR_EINVAL, "guess_ld < n_cells");
-    if (o.guess && net->wide) return fail(KR_EINVAL, "a learned guess is not supported in the wavefront layout");
-    p.guess = o.guess; p.guess_ld = o.guess_ld; p.counters = o.counters;
-    p.order = nullptr;
-    if (o.h_log && (o.h_log_ld < n_cells || o.h_log_cap < 0)) return fail(KR_EINVAL, "h_log_ld < n_cells or h_log_cap < 0");
-    p.h_hint = o.h_hint; p.h_log = o.h_log; p.h_log_ld = o.h_log_ld; p.h_log_cap = o.h_log_cap;
-    p.h_log_n = o.h_log_n;
-    p.totals = nullptr;
-    if (o.stats) {
-      /* totals and this call's statistics counters in the network's block,
-       * cleared by a kernel on the stream */
-      hipLaunchKernelGGL(kr_zero_u64n, dim3(1), dim3(64), 0, st, net->d_totals, 16);
-      HIP_TRY(hipGetLastError());
-      p.totals = net->d_totals;
-      p.counters = net->d_totals + 8;
-    }
-    if (want_order(o, n_cells)) {
-      kr_network *mnet = const_cast<kr_network *>(net);   /* scratch buffers only */
-      int rc = order_reserve(mnet->ord, n_cells);
-      if (rc == KR_OK)
-        rc = order_launch(net->f_keys, net->f_scan, net->f_scatter, net->ord, net->wide, net->cu_count, p, st);
-      if (rc != KR_OK) return rc;
-    }
+/* ------------------------------------------------------------------------ */
+/* integration without allocations                                          */
+/* ------------------------------------------------------------------------ */
 
-    unsigned long long *cnt = net->d_counter;
-    void *rargs[] = {&cnt};
-    HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
-    hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
-    const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
-    long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
-    const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    void *args[] = {&p};
-    HIP_TRY(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, st, args, nullptr));
-    if (o.stats) return finish_stats(net->d_totals, o.counters, o.stats, st);
-    return KR_OK;
+/* The workspace of kr_chem_integrate_noalloc: one static device array per
+ * GPU, held until the process ends.  Layout (bytes): [0, 8) work counter,
+ * [256, 384) totals block, [512, 2560) order histogram and bucket starts,
+ * [4096, 4096 + 4 n) cell order, then n bucket bytes (n <= the order
+ * capacity).  In host code `scratch` names a host-side stand-in; its device
+ * address comes from hipGetSymbolAddress, kept per device. */
+static __device__ __align__(256) unsigned char scratch[KR_NOALLOC_SCRATCH_BYTES];
+
+static const long long kScratchOrderBase = 4096;
+static const long long kScratchOrderCap = (KR_NOALLOC_SCRATCH_BYTES - kScratchOrderBase) / 5;
+
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[KR_MAX_DEVICES];
+
+/* Looks up (once per device, with that device current) the device address of
+ * the scratch array.  Called by kr_network_create. */
+static int scratch_setup(int device) {
+  if (device < 0 || device >= KR_MAX_DEVICES) return fail(KR_EDEVICE, "device index %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return KR_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(KR_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_ptr[device] = (unsigned char *)ptr;
+  return KR_OK;
+}
+
+extern "C" int kr_chem_integrate_noalloc(const kr_network *net, int64_t n_cells, double *states, int64_t ld,
+                                         double *T, const double *rho, const double *dt, double dt_scalar,
+                                         double rtol, const kr_options *opt, int32_t *status,
+                                         int32_t *cell_stats, kr_stream_t stream) {
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    unsigned char *base = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (net->device >= 0 && net->device < KR_MAX_DEVICES) base = g_scratch_ptr[net->device];
+    }
+    if (!base) return fail(KR_EDEVICE, "no scratch address for device %d", net->device);
+    OrderBufs ob;
+    ob.hist = (unsigned *)(base + 512);
+    ob.order = (unsigned *)(base + kScratchOrderBase);
+    ob.bucket = base + kScratchOrderBase + 4 * kScratchOrderCap;
+    ob.cap = kScratchOrderCap;
+    Workspace ws{(unsigned long long *)base, (unsigned long long *)(base + 256), &ob, false, true};
+    return integrate_impl(net, n_cells, states, ld, T, rho, dt, dt_scalar, rtol, opt, status, cell_stats,
+                          stream, ws);
   } KR_CATCH
 }
 
