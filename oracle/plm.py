@@ -116,26 +116,8 @@ def ssp_rk2(n, rho, v, xc, xf, dt, P=None, limit=True):
 
 
 # --------------------------------------------------------------------------
-# the advection test of Sec. 4.1
+# the advection test of Sec. 4.1 (its inputs: synthetic.e1_initial)
 # --------------------------------------------------------------------------
 
-E1_SPECIES = ("A", "A2", "AB", "B")
 E1_COMP = np.array([[1, 2, 1, 0],      # element A
                     [0, 0, 1, 1]])     # element B
-
-
-def e1_initial(xc):
-    """Abundances [4, n] of A, A2, AB, B at cell centres xc in [-0.5, 0.5]:
-    steps at x = 0 plus linear parts (the test's initial profiles)."""
-    h = (np.asarray(xc) > 0).astype(float)
-    hm = 1.0 - h
-    x = np.asarray(xc, np.float64)
-    return np.vstack([0.49 * hm + 0.05 * h + 0.2 * x,
-                      0.20 * hm + 0.40 * h - 0.1 * x,
-                      0.01 * hm + 0.05 * h,
-                      0.09 * hm + 0.05 * h])
-
-
-def uniform_grid(n, lo=-0.5, hi=0.5):
-    xf = np.linspace(lo, hi, n + 1)
-    return 0.5 * (xf[:-1] + xf[1:]), xf

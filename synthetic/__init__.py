@@ -497,6 +497,77 @@ def log_uniform(n: int, lo: float, hi: float, config_index: int, salt: int) -> n
     return 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=n)
 
 
+# ----------------------------------------------------------------------------
+# species advection (Sec. 2.1 and the advection test of Sec. 4.1)
+# ----------------------------------------------------------------------------
+
+def network_e1() -> NetworkDesc:
+    """Passive species A, A2, AB, B over elements A and B (the advection
+    test's species); two reversible reactions 2 A <=> A2 and A + B <=> AB make
+    it a complete description (advection does not use them)."""
+    species = ["A", "A2", "AB", "B"]
+    comp = np.array([[1, 2, 1, 0],
+                     [0, 0, 1, 1]], np.int32)
+    reac = np.array([[0, 0, -1], [0, 3, -1]], np.int32)
+    prod = np.array([[1, -1, -1], [2, -1, -1]], np.int32)
+    arr = np.array([[1e-12, 0.0, 0.0], [1e-12, 0.0, 0.0]])
+    return NetworkDesc("e1_4sp", species, ["A", "B"], 2, comp, np.array([0, 3], np.int32),
+                       np.array([1.5, 2.5, 2.5, 1.5]), np.array([0.0, -1e4, -1e4, 0.0]),
+                       np.zeros(4), reac, prod, arr, None, p_ref=ATM, T_min=1.0, T_max=1.0e6)
+
+
+def uniform_grid(n: int, lo: float = -0.5, hi: float = 0.5):
+    """Cell centres [n] and faces [n + 1] of a uniform 1-D grid."""
+    xf = np.linspace(lo, hi, n + 1)
+    return 0.5 * (xf[:-1] + xf[1:]), xf
+
+
+def e1_initial(xc) -> np.ndarray:
+    """Abundances [4, n] of A, A2, AB, B at the cell centres xc in [-0.5, 0.5]
+    (the advection test's initial profiles: steps at x = 0 plus linear
+    parts; element abundances 0.9 and 0.1 everywhere)."""
+    x = np.asarray(xc, np.float64)
+    h = (x > 0).astype(float)
+    hm = 1.0 - h
+    return np.vstack([0.49 * hm + 0.05 * h + 0.2 * x,
+                      0.20 * hm + 0.40 * h - 0.1 * x,
+                      0.01 * hm + 0.05 * h,
+                      0.09 * hm + 0.05 * h])
+
+
+def advection_lines(net: NetworkDesc, n_lines: int, n_cells: int, seed_index: int = 5):
+    """Seeded lines for the advection kernel: per line, the cells of a
+    random composition of the network's own cell recipe mixed along the line
+    with a smooth wave and a step (element abundances vary per line, not
+    along it: each cell is a mixture of the line's two end states moved
+    along reaction directions); a non-uniform grid (faces jittered by up to
+    30 % of the spacing); density 1 + 0.5 sin; velocity +1 or -1 per line.
+    Returns (n [S, n_lines * n_cells], rho, xc [n_cells], xf [n_cells + 1],
+    v [n_lines])."""
+    rng = rng_for(seed_index, salt=77)
+    S = net.n_species
+    # reaction directions (net stoichiometry of the network's reactions)
+    null = np.asarray(net.stoich(), np.float64)
+    xf = np.linspace(0.0, 1.0, n_cells + 1)
+    h = 1.0 / n_cells
+    xf[1:-1] += rng.uniform(-0.3, 0.3, n_cells - 1) * h
+    xc = 0.5 * (xf[:-1] + xf[1:])
+    n = np.empty((S, n_lines * n_cells))
+    rho = np.empty(n_lines * n_cells)
+    v = np.where(rng.uniform(size=n_lines) < 0.5, -1.0, 1.0)
+    for line in range(n_lines):
+        base = rng.uniform(0.2, 1.0, S)
+        amp = rng.uniform(-1.0, 1.0, null.shape[0])
+        d = null.T @ amp
+        scale = 0.15 / max(np.abs(d / base).max(), 1e-30)
+        wave = np.sin(2 * np.pi * (xc + rng.uniform())) + (xc > rng.uniform(0.2, 0.8))
+        cells = base[:, None] + scale * d[:, None] * wave[None, :] * 0.5
+        r = 1.0 + 0.5 * np.sin(2 * np.pi * (xc + rng.uniform()))
+        n[:, line * n_cells:(line + 1) * n_cells] = cells * r[None, :]
+        rho[line * n_cells:(line + 1) * n_cells] = r
+    return n, rho, xc, xf, v
+
+
 def network_for(config_index: int) -> NetworkDesc:
     if config_index == 0:
         return network_h_he(0)

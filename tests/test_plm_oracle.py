@@ -19,6 +19,7 @@ what the paper and the mathematics fix (no GPU):
 import numpy as np
 import pytest
 
+import synthetic as sy
 from oracle import plm
 
 
@@ -67,8 +68,8 @@ def test_linear_profile_reconstructed_exactly():
 
 
 def _run_e1(n, P, limit=True, cfl=0.4):
-    xc, xf = plm.uniform_grid(n)
-    n0 = plm.e1_initial(xc)
+    xc, xf = sy.uniform_grid(n)
+    n0 = sy.e1_initial(xc)
     rho = np.ones(n)
     dt = cfl * (xf[1] - xf[0])
     steps = int(round(1.0 / dt))
@@ -118,7 +119,7 @@ def test_second_order_on_smooth_profile():
     P = plm.projector_svd(plm.E1_COMP)
     errs = []
     for n in (64, 128, 256):
-        xc, xf = plm.uniform_grid(n)
+        xc, xf = sy.uniform_grid(n)
         # variations along the reaction vectors (-2, 1, 0, 0) and (-1, 0, 1,
         # -1): the element abundances are uniform, as the method assumes
         w = np.sin(2 * np.pi * xc)
@@ -135,7 +136,7 @@ def test_second_order_on_smooth_profile():
 
 
 def test_constant_state_unchanged():
-    xc, xf = plm.uniform_grid(32)
+    xc, xf = sy.uniform_grid(32)
     n0 = np.tile(np.array([[0.3], [0.2], [0.1], [0.4]]), (1, 32))
     s, r = plm.ssp_rk2(n0, np.ones(32), 1.0, xc, xf, 0.01, plm.projector_svd(plm.E1_COMP))
     np.testing.assert_allclose(s, n0, rtol=1e-15)
