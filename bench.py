@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, flop/s
+SHORT_DT = 1e-7              # the learned guess's short-step leg (s)
 C_EXP = 27.0                 # FP64 exp / log counted as 27 flops each (range
                              # reduction + degree-11 polynomial + scaling)
 
@@ -82,7 +83,35 @@ def measured_traffic(kernel_source):
     return rec["traffic_bytes"]
 
 
-def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None):
+EPS = float(np.finfo(np.float64).eps)
+FLOOR = 1e-20
+
+
+def parity(desc, cs, idx, gpu_n, gpu_T, gpu_status, orc, iters):
+    """Relative error of GPU results on the sampled cells against the
+    oracle's: abundances over max(|oracle|, 1e-20 n_nuc), T over T; the
+    reservoir species of each conserved row first get the stage-2 rounding
+    drift of the row totals, 4 sqrt(Newton iterations) eps n_nuc (the parity
+    tests' gate).  Returns max and 99.9th percentile, and status agreement."""
+    n_o, T_o, st_o = orc
+    sub_n = cs.n[:, idx]
+    nnuc = np.abs(np.asarray(desc.composition)[:desc.n_elem]).sum(axis=0) @ sub_n
+    slack = np.zeros_like(n_o)
+    walk = 4.0 * EPS * np.sqrt(np.maximum(iters, 1).astype(float)) * nnuc
+    for rs in np.unique(np.asarray(desc.reservoir)):
+        slack[rs] = walk
+    err = np.maximum(np.abs(gpu_n - n_o) - slack, 0.0) / np.maximum(np.abs(n_o), FLOOR * nnuc[None, :])
+    terr = np.abs(gpu_T - T_o) / np.abs(T_o)
+    both = np.concatenate([err.ravel(), terr])
+    return {"max_rel_err": float(both.max()), "p99.9_rel_err": float(np.percentile(both, 99.9)),
+            "status_agree": float(np.mean(gpu_status == st_o)), "cells": int(idx.size)}
+
+
+def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None, gpu=None, one_core=256):
+    """The oracle on a seeded sample of the batch, on every host core and on
+    one; with gpu = {variant: (n [S, sample], T, status, newton iterations)}
+    of the same sampled cells, also the parity of each variant against the
+    oracle's results."""
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(seed)
@@ -90,12 +119,25 @@ def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None):
     on = oracle.OracleNet(desc)
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    on.integrate(cs.n[:, idx], cs.T[idx], cs.rho[idx], dt=None if dt is None else dt[idx],
-                 dt_scalar=dt_scalar, nthreads=cores)
+    n_o, T_o, st_o, stats_o = on.integrate(cs.n[:, idx], cs.T[idx], cs.rho[idx],
+                                           dt=None if dt is None else dt[idx],
+                                           dt_scalar=dt_scalar, nthreads=cores)
     el = time.perf_counter() - t0
-    return {"value": sample / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{sample} cells drawn uniformly (seed {seed}) from the same {cs.n.shape[1]}-cell "
-                      f"batch, FP64 C oracle, OpenMP over {cores} threads, {el:.1f} s"}
+    k1 = min(one_core, sample)
+    t0 = time.perf_counter()
+    on.integrate(cs.n[:, idx[:k1]], cs.T[idx[:k1]], cs.rho[idx[:k1]],
+                 dt=None if dt is None else dt[idx[:k1]], dt_scalar=dt_scalar, nthreads=1)
+    el1 = time.perf_counter() - t0
+    out = {"value": sample / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"{sample} cells drawn uniformly (seed {seed}) from the same {cs.n.shape[1]}-cell "
+                     f"batch, FP64 C oracle, OpenMP over {cores} threads, {el:.1f} s; the first {k1} "
+                     f"of them on 1 thread, {el1:.1f} s",
+           "value_1_core": k1 / el1}
+    if gpu:
+        out["parity"] = {v: parity(desc, cs, idx, g[0][:, idx], g[1][idx], g[2][idx], (n_o, T_o, st_o),
+                                   stats_o[:, 1])
+                         for v, g in gpu.items()}
+    return out
 
 
 MIX_FRACTIONS = (0.5, 0.3, 0.2)
@@ -245,11 +287,17 @@ def run_large(args):
     counters = torch.zeros(8, dtype=torch.int64, device=dev)
     f_it, f_rhs = flops_per_unit(desc)
     stream = torch.cuda.current_stream()
-    results = {}
+    results, gpu_out = {}, {}
+    net_mfma = None
     for variant in args.variants.split(","):
-        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE}.get(variant)
+        prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE, "fp32lu+mfma": kr.KR_FP32LU_REFINE}.get(variant)
         if prec is None:
             continue
+        vnet = net
+        if variant == "fp32lu+mfma":
+            # the FP32 LU blocked, its trailing updates on MFMA tiles
+            net_mfma = net_mfma or kr.Network(desc, kr.build_options(lu_mfma=1))
+            vnet = net_mfma
         opts = kr.default_options(precision=prec, order=_order(args))
         opts.counters = counters.data_ptr()
 
@@ -259,7 +307,7 @@ def run_large(args):
             counters.zero_()
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(stream)
-            kr.chem_integrate(net, n, T, dt=dt, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
+            kr.chem_integrate(vnet, n, T, dt=dt, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
                               stream=stream)
             ev1.record(stream)
             return ev0, ev1
@@ -275,6 +323,7 @@ def run_large(args):
         st = stats.cpu().numpy().astype(np.int64)
         acc = st[:, 0]
         flops = st[:, 1].sum() * f_it + (st[:, 0] + st[:, 2]).sum() * f_rhs
+        gpu_out[variant] = (n.cpu().numpy(), T.cpu().numpy(), status.cpu().numpy(), st[:, 1])
         results[variant] = {
             "ms_per_step": wall / args.steps * 1e3, "value": args.cells * args.steps / wall,
             "kernel_ms": kernel_s * 1e3, "flops_per_launch": float(flops),
@@ -305,7 +354,175 @@ def run_large(args):
                         "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
                         "flops_per_error_estimate": f_rhs}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(desc, cs, 0.0, min(args.cpu_sample, args.cells), dt=cs.dt)
+        out["cpu_baseline"] = cpu_baseline(desc, cs, 0.0, min(args.cpu_sample, args.cells), dt=cs.dt, gpu=gpu_out,
+                                           one_core=4)
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
+def run_h_he(args):
+    """Small case: 4096 cells of the 5-species H/He/charge network (10
+    reversible reactions, 6 unknowns), each cell's step 1e3 times its own
+    fastest timescale, adaptive, rtol 1e-6; plain FP64 and the FP32 LU
+    form, one cell per lane."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    dev = torch.device("cuda", 0)
+    desc = sy.network_h_he(0)
+    cs = sy.cells_h_he(desc, args.cells, 0)
+    net = kr.Network(desc, kr.build_options(layout={"auto": kr.KR_LAYOUT_AUTO, "lane": kr.KR_LAYOUT_LANE,
+                                                    "wave": kr.KR_LAYOUT_WAVE}[args.layout]))
+    n0 = torch.tensor(cs.n, device=dev)
+    T0 = torch.tensor(cs.T, device=dev)
+    dt = 1e3 * kr.fastest_timescale(net, n0, T0)
+    n, T = torch.empty_like(n0), torch.empty_like(T0)
+    status = torch.empty(args.cells, dtype=torch.int32, device=dev)
+    stats = torch.empty((args.cells, 4), dtype=torch.int32, device=dev)
+    f_it, f_rhs = flops_per_unit(desc)
+    stream = torch.cuda.current_stream()
+    results, gpu_out = {}, {}
+    for variant in ("fp64", "fp32lu"):
+        opts = kr.default_options(precision=kr.KR_FP64 if variant == "fp64" else kr.KR_FP32LU_REFINE)
+
+        def step():
+            n.copy_(n0)
+            T.copy_(T0)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            kr.chem_integrate(net, n, T, dt=dt, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
+                              stream=stream)
+            ev1.record(stream)
+            return ev0, ev1
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_s = np.mean([a.elapsed_time(b) for a, b in evs]) * 1e-3
+        st = stats.cpu().numpy().astype(np.int64)
+        flops = st[:, 1].sum() * f_it + (st[:, 0] + st[:, 2]).sum() * f_rhs
+        resid = torch.empty(args.cells, dtype=torch.float64, device=dev)
+        kr.element_residual(net, n0, n, resid=resid)
+        gpu_out[variant] = (n.cpu().numpy(), T.cpu().numpy(), status.cpu().numpy(), st[:, 1])
+        results[variant] = {"ms_per_step": wall / args.steps * 1e3, "value": args.cells * args.steps / wall,
+                            "kernel_ms": kernel_s * 1e3, "achieved_tflops": flops / kernel_s / 1e12,
+                            "newton_iters_per_cell": float(st[:, 1].mean()),
+                            "max_newton_iters": int(st[:, 1].max()),
+                            "substeps_per_cell": float(st[:, 0].mean()),
+                            "status_counts": np.bincount(status.cpu().numpy(), minlength=3).tolist(),
+                            "max_element_residual": float(resid.max().item())}
+        print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
+    head = results["fp64"]
+    out = {"metric": "cell-steps/s implicit chem update, 5-species H/He network, 1 GPU",
+           "value": head["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"h_he_5sp: {args.cells} cells, 5 species / 10 reversible reactions / "
+                                  "H, He, charge rows + energy (6x6 LU), dt = 1e3 tau_fast per cell, "
+                                  "adaptive, rtol 1e-6, one cell per " + ("wavefront" if net.wide else "lane")},
+           "variants": results,
+           "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
+                        "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64, "traffic": None,
+                        "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
+                        "flops_per_error_estimate": f_rhs}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc, cs, 0.0, args.cells, dt=dt.cpu().numpy(), gpu=gpu_out,
+                                           one_core=args.cells)
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
+def run_advect(args):
+    """Species advection (Sec. 2.1): one SSP-RK2 step (two kr_advect_plm
+    stages) of the stoichiometry-compatible PLM over lines of cells with
+    periodic ends, 9-species combustion network, non-uniform grid, density
+    and velocity per line as synthetic.advection_lines draws them.  HBM
+    bound: per cell and step the algorithmic traffic is (5 S + 4) 8 bytes
+    (stage 1 reads n, rho, the face flux and writes n; stage 2 also reads the
+    step's initial state)."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    dev = torch.device("cuda", 0)
+    desc = sy.network_h_o_n(1)
+    S = desc.n_species
+    n_cells = 256
+    n_lines = max(1, args.cells // n_cells)
+    t0 = time.perf_counter()
+    n_h, rho_h, xc_h, xf_h, v = sy.advection_lines(desc, n_lines, n_cells)
+    F_h = np.empty_like(rho_h)
+    for l in range(n_lines):
+        r = rho_h[l * n_cells:(l + 1) * n_cells]
+        F_h[l * n_cells:(l + 1) * n_cells] = (np.roll(r, 1) if v[l] > 0 else r) * v[l]
+    setup_s = time.perf_counter() - t0
+    net = kr.Network(desc)
+    u0 = torch.tensor(n_h, device=dev)
+    u = u0.clone()
+    u1 = torch.empty_like(u0)
+    u2 = torch.empty_like(u0)
+    rho = torch.tensor(rho_h, device=dev)
+    F = torch.tensor(F_h, device=dev)
+    xc, xf = torch.tensor(xc_h, device=dev), torch.tensor(xf_h, device=dev)
+    dt = 0.4 * float(np.min(np.diff(xf_h)))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        # the density is held fixed across the step: a stage's fluxes move
+        # mass as the density's own update would, whose effect on the species
+        # per mass the test of the kernel covers; the work per cell is the same
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        kr.advect_plm(net, u, u1, rho, F, xc, xf, dt, n_lines=n_lines, stream=stream)
+        kr.advect_plm(net, u1, u2, rho, F, xc, xf, dt, n_lines=n_lines, base=u, alpha=0.5, beta=0.5,
+                      stream=stream)
+        ev1.record(stream)
+        return ev0, ev1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+    cells = n_lines * n_cells
+    bytes_step = cells * (5 * S + 4) * 8.0
+    out = {"metric": "cell-steps/s species advection (projected PLM, SSP-RK2), 1 GPU",
+           "value": cells * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"advect: {n_lines} periodic lines x {n_cells} cells, h_o_n 9 species, "
+                                  "non-uniform grid, projected PLM, SSP-RK2 (2 stages)"},
+           "kernel_ms_per_step": kernel_s * 1e3, "setup_s": setup_s,
+           "roofline": {"bound": "hbm", "achieved": bytes_step / kernel_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": bytes_step / kernel_s / 8e12, "traffic": None, "kernel": "kr_advect",
+                        "bytes_per_cell_step": (5 * S + 4) * 8}}
+    if not args.no_cpu_baseline:
+        from oracle import plm
+        P = plm.projector_svd(desc.composition)
+        k = min(n_lines, 64)
+        got = u2.cpu().numpy()
+        cores = len(os.sched_getaffinity(0))
+        t1 = time.perf_counter()
+        worst = 0.0
+        for l in range(k):
+            sl = slice(l * n_cells, (l + 1) * n_cells)
+            n1, _ = plm.stage(n_h[:, sl], rho_h[sl], F_h[sl], xc_h, xf_h, dt, P)
+            n2, _ = plm.stage(n1, rho_h[sl], F_h[sl], xc_h, xf_h, dt, P)
+            ref = 0.5 * (n_h[:, sl] + n2)
+            worst = max(worst, float(np.abs(got[:, sl] - ref).max() / np.abs(n_h[:, sl]).max()))
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": k * n_cells / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} lines of {n_cells} cells, numpy FP64 reference (one thread), "
+                                         f"{el:.2f} s",
+                               "parity": {"max_rel_err": worst, "cells": k * n_cells}}
     print(json.dumps(out), flush=True)
     net.close()
 
@@ -353,7 +570,8 @@ def calibrate_mixed(args):
 # for the long, uneven cells of the combustion and 48-species batches; input
 # order (coalesced state accesses, no extra rate evaluation) for the mixed
 # batch, whose cells mostly take one substep
-_ORDER_DEFAULT = {"h_o_n": "work", "large48": "work", "mixed": "input", "calibrate": "input"}
+_ORDER_DEFAULT = {"h_o_n": "work", "large48": "work", "mixed": "input", "calibrate": "input",
+                  "h_he": "input", "advect": "input"}
 
 
 def _order(args):
@@ -366,14 +584,17 @@ def _order(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="h_o_n", choices=["h_o_n", "mixed", "large48", "calibrate"])
+    ap.add_argument("--workload", default="h_o_n",
+                    choices=["h_o_n", "h_he", "mixed", "large48", "calibrate", "advect"])
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--layout", default="auto", choices=["auto", "lane", "wave"],
+                    help="h_he workload: the integrator layout")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=1 << 20)
     ap.add_argument("--variants", default="fp64,fp32lu,fp32lu+mlp")
-    ap.add_argument("--train-pairs", type=int, default=1 << 22)
-    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-pairs", type=int, default=1 << 24)
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--order", default="default", choices=["default", "work", "input"],
@@ -387,6 +608,14 @@ def main():
 
     if args.workload == "calibrate":
         calibrate_mixed(args)
+        return
+    if args.workload == "advect":
+        run_advect(args)
+        return
+    if args.workload == "h_he":
+        if args.cells == 1 << 20:
+            args.cells = 4096
+        run_h_he(args)
         return
     if args.workload == "large48":
         if args.cells == 1 << 20:
@@ -438,19 +667,55 @@ def main():
         # iterations from the plain start and from the learned start
         evals = {}
         for use in (False, True):
-            r = learned.newton_counts(net, model if use else None, desc, 1 << 20, salt=99)
+            r = learned.newton_counts(net, model if use else None, desc, 1 << 20, salt=99,
+                                      precision=kr.KR_FP32LU_REFINE)
             st_ = r["cell_stats"].cpu().numpy()
+            hl = np.floor(np.log10(r["h"].cpu().numpy())).astype(int)
             evals["guess" if use else "plain"] = {
                 "newton_per_cell": float(st_[:, 1].mean()),
+                "newton_per_cell_by_h_decade": {f"1e{d}": float(st_[hl == d, 1].mean())
+                                                for d in range(-10, -4) if np.any(hl == d)},
+                "newton_failures": int(st_[:, 3].sum()),
                 "status_counts": np.bincount(r["status"].cpu().numpy(), minlength=3).tolist(),
                 "guess_starts_fallbacks": r["counters"].cpu().numpy()[:2].tolist()}
+        # a short adaptive step (few substeps per cell), where the learned
+        # first substep is a large share of the work
+        short = {}
+        for use in (False, True):
+            ns, Ts = n0.clone(), T0.clone()
+            st_s = torch.empty((args.cells, 4), dtype=torch.int32, device=dev)
+            cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+            guess_s = torch.empty((desc.n_unknowns, args.cells), dtype=torch.float64, device=dev)
+            o_ = (kr.guess_options(guess_s, cnt, precision=kr.KR_FP32LU_REFINE) if use
+                  else kr.default_options(precision=kr.KR_FP32LU_REFINE))
+            o_.counters = cnt.data_ptr()
+            ts = []
+            for rep_ in range(3):
+                ns.copy_(n0)
+                Ts.copy_(T0)
+                cnt.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                if use:
+                    model.predict(ns, Ts, dt_scalar=SHORT_DT, guess=guess_s, stream=stream)
+                kr.chem_integrate(net, ns, Ts, dt_scalar=SHORT_DT, rtol=1e-6, opts=o_, cell_stats=st_s,
+                                  stream=stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t1)
+            sts = st_s.cpu().numpy().astype(np.int64)
+            short["guess" if use else "plain"] = {
+                "ms": float(np.min(ts) * 1e3), "cell_steps_per_s": args.cells / float(np.min(ts)),
+                "newton_per_cell": float(sts[:, 1].mean()), "substeps_per_cell": float(sts[:, 0].mean()),
+                "guess_starts_fallbacks": cnt.cpu().numpy()[:2].tolist()}
         learned_info = {"training_pairs": args.train_pairs, "training_steps": args.train_steps,
                         "final_batch_loss": hist[-1][1], "setup_s": train_s,
-                        "single_substep_eval_2^20_cells": evals}
+                        "single_substep_eval_2^20_cells_fp32lu": evals,
+                        f"short_step_dt_{SHORT_DT:g}_fp32lu": short}
         print(f"# learned guess: {learned_info}", file=sys.stderr, flush=True)
 
     guess = torch.empty((desc.n_unknowns, args.cells), dtype=torch.float64, device=dev)
     counters = torch.zeros(8, dtype=torch.int64, device=dev)
+    gpu_out = {}
     xs = torch.empty((args.cells, desc.n_species + 2), dtype=torch.float32, device=dev)
     for variant in args.variants.split(","):
         prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE,
@@ -488,6 +753,11 @@ def main():
         stat_codes = np.bincount(status.cpu().numpy(), minlength=3)
         iters, acc, rej = st[:, 1].sum(), st[:, 0].sum(), st[:, 2].sum()
         flops = iters * f_it + (acc + rej) * f_rhs
+        gpu_out[variant] = (n.cpu().numpy(), T.cpu().numpy(), status.cpu().numpy(), st[:, 1])
+        resid = torch.empty(args.cells, dtype=torch.float64, device=dev)
+        kr.element_residual(net, n0, n, resid=resid)
+        ok = status != 2
+        max_resid = float(resid[ok].max().item()) if bool(ok.any()) else 0.0
         results[variant] = {
             "ms_per_step": wall / args.steps * 1e3,
             "value": args.cells * args.steps / wall,
@@ -497,6 +767,7 @@ def main():
             "newton_iters_per_cell": float(iters) / args.cells,
             "substeps_per_cell": float(acc) / args.cells,
             "status_counts": stat_codes.tolist(),
+            "max_element_residual": max_resid,
             "counters_last_step": dict(zip(("guess_starts", "guess_fallbacks", "row_exchanges",
                                             "fp32_solves", "fp64_fallbacks"),
                                            counters.cpu().numpy()[:5].tolist())),
@@ -530,7 +801,7 @@ def main():
                      "flops_per_error_estimate": f_rhs, "exp_log_flops": C_EXP},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(desc, cs, dt_scalar, min(args.cpu_sample, args.cells))
+        out["cpu_baseline"] = cpu_baseline(desc, cs, dt_scalar, min(args.cpu_sample, args.cells), gpu=gpu_out)
     print(json.dumps(out), flush=True)
 
 

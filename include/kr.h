@@ -135,7 +135,14 @@ void kr_network_destroy(kr_network *net);
  *                 at 23); KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
  *                 wavefront layout holds the Newton matrix one row per lane
  *                 and needs n_species <= 62 and 5 * 2 * n_reactions
- *                 rounded up to 320 <= 4095 (n_reactions <= 384). */
+ *                 rounded up to 320 <= 4095 (n_reactions <= 384).
+ *   lu_mfma       1: the FP32 LU of the KR_FP32LU_REFINE form runs blocked,
+ *                 its trailing updates on FP32 MFMA tiles (wavefront layout
+ *                 with n_species >= 31, where the rate table's LDS holds the
+ *                 panel blocks; elsewhere ignored); 0 (default): the
+ *                 unblocked LU on the vector ALUs.  Same solution up to
+ *                 rounding; measured slower or faster per network (see the
+ *                 autotuner). */
 #define KR_LAYOUT_AUTO 0
 #define KR_LAYOUT_LANE 1
 #define KR_LAYOUT_WAVE 2
@@ -144,6 +151,7 @@ typedef struct {
   int32_t waves_per_eu;
   float pivot_tau;
   int32_t layout;
+  int32_t lu_mfma;
 } kr_build_opts;
 
 void kr_default_build_options(kr_build_opts *opt);
@@ -352,6 +360,39 @@ int kr_element_residual(const kr_network *net, int64_t n_cells,
  * Errors: KR_EINVAL, KR_EDEVICE. */
 int kr_postprocess(const kr_network *net, int64_t n_cells, const double *before,
                    double *after, int64_t ld, int32_t *flags, kr_stream_t stream);
+
+/* One forward-Euler stage of the stoichiometry-compatible PLM advection of
+ * the species (Sec. 2.1, eqs. method-flux-sp, method-plm-general,
+ * method-sto-plm-def, method-sto-plm-proj, method-sto-plm-recon) along lines
+ * of cells with periodic ends: every face takes its upwind cell's species
+ * per mass x = n / rho (upwind by the sign of the face's mass flux),
+ * extrapolated to the face with the modified van Leer slope for non-uniform
+ * grids (the limiter of Mignone 2014 that the paper names), the correction
+ * projected onto the null space of the network's element-species matrix
+ * (P = V V^T), so that the species fluxes F_s = x_face,s F_rho carry element
+ * fluxes proportional to the mass flux; then
+ *   n_out = alpha base + beta (n_in - dt / dx (F(i+1/2) - F(i-1/2)))
+ * (alpha is ignored when base is NULL; two such stages with (alpha, beta) =
+ * (0, 1) and (1/2, 1/2), base = the step's initial state, make the SSP-RK2
+ * step).  The density's own update (by the same mass fluxes) is the
+ * caller's.
+ *   n_lines, n_cells   lines and cells per line (>= 3); cell i of line l is
+ *                      column l * line_stride + i of the [S][ld] arrays
+ *   n_in, n_out, base  device [n_species][ld]; n_out must not alias n_in
+ *   rho                device [cells]: density of the stage's input state
+ *   flux               device [cells]: mass flux through each cell's left
+ *                      face (face i-1/2 of cell i; periodic)
+ *   xc, xf             device [n_cells] cell centres and [n_cells + 1] faces
+ *                      of every line (xf[n_cells] - xf[0] the period)
+ *   mode               1 projected PLM; 0 PLM without the projection (the
+ *                      paper's non-conserving comparison); 2 donor cell
+ * Errors: KR_EINVAL, KR_EDEVICE.  Asynchronous on the stream. */
+int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells,
+                  int64_t line_stride, const double *n_in, double *n_out,
+                  int64_t ld, const double *rho, const double *flux,
+                  const double *xc, const double *xf, double dt,
+                  const double *base, double alpha, double beta, int32_t mode,
+                  kr_stream_t stream);
 
 /* Fastest self-coupling timescale of each cell at its (pre-processed) input
  * state, out[c] = 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s

@@ -35,6 +35,7 @@ KR_NOALLOC_MAX_ORDER_CELLS = (KR_NOALLOC_SCRATCH_BYTES - 4096) // 5
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns", "kr_network_layout",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
             "kr_default_options", "kr_chem_integrate", "kr_element_residual", "kr_postprocess",
+            "kr_advect_plm", "kr_chem_integrate_noalloc",
             "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
             "kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
             "kr_guess_set_normalization", "kr_guess_features", "kr_guess_targets",
@@ -82,7 +83,8 @@ class Options(C.Structure):
 
 class BuildOpts(C.Structure):
     """kr_build_opts: compile-time tuning of the generated kernels."""
-    _fields_ = [("waves_per_eu", C.c_int32), ("pivot_tau", C.c_float), ("layout", C.c_int32)]
+    _fields_ = [("waves_per_eu", C.c_int32), ("pivot_tau", C.c_float), ("layout", C.c_int32),
+                ("lu_mfma", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -128,6 +130,9 @@ def lib():
                                           C.c_int64, C.c_void_p, C.POINTER(C.c_double),
                                           C.c_void_p]
         L.kr_chem_integrate_noalloc.argtypes = L.kr_chem_integrate.argtypes
+        L.kr_advect_plm.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                    C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p]
         L.kr_postprocess.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_void_p, C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
@@ -362,6 +367,32 @@ def postprocess(net: Network, before, after, flags=None, stream=None) -> None:
     _check(lib().kr_postprocess(net.handle, n, _dev_ptr(before, torch.float64, "before"),
                                 _dev_ptr(after, torch.float64, "after"), int(after.stride(0)),
                                 _dev_ptr(flags, torch.int32, "flags"), _stream_ptr(stream)))
+
+
+ADVECT_PLAIN, ADVECT_PROJECTED, ADVECT_DONOR = 0, 1, 2
+
+
+def advect_plm(net: Network, n_in, n_out, rho, flux, xc, xf, dt: float, n_lines: int = 1,
+               line_stride: int | None = None, base=None, alpha: float = 0.0, beta: float = 1.0,
+               mode: int = ADVECT_PROJECTED, stream=None) -> None:
+    """kr_advect_plm: one forward-Euler stage of the stoichiometry-compatible
+    PLM advection of the species along n_lines periodic lines.  n_in, n_out,
+    base: float64 [S, ld] (unit stride along cells); rho, flux: float64
+    [cells]; xc [n_cells], xf [n_cells + 1]."""
+    import torch
+    if n_in.dim() != 2 or n_in.stride(1) != 1 or n_out.stride() != n_in.stride():
+        raise ValueError("n_in/n_out must be [n_species, ld] with the same layout")
+    if base is not None and base.stride() != n_in.stride():
+        raise ValueError("base must share the layout of n_in")
+    n_cells = int(xc.numel())
+    stride = n_cells if line_stride is None else int(line_stride)
+    _check(lib().kr_advect_plm(net.handle, int(n_lines), n_cells, stride,
+                               _dev_ptr(n_in, torch.float64, "n_in"), _dev_ptr(n_out, torch.float64, "n_out"),
+                               int(n_in.stride(0)), _dev_ptr(rho, torch.float64, "rho"),
+                               _dev_ptr(flux, torch.float64, "flux"), _dev_ptr(xc, torch.float64, "xc"),
+                               _dev_ptr(xf, torch.float64, "xf"), float(dt),
+                               _dev_ptr(base, torch.float64, "base"), float(alpha), float(beta), int(mode),
+                               _stream_ptr(stream)))
 
 
 def work_order(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,

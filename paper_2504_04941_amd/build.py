@@ -2,7 +2,8 @@
 
 The integrator's device templates (csrc/kr_device.h: one cell per lane;
 csrc/kr_wide.h: one cell per wavefront), the rate-coefficient math
-(csrc/kr_math.h), the cell-ordering kernels (csrc/kr_order.h) and the
+(csrc/kr_math.h), the cell-ordering kernels (csrc/kr_order.h), the
+species advection (csrc/kr_advect.h) and the
 launch-parameter struct (csrc/kr_params.h) are embedded into the library as string literals:
 at network creation they are compiled together with the generated network
 code by hipRTC."""
@@ -35,6 +36,7 @@ def build(verbose: bool = False) -> str:
     _embed("kr_wide.h", "kr_wide_src.inc")
     _embed("kr_math.h", "kr_math_src.inc")
     _embed("kr_order.h", "kr_order_src.inc")
+    _embed("kr_advect.h", "kr_advect_src.inc")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-result",

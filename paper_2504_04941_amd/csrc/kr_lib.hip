@@ -47,6 +47,9 @@ static const char *kMathSource =
 static const char *kOrderSource =
 #include "kr_order_src.inc"
     ;
+static const char *kAdvectSource =
+#include "kr_advect_src.inc"
+    ;
 
 static const double kBoltzmann = 1.380649e-16; /* erg / K */
 static const int KR_ORDER_NBUCKETS = 256;       /* KR_ORDER_BUCKETS of kr_order.h */
@@ -122,9 +125,9 @@ struct kr_network {
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
-  hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr;
+  hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr, f_adv = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
-  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
+  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
   bool wide = false;            /* one wavefront per cell */
   OrderBufs ord;
   unsigned long long *d_counter = nullptr;
@@ -414,6 +417,42 @@ static std::string network_tables(const kr_network *n) {
   o += "};\n";
   o += "__device__ static constexpr double kr_T_min = " + hexd(n->T_min) + ";\n";
   o += "__device__ static constexpr double kr_T_max = " + hexd(n->T_max) + ";\n";
+  /* projector onto the stoichiometric space, the null space of the
+   * element-species matrix (Sec. 2.1: P = V V^T), as I - Q^T Q with Q an
+   * orthonormal basis of the conserved rows' span (modified Gram-Schmidt,
+   * twice, in extended precision; dependent rows are skipped) */
+  std::vector<std::vector<long double>> Q;
+  for (int v = 0; v < V; ++v) {
+    std::vector<long double> w(S);
+    long double nrm0 = 0.0L;
+    for (int k = 0; k < S; ++k) {
+      w[k] = (long double)n->comp[(size_t)v * S + k];
+      nrm0 += w[k] * w[k];
+    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto &q : Q) {
+        long double d = 0.0L;
+        for (int k = 0; k < S; ++k) d += q[k] * w[k];
+        for (int k = 0; k < S; ++k) w[k] -= d * q[k];
+      }
+    long double nrm = 0.0L;
+    for (int k = 0; k < S; ++k) nrm += w[k] * w[k];
+    if (!(nrm > 1e-24L * nrm0) || nrm0 == 0.0L) continue;
+    nrm = sqrtl(nrm);
+    for (int k = 0; k < S; ++k) w[k] /= nrm;
+    Q.push_back(w);
+  }
+  o += "__device__ static constexpr double kr_proj[" + std::to_string(S) + "][" + std::to_string(S) + "] = {";
+  for (int i = 0; i < S; ++i) {
+    o += "{";
+    for (int j = 0; j < S; ++j) {
+      long double pij = i == j ? 1.0L : 0.0L;
+      for (const auto &q : Q) pij -= q[i] * q[j];
+      o += hexd((double)pij) + (j + 1 < S ? "," : "");
+    }
+    o += i + 1 < S ? "}," : "}";
+  }
+  o += "};\n";
   return o;
 }
 
@@ -547,6 +586,7 @@ extern "C" void kr_default_build_options(kr_build_opts *o) {
     o->waves_per_eu = default_waves_per_eu();
     o->pivot_tau = 0.1f;
     o->layout = KR_LAYOUT_AUTO;
+    o->lu_mfma = 0;
   } catch (...) {
   }
 }
@@ -555,6 +595,7 @@ static int check_build_options(const kr_build_opts *o) {
   if (o->waves_per_eu < 0 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [0, 8]");
   if (!(o->pivot_tau > 0.0f && o->pivot_tau <= 1.0f)) return fail(KR_EINVAL, "pivot_tau out of (0, 1]");
   if (o->layout < KR_LAYOUT_AUTO || o->layout > KR_LAYOUT_WAVE) return fail(KR_EINVAL, "layout out of [0, 2]");
+  if (o->lu_mfma != 0 && o->lu_mfma != 1) return fail(KR_EINVAL, "lu_mfma must be 0 or 1");
   return KR_OK;
 }
 
@@ -563,6 +604,18 @@ static std::string build_prefix(int waves_per_eu, const kr_build_opts &o) {
   snprintf(b, sizeof b, "#define KR_WAVES_PER_EU %d\n#define KR_PIVOT_TAU %a\n", waves_per_eu,
            (double)o.pivot_tau);
   return b;
+}
+
+/* The blocked FP32 LU with MFMA trailing updates (kr_wide.h) applies to a
+ * wavefront-layout network of N = S + 1 >= 32 unknowns whose panel blocks
+ * (panels of KR_PF, then 16 columns) fit into its rate table's LDS. */
+static bool lu_mfma_fits(int S, int n_dirs) {
+  const int N = S + 1;
+  if (N < 32) return false;
+  const int PF = N - 16 * ((N - 1) / 16), KP = (PF + 3) / 4 * 4, W = N - PF;
+  const long ndp = 64L * std::max(1, (n_dirs + 63) / 64);
+  const long need = std::max(4L * (64 * KP + KP * W + 64 * W), 4L * (64 * 16 + 80 * (W - 16)));
+  return need <= 5 * ndp * 8;
 }
 
 static bool use_wide(const kr_network *n, const kr_build_opts &o) {
@@ -591,13 +644,22 @@ static int auto_waves_per_eu(const kr_network *n, const kr_build_opts &o) {
   return std::max(1, std::min(2, per_simd));
 }
 
+/* "#define KR_LU_MFMA 1" when the build asks for the blocked FP32 LU and it
+ * applies to this (wavefront-layout) network, else empty. */
+static std::string lu_mfma_define(const kr_network *n, const kr_build_opts &o) {
+  if (!o.lu_mfma || !lu_mfma_fits(n->S, (int)wide_directions(n).size())) return "";
+  return "#define KR_LU_MFMA 1 /* FP32 LU with MFMA trailing updates */\n";
+}
+
 static std::string full_source(const kr_network *n, const kr_build_opts &o) {
   const int w = auto_waves_per_eu(n, o);
   if (use_wide(n, o))
     return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(w, o) +
-           kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_wide(n) + "\n" + kWideSource;
+           kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + lu_mfma_define(n, o) +
+           generate_wide(n) + "\n" + kWideSource + "\n" + kAdvectSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource;
+         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource +
+         "\n" + kAdvectSource;
 }
 
 static void release(kr_network *n) {
@@ -659,6 +721,7 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
     CREATE_TRY(hipModuleGetFunction(&n->f_scan, n->module, "kr_order_scan"));
     CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
     CREATE_TRY(hipModuleGetFunction(&n->f_post, n->module, "kr_post"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_adv, n->module, "kr_advect"));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
     CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
@@ -1124,6 +1187,49 @@ extern "C" int kr_postprocess(const kr_network *net, int64_t n_cells, const doub
   } KR_CATCH
 }
 
+/* ------------------------------------------------------------------------ */
+/* stoichiometry-compatible PLM advection (generated module's kr_advect)     */
+/* ------------------------------------------------------------------------ */
+
+struct KrAdvParamsHost {          /* mirrors the device struct KrAdvParams (kr_advect.h) */
+  long long n_lines, n_cells, line_stride;
+  const double *n_in;
+  double *n_out;
+  long long ld;
+  const double *rho, *flux, *xc, *xf, *base;
+  double dt, alpha, beta;
+  int mode;
+};
+
+extern "C" int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells, int64_t line_stride,
+                             const double *n_in, double *n_out, int64_t ld, const double *rho,
+                             const double *flux, const double *xc, const double *xf, double dt,
+                             const double *base, double alpha, double beta, int32_t mode,
+                             kr_stream_t stream) {
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (n_lines < 0 || n_cells < 0 || (n_lines > 1 && line_stride < n_cells) || (n_lines == 1 && line_stride < 0))
+      return fail(KR_EINVAL, "bad line sizes");
+    if (n_lines == 0 || n_cells == 0) return KR_OK;
+    if (n_cells < 3) return fail(KR_EINVAL, "a periodic line needs at least 3 cells");
+    if ((n_lines - 1) * line_stride + n_cells > ld) return fail(KR_EINVAL, "ld too small for the lines");
+    if (!n_in || !n_out || !rho || !flux || !xc || !xf) return fail(KR_EINVAL, "null array");
+    if (n_in == n_out) return fail(KR_EINVAL, "n_out must not alias n_in");
+    if (mode < 0 || mode > 2) return fail(KR_EINVAL, "mode out of [0, 2]");
+    if (!std::isfinite(dt) || !std::isfinite(alpha) || !std::isfinite(beta)) return fail(KR_EINVAL, "bad scalars");
+    HIP_TRY(hipSetDevice(net->device));
+    KrAdvParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho, flux, xc, xf,
+                      base, dt, base ? alpha : 0.0, beta, mode};
+    const int chunk = net->S <= 16 ? 256 : 64;
+    const long long blocks = std::min<long long>(n_lines * ((n_cells + chunk - 1) / chunk),
+                                                 (long long)net->cu_count * 16);
+    void *args[] = {&p};
+    HIP_TRY(hipModuleLaunchKernel(net->f_adv, (unsigned)blocks, 1, 1, chunk, 1, 1, 0, (hipStream_t)stream, args,
+                                  nullptr));
+    return KR_OK;
+  } KR_CATCH
+}
+
 extern "C" int kr_work_order(const kr_network *net, int64_t n_cells, const double *states, int64_t ld,
                              const double *T, const double *rho, const double *dt, double dt_scalar,
                              const kr_options *opt, uint32_t *order, kr_stream_t stream) {
@@ -1187,7 +1293,7 @@ struct KrMultiHost {          /* mirrors the device struct KrMulti */
 
 struct kr_multi {
   std::vector<const kr_network *> nets;
-  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO};
+  kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
   std::string source;
   hipModule_t module = nullptr;
   /* one persistent kernel per group of networks compiled for the same
@@ -1218,7 +1324,7 @@ static std::vector<std::pair<int, std::vector<int>>> multi_groups(const std::vec
   std::vector<int> members[2];
   for (size_t k = 0; k < nets.size(); ++k) {
     const int g = nets[k]->wide ? 1 : 0;
-    const kr_build_opts ok{o.waves_per_eu, o.pivot_tau, g ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE};
+    const kr_build_opts ok{o.waves_per_eu, o.pivot_tau, g ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE, o.lu_mfma};
     w[g] = std::min(w[g], auto_waves_per_eu(nets[k], ok));
     members[g].push_back((int)k);
   }
@@ -1245,9 +1351,11 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
                   build_prefix(multi_waves_per_eu(nets, o), o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
     if (nets[k]->wide)
-      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_wide(nets[k]) + "\n" + kWideSource +
+      s += "namespace kr_m" + std::to_string(k) + " {\n" + lu_mfma_define(nets[k], o) + generate_wide(nets[k]) +
+           "\n" + kWideSource +
            "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n#undef KR_LDJ\n#undef KR_NDR\n"
-           "#undef KR_NC\n#undef KR_NF\n#undef KR_NDP\n#undef KR_NOTPIV\n";
+           "#undef KR_NC\n#undef KR_NF\n#undef KR_NDP\n#undef KR_NOTPIV\n#undef KR_LU_MFMA\n#undef KR_USE_LU_MFMA\n"
+           "#undef KR_PF\n";
     else
       s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" + kDeviceSource +
            "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";

@@ -354,6 +354,153 @@ __device__ __forceinline__ bool kr_wlu_fwd(F (&a)[KR_N], int &pc, F &dinv, F &b)
   return kr_wlu_impl<F, true>(a, pc, dinv, b);
 }
 
+/* ------------------------------------------------------------------------ */
+/* FP32 LU with the trailing updates on MFMA (networks of 31+ species)      */
+/* ------------------------------------------------------------------------ */
+
+/* Blocked right-looking variant of kr_wlu<float> (same pivot choice, same
+ * factor layout, different rounding): columns in panels, the first of
+ * KR_PF columns, then panels of 16, so that every trailing block is a
+ * multiple of 16 wide.  Inside a panel a column is eliminated as in
+ * kr_wlu, but only the panel's own columns are updated.  After the panel
+ * [j0, j1), with M the rows' multipliers of the panel columns (zero where a
+ * row was already a pivot row) and T the rows' trailing parts (columns j1
+ * and on):
+ *   U = (unit lower L of the panel's pivot rows)^-1 T[pivot rows]
+ *       (lanes own columns of U; a forward substitution over the panel),
+ *   T -= M U  (64 x Kp times Kp x W on v_mfma_f32_16x16x4f32 tiles),
+ * which leaves every row's trailing part as the unblocked elimination would.
+ * M, U and T pass through LDS (the rate table P, which is dead during the
+ * linear solve).  Returns false (wave-uniform) for a singular matrix. */
+#ifdef KR_LU_MFMA
+/* set by the network compiler only where it applies: N >= 32 and the panel
+ * blocks fit into the rate table's LDS */
+#define KR_USE_LU_MFMA 1
+#define KR_PF (KR_N - 16 * ((KR_N - 1) / 16))
+static_assert(KR_N >= 32, "blocked LU needs at least two panels");
+static_assert(4 * (64 * ((KR_PF + 3) / 4 * 4) + ((KR_PF + 3) / 4 * 4) * (KR_N - KR_PF) + 64 * (KR_N - KR_PF)) <=
+                  5 * KR_NDP * 8 &&
+              4 * (64 * 16 + 80 * (KR_N - KR_PF - 16)) <= 5 * KR_NDP * 8,
+              "panel blocks exceed the rate table's LDS");
+#endif
+
+#ifdef KR_USE_LU_MFMA
+typedef float kr_v4f __attribute__((ext_vector_type(4)));
+
+/* Trailing update after the panel [J0, J1) (see kr_wlu_blocked); pv[jj]:
+ * pivot lane of column J0 + jj. */
+template <int J0, int J1>
+__device__ __forceinline__ void kr_wlu_trailing(float (&a)[KR_N], int pc, const int (&pv)[J1 - J0], float *lds) {
+  constexpr int F = J1 - J0, KP = (F + 3) / 4 * 4, W = KR_N - J1;
+  static_assert(W % 16 == 0 && W > 0, "trailing blocks are multiples of 16 wide");
+  const int lane = threadIdx.x;
+  float *Ml = lds, *Ul = lds + 64 * KP, *Tl = Ul + KP * W;
+  /* multipliers of the panel columns (zero for pivot rows and padding) and
+   * the trailing part, one row per lane */
+#pragma unroll
+  for (int jj = 0; jj < KP; ++jj) Ml[lane * KP + jj] = (jj < F && pc > J0 + jj) ? a[J0 + jj] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < W; ++k) Tl[lane * W + k] = a[J1 + k];
+  __syncthreads();
+  /* U: lane t (columns past W repeat the last one) owns column t */
+  {
+    const int t = lane < W ? lane : W - 1;
+    float u[KP];
+#pragma unroll
+    for (int jj = 0; jj < F; ++jj) {
+      const int p = pv[jj];
+      float x = Tl[p * W + t];
+#pragma unroll
+      for (int q = 0; q < jj; ++q) x = fmaf(-Ml[p * KP + q], u[q], x);
+      u[jj] = x;
+    }
+#pragma unroll
+    for (int jj = F; jj < KP; ++jj) u[jj] = 0.0f;
+#pragma unroll
+    for (int jj = 0; jj < KP; ++jj) Ul[jj * W + t] = u[jj];
+  }
+  __syncthreads();
+  /* C = M U on MFMA tiles, into T's place: lane l supplies A[l%16][l/16] and
+   * B[l/16][l%16] of each 16x4 / 4x16 step and receives C rows
+   * 4 (l/16) .. 4 (l/16) + 3 of column l%16 */
+  const int r16 = lane & 15, q4 = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int nt = 0; nt < W / 16; ++nt) {
+      kr_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kk = 0; kk < KP / 4; ++kk) {
+        const float av = Ml[(mt * 16 + r16) * KP + kk * 4 + q4];
+        const float bv = Ul[(kk * 4 + q4) * W + nt * 16 + r16];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tl[(mt * 16 + 4 * q4 + r) * W + nt * 16 + r16] = acc[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < W; ++k) a[J1 + k] -= Tl[lane * W + k];
+  __syncthreads();
+}
+
+/* Columns [J0, J1) eliminated as in kr_wlu but updating only the panel's own
+ * columns, then the trailing update, then the next panel (compile-time
+ * recursion, so that every loop bound is a constant). */
+template <int J0, int J1>
+__device__ __forceinline__ void kr_wlu_panel(float (&a)[KR_N], int &pc, float &dinv, float sc, bool &ok,
+                                             float *lds) {
+  const int lane = threadIdx.x;
+  int pv[J1 - J0];
+#pragma unroll
+  for (int jj = 0; jj < J1 - J0; ++jj) {
+    const int j = J0 + jj;
+    const bool cand = pc == KR_NOTPIV;
+    const float aj = a[j];
+    unsigned best;
+    const int p = kr_wargmax(fabsf(fabsf(aj) * sc), cand, best);
+    ok = ok && (best >> 6) != 0u;
+    pv[jj] = p;
+    const float piv = kr_bcastf(aj, p);
+    ok = ok && piv != 0.0f && kr_finite((double)piv);
+    const float inv = 1.0f / piv;
+    if (lane == p) { pc = j; dinv = inv; }
+    const float l = pc == KR_NOTPIV ? aj * inv : 0.0f;
+    if (pc == KR_NOTPIV) a[j] = l;
+    /* the panel's own remaining columns, from lane p's registers */
+#pragma unroll
+    for (int k = j + 1; k < J1; k += 2) {
+      const float u0 = kr_bcastf(a[k], p);
+      if (k + 1 < J1) {
+        const float u1 = kr_bcastf(a[k + 1], p);
+        a[k] = fmaf(-l, u0, a[k]);
+        a[k + 1] = fmaf(-l, u1, a[k + 1]);
+      } else {
+        a[k] = fmaf(-l, u0, a[k]);
+      }
+    }
+  }
+  if constexpr (J1 < KR_N) {
+    kr_wlu_trailing<J0, J1>(a, pc, pv, lds);
+    kr_wlu_panel<J1, J1 + 16>(a, pc, dinv, sc, ok, lds);
+  }
+}
+
+__device__ __forceinline__ bool kr_wlu_blocked(float (&a)[KR_N], int &pc, float &dinv, float *lds) {
+  const int lane = threadIdx.x;
+  float mx = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KR_N; ++k) mx = fmaxf(mx, fabsf(a[k]));
+  const float sc = lane < KR_N && mx > 0.0f ? 1.0f / mx : 0.0f;
+  pc = lane < KR_N ? KR_NOTPIV : -1;
+  dinv = 0.0f;
+  bool ok = true;
+  kr_wlu_panel<0, KR_PF>(a, pc, dinv, sc, ok, lds);
+  return ok;
+}
+#endif /* KR_USE_LU_MFMA */
+
 /* Back substitution with the factors of kr_wlu: b after the forward
  * substitution, by row, in; the solution by unknown (lane j: x_j) out. */
 template <typename F>
@@ -511,7 +658,11 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
       for (int k = 0; k < KR_N; ++k) a32[k] = (float)(a[k] * rs);
       int pc;
       float dinv;
+#ifdef KR_USE_LU_MFMA
+      bool ok32 = kr_wlu_blocked(a32, pc, dinv, reinterpret_cast<float *>(w.P));
+#else
       bool ok32 = kr_wlu(a32, pc, dinv);
+#endif
       double r = b;
       bool conv = false;
       int sweeps = 0;

@@ -100,3 +100,48 @@ def test_wave_layout_timescale(oracle_lib):
     ref = np.array([on.fastest_timescale(np.r_[cs.n[:, c], cs.T[c]]) for c in range(200)])
     np.testing.assert_allclose(tau, ref, rtol=1e-11)
     net.close()
+
+
+def _counted(kr, desc, cs, dt, build):
+    """FP32 LU form on the GPU with its statistics counters."""
+    net = kr.Network(desc, build)
+    n = torch.as_tensor(cs.n, device="cuda").clone()
+    T = torch.as_tensor(cs.T, device="cuda").clone()
+    status = torch.empty(cs.n_cells, dtype=torch.int32, device="cuda")
+    stats = torch.zeros((cs.n_cells, 4), dtype=torch.int32, device="cuda")
+    counters = torch.zeros(8, dtype=torch.int64, device="cuda")
+    o = kr.default_options(precision=kr.KR_FP32LU_REFINE)
+    o.counters = counters.data_ptr()
+    kr.chem_integrate(net, n, T, dt=torch.as_tensor(dt, device="cuda"), rtol=1e-6, opts=o, status=status,
+                      cell_stats=stats)
+    resid = torch.zeros(cs.n_cells, dtype=torch.float64, device="cuda")
+    kr.element_residual(net, torch.as_tensor(cs.n, device="cuda"), n, resid=resid)
+    torch.cuda.synchronize()
+    net.close()
+    return ((n.cpu().numpy(), T.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy(), resid.cpu().numpy()),
+            counters.cpu().numpy())
+
+
+@pytest.mark.parametrize("ncell,cap", [(96, 1e-5), (64, 1e-2)])
+def test_large48_mfma_blocked_lu(oracle_lib, ncell, cap):
+    """The FP32 LU with its trailing updates on MFMA tiles (panels of 1, 16,
+    16, 16 columns for 49 unknowns) against the oracle at 1e-6, in full
+    waves, steps up to 1e-5 s and over the configuration's whole range
+    [1e-8, 1e-2] s.  The FP32 form falls back to the FP64 LU where
+    refinement does not settle, which would hide a broken factorisation:
+    the blocked LU must need no more refinement sweeps and FP64 fallbacks
+    per Newton iteration than the unblocked one, within a few percent."""
+    kr = _kr()
+    desc, cs, dt = _large_inputs(ncell, cap)
+    src = kr.network_check(desc, build=kr.build_options(lu_mfma=1))
+    assert "#define KR_LU_MFMA 1" in src
+    g, c = _counted(kr, desc, cs, dt, kr.build_options(lu_mfma=1))
+    g0, c0 = _counted(kr, desc, cs, dt, kr.build_options(lu_mfma=0))
+    orc = run_oracle(oracle_lib, desc, cs, dt=dt)
+    assert_parity(g, orc, cs, 1e-6, "large48 fp32lu mfma", desc=desc)
+    assert_parity(g0, orc, cs, 1e-6, "large48 fp32lu valu", desc=desc)
+    it, it0 = g[3][:, 1].sum(), g0[3][:, 1].sum()
+    print(f"mfma: sweeps {c[3]} fallbacks {c[4]} iterations {it}; valu: sweeps {c0[3]} "
+          f"fallbacks {c0[4]} iterations {it0}", flush=True)
+    assert c[3] / it <= 1.05 * c0[3] / it0
+    assert c[4] <= 1.05 * c0[4] + 0.001 * it

@@ -153,3 +153,17 @@ def test_multi_kernels_grouped_by_occupancy_target():
     assert kernels([sy.network_h_he(0), sy.network_h_o_n(1)]) == [("1", "0")]
     assert kernels([sy.network_astro23(2), sy.network_large48(3)]) == [("1", "0")]
     assert kernels([sy.network_astro23(2)]) == [("2", "0")]
+
+
+def test_blocked_lu_build_option():
+    """lu_mfma=1 selects the blocked FP32 LU (MFMA trailing updates) where it
+    applies -- the 48-species network in the wavefront layout -- and is
+    ignored elsewhere; the blocked source compiles for gfx950."""
+    kr = _kr()
+    src = kr.network_check(sy.network_large48(3), compile=True, build=kr.build_options(lu_mfma=1))
+    assert "#define KR_LU_MFMA 1" in src
+    assert "#define KR_LU_MFMA 1" not in kr.network_check(sy.network_large48(3))
+    assert "#define KR_LU_MFMA 1" not in kr.network_check(sy.network_astro23(2),
+                                                          build=kr.build_options(lu_mfma=1))
+    with pytest.raises(kr.KrError):
+        kr.network_check(sy.network_large48(3), build=kr.build_options(lu_mfma=2))
