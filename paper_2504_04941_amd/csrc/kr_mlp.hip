@@ -18,10 +18,11 @@
  * the starting point of Newton's method, and the Newton residual decides.
  *
  * GEMM: 64x64 output tile per 256-thread workgroup, 4 waves of 32x32, K in
- * steps of 32 through LDS, v_mfma_f32_16x16x16_bf16 (2x2 per wave and
- * 16-deep k slice).  Operand layouts: A(m,k) and B(n,k) are read either
- * k-contiguous or transposed, so forward (X W^T), input gradient (dZ W) and
- * weight gradient (dZ^T X) share one kernel.
+ * steps of 32 through LDS, v_mfma_f32_16x16x32_bf16 (gfx950; 2x2 per wave and
+ * step), operands staged with 16-byte loads where the layout allows.
+ * Operand layouts: A(m,k) and B(n,k) are read either k-contiguous or
+ * transposed, so forward (X W^T), input gradient (dZ W) and weight gradient
+ * (dZ^T X) share one kernel.
  */
 #include <hip/hip_runtime.h>
 
@@ -31,7 +32,6 @@
 #include <vector>
 
 typedef uint16_t kr_bf16;
-typedef short kr_v4i16 __attribute__((ext_vector_type(4)));
 typedef float kr_v4f32 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ static inline kr_bf16 kr_f2bf(float x) {
@@ -69,21 +69,68 @@ struct KrEpi {
   kr_bf16 *outb;       /* [M][ldc] BF16 copy (gelu(z) or dz), or null */
   const float *zprev;  /* [M][ldc] pre-activation for DGELU */
   int ldc;
+  long long zstride;   /* STORE with a split K: slice z writes outf + z * zstride */
 };
 
+#define KR_SPLITS 16 /* batch slices of the weight-gradient products */
 #define KR_BM 64
 #define KR_BN 64
 #define KR_BK 32
 #define KR_LDS_K (KR_BK + 8)
 
+typedef __bf16 kr_v8bf16 __attribute__((ext_vector_type(8)));
+typedef unsigned short kr_v8u16 __attribute__((ext_vector_type(8)));
+
+/* Stages one operand's 64 x 32 tile into s[row][k] (zero outside the
+ * matrix).  Element (r, k) of the tile is X(r0 + r, k0 + k) with X(r, k) =
+ * TX ? X[k * ld + r] : X[r * ld + k].  VEC: 16-byte loads of 8 elements
+ * along the contiguous dimension (its extent and ld are multiples of 8). */
+template <bool TX, bool VEC>
+__device__ __forceinline__ void kr_stage_tile(kr_bf16 (*s)[KR_LDS_K], const kr_bf16 *__restrict__ X, int ld,
+                                              int R, int K, int r0, int k0, int tid) {
+  if (VEC) {
+    if (!TX) {
+      /* 64 rows x 4 chunks of 8 k: one chunk per thread */
+      const int r = tid >> 2, kc = (tid & 3) * 8;
+      const int gr = r0 + r, gk = k0 + kc;
+      kr_v8u16 v = (kr_v8u16){0, 0, 0, 0, 0, 0, 0, 0};
+      if (gr < R && gk < K) v = *reinterpret_cast<const kr_v8u16 *>(X + (size_t)gr * ld + gk);
+      *reinterpret_cast<kr_v8u16 *>(&s[r][kc]) = v;
+    } else {
+      /* 32 k x 8 chunks of 8 rows: one chunk per thread, stored transposed */
+      const int k = tid >> 3, rc = (tid & 7) * 8;
+      const int gk = k0 + k, gr = r0 + rc;
+      kr_v8u16 v = (kr_v8u16){0, 0, 0, 0, 0, 0, 0, 0};
+      if (gk < K && gr < R) v = *reinterpret_cast<const kr_v8u16 *>(X + (size_t)gk * ld + gr);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s[rc + e][k] = v[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid * 8 + e;                  /* 0..2047 */
+      int r, kk;
+      if (!TX) { r = idx / KR_BK; kk = idx % KR_BK; } else { kk = idx / KR_BM; r = idx % KR_BM; }
+      const int gr = r0 + r, gk = k0 + kk;
+      kr_bf16 v = 0;
+      if (gr < R && gk < K) v = TX ? X[(size_t)gk * ld + gr] : X[(size_t)gr * ld + gk];
+      s[r][kk] = v;
+    }
+  }
+}
+
 /* C(m, n) = sum_k A(m, k) B(n, k), A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
- * B(n,k) = TB ? B[k*ldb+n] : B[n*ldb+k]. */
-template <bool TA, bool TB, int EPI>
+ * B(n,k) = TB ? B[k*ldb+n] : B[n*ldb+k].  64 x 64 output tile per 256-thread
+ * workgroup (4 waves of 32 x 32), K in steps of 32 through LDS, each wave
+ * 2 x 2 v_mfma_f32_16x16x32_bf16 per step (lane l supplies A rows l%16,
+ * k = 8 (l/16) .. +7, and receives C rows 4 (l/16) .. +3 of column l%16).
+ * VA / VB: 16-byte operand loads (see kr_stage_tile). */
+template <bool TA, bool TB, int EPI, bool VA, bool VB>
 __global__ void __launch_bounds__(256) kr_gemm_bf16(int M, int N, int K, const kr_bf16 *__restrict__ A,
                                                     int lda, const kr_bf16 *__restrict__ B, int ldb,
-                                                    KrEpi ep) {
-  __shared__ kr_bf16 sA[KR_BM][KR_LDS_K];
-  __shared__ kr_bf16 sB[KR_BN][KR_LDS_K];
+                                                    KrEpi ep, int kchunk) {
+  __shared__ __attribute__((aligned(16))) kr_bf16 sA[KR_BM][KR_LDS_K];
+  __shared__ __attribute__((aligned(16))) kr_bf16 sB[KR_BN][KR_LDS_K];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * KR_BM, n0 = blockIdx.x * KR_BN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -93,42 +140,26 @@ __global__ void __launch_bounds__(256) kr_gemm_bf16(int M, int N, int K, const k
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (kr_v4f32){0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < K; k0 += KR_BK) {
-    /* stage the 64x32 A and B tiles (zero outside the matrix) */
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int idx = tid * 8 + e;                  /* 0..2047 */
-      int r, kk;
-      if (!TA) { r = idx / KR_BK; kk = idx % KR_BK; } else { kk = idx / KR_BM; r = idx % KR_BM; }
-      const int gm = m0 + r, gk = k0 + kk;
-      kr_bf16 v = 0;
-      if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      sA[r][kk] = v;
-      int c, kb;
-      if (!TB) { c = idx / KR_BK; kb = idx % KR_BK; } else { kb = idx / KR_BN; c = idx % KR_BN; }
-      const int gn = n0 + c, gk2 = k0 + kb;
-      kr_bf16 w = 0;
-      if (gn < N && gk2 < K) w = TB ? B[(size_t)gk2 * ldb + gn] : B[(size_t)gn * ldb + gk2];
-      sB[c][kb] = w;
-    }
+  /* split K: slice blockIdx.z covers [kb, ke) (kchunk a multiple of 32) */
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  if (EPI == KR_EPI_STORE) ep.outf += (size_t)blockIdx.z * ep.zstride;
+  for (int k0 = kb; k0 < ke; k0 += KR_BK) {
+    kr_stage_tile<TA, VA>(sA, A, lda, M, ke, m0, k0, tid);
+    kr_stage_tile<TB, VB>(sB, B, ldb, N, ke, n0, k0, tid);
     __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    kr_v8bf16 af[2], bfr[2];
 #pragma unroll
-    for (int ks = 0; ks < KR_BK; ks += 16) {
-      kr_v4i16 af[2], bfr[2];
-      const int kq = ks + 4 * (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const kr_bf16 *pa = &sA[wm + i * 16 + (lane & 15)][kq];
-        af[i] = (kr_v4i16){(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-        const kr_bf16 *pb = &sB[wn + i * 16 + (lane & 15)][kq];
-        bfr[i] = (kr_v4i16){(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < 2; ++i) {
+      af[i] = __builtin_bit_cast(kr_v8bf16, *reinterpret_cast<const kr_v8u16 *>(&sA[wm + i * 16 + (lane & 15)][kq]));
+      bfr[i] = __builtin_bit_cast(kr_v8bf16, *reinterpret_cast<const kr_v8u16 *>(&sB[wn + i * 16 + (lane & 15)][kq]));
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   /* epilogue: lane holds rows 4*(lane/16)+r of column lane%16 of each 16x16 block */
@@ -159,6 +190,42 @@ __global__ void __launch_bounds__(256) kr_gemm_bf16(int M, int N, int K, const k
       }
 }
 
+/* Launches kr_gemm_bf16 with 16-byte operand loads where the contiguous
+ * dimension and the leading dimension allow them.  splits > 1 (STORE only):
+ * K is cut into that many slices of whole 32-steps, slice z writing its
+ * partial product at ep.outf + z * ep.zstride (summed by kr_sum_slices). */
+template <bool TA, bool TB, int EPI>
+static hipError_t kr_gemm(int M, int N, int K, const kr_bf16 *A, int lda, const kr_bf16 *B, int ldb, const KrEpi &ep,
+                          hipStream_t st, int splits = 1) {
+  const int kchunk = ((K + splits - 1) / splits + KR_BK - 1) / KR_BK * KR_BK;
+  const int nz = kchunk > 0 ? (K + kchunk - 1) / kchunk : 1;
+  const dim3 grid((N + KR_BN - 1) / KR_BN, (M + KR_BM - 1) / KR_BM, nz > 0 ? nz : 1);
+  const bool va = lda % 8 == 0 && (TA ? M : K) % 8 == 0 && (((uintptr_t)A) & 15) == 0;
+  const bool vb = ldb % 8 == 0 && (TB ? N : K) % 8 == 0 && (((uintptr_t)B) & 15) == 0;
+  if (va && vb)
+    hipLaunchKernelGGL((kr_gemm_bf16<TA, TB, EPI, true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, ep,
+                       kchunk);
+  else if (va)
+    hipLaunchKernelGGL((kr_gemm_bf16<TA, TB, EPI, true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, ep,
+                       kchunk);
+  else if (vb)
+    hipLaunchKernelGGL((kr_gemm_bf16<TA, TB, EPI, false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, ep,
+                       kchunk);
+  else
+    hipLaunchKernelGGL((kr_gemm_bf16<TA, TB, EPI, false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
+                       ep, kchunk);
+  return hipGetLastError();
+}
+
+/* dst[i] = sum over z of src[z * n + i], z in order (deterministic) */
+__global__ void kr_sum_slices(long n, int nz, const float *__restrict__ src, float *__restrict__ dst) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int z = 0; z < nz; ++z) s += src[(size_t)z * n + i];
+    dst[i] = s;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* elementwise kernels                                                       */
 /* ------------------------------------------------------------------------ */
@@ -182,13 +249,30 @@ __global__ void kr_mse_grad(int B, int n_out, int ld, const float *__restrict__ 
   if ((threadIdx.x & 63) == 0) atomicAdd(loss, local);
 }
 
-/* db[c] = sum over the batch of dz[b][c] (FP32), one thread per column */
-__global__ void kr_col_sum(int B, int N, int ld, const float *__restrict__ dz, float *__restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += dz[(size_t)b * ld + c];
-  db[c] = s;
+/* Column sums of dz [B][ld] over row slices: workgroup (x, y) sums the 64
+ * columns 64 x .. 64 x + 63 over rows [y rows_per, (y + 1) rows_per) into
+ * part[y][c] (4 row groups of 4 partial sums each, added in a fixed order;
+ * kr_sum_slices then adds the slices in order: deterministic). */
+__global__ void __launch_bounds__(256) kr_col_sum(int B, int N, int ld, int rows_per, const float *__restrict__ dz,
+                                                  float *__restrict__ part) {
+  __shared__ float sp[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * rows_per, r1 = min(B, r0 + rows_per);
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  if (c < N) {
+    int b = r0 + g;
+    for (; b + 12 < r1; b += 16) {
+      s0 += dz[(size_t)b * ld + c];
+      s1 += dz[(size_t)(b + 4) * ld + c];
+      s2 += dz[(size_t)(b + 8) * ld + c];
+      s3 += dz[(size_t)(b + 12) * ld + c];
+    }
+    for (; b < r1; b += 4) s0 += dz[(size_t)b * ld + c];
+  }
+  sp[g][threadIdx.x & 63] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && c < N)
+    part[(size_t)blockIdx.y * N + c] = (sp[0][threadIdx.x] + sp[1][threadIdx.x]) + (sp[2][threadIdx.x] + sp[3][threadIdx.x]);
 }
 
 /* Adam on FP32 master weights, re-rounding the BF16 copy (n elements) */
@@ -340,6 +424,7 @@ struct kr_guess {
   int bcap = 0;                  /* activation buffers sized for bcap rows */
   kr_bf16 *a_in = nullptr, *act[2] = {nullptr, nullptr}, *dzb[2] = {nullptr, nullptr};
   float *zbuf = nullptr, *out = nullptr, *tgt = nullptr, *dzf[2] = {nullptr, nullptr};
+  float *part = nullptr;         /* split-K partial weight gradients [KR_SPLITS][max layer size] */
   std::vector<float *> zl;       /* per hidden layer pre-activations (training) */
   std::vector<kr_bf16 *> al;     /* per hidden layer BF16 activations (training) */
 };
@@ -349,10 +434,10 @@ static void guess_free_buffers(kr_guess *q) {
   for (auto p : q->al) (void)hipFree(p);
   q->zl.clear();
   q->al.clear();
-  void *bufs[] = {q->a_in, q->out, q->tgt, q->dzf[0], q->dzf[1], q->dzb[0], q->dzb[1]};
+  void *bufs[] = {q->a_in, q->out, q->tgt, q->dzf[0], q->dzf[1], q->dzb[0], q->dzb[1], q->part};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
-  q->a_in = nullptr; q->out = q->tgt = nullptr;
+  q->a_in = nullptr; q->out = q->tgt = nullptr; q->part = nullptr;
   q->dzf[0] = q->dzf[1] = nullptr; q->dzb[0] = q->dzb[1] = nullptr;
   q->bcap = 0;
 }
@@ -369,6 +454,9 @@ static int guess_reserve(kr_guess *q, int B) {
     HIP_TRY(hipMalloc(&q->dzf[k], sizeof(float) * B * HD));
     HIP_TRY(hipMalloc(&q->dzb[k], sizeof(kr_bf16) * B * HD));
   }
+  long maxw = 0;
+  for (int l = 0; l <= q->layers; ++l) maxw = std::max(maxw, q->fan_in[l] * q->fan_out[l]);
+  HIP_TRY(hipMalloc(&q->part, sizeof(float) * KR_SPLITS * (size_t)maxw));
   q->zl.assign(q->layers, nullptr);
   q->al.assign(q->layers, nullptr);
   for (int l = 0; l < q->layers; ++l) {
@@ -378,8 +466,6 @@ static int guess_reserve(kr_guess *q, int B) {
   q->bcap = B;
   return KR_OK;
 }
-
-static dim3 gemm_grid(int M, int N) { return dim3((N + KR_BN - 1) / KR_BN, (M + KR_BM - 1) / KR_BM); }
 
 /* forward pass of B standardised rows already in a_in; out <- outputs */
 static int guess_forward(kr_guess *q, int B, hipStream_t st) {
@@ -394,13 +480,11 @@ static int guess_forward(kr_guess *q, int B, hipStream_t st) {
     if (l < q->layers) {
       ep.outf = q->zl[l];
       ep.outb = q->al[l];
-      hipLaunchKernelGGL((kr_gemm_bf16<false, false, KR_EPI_BIAS_GELU>), gemm_grid(B, N), dim3(256), 0, st,
-                         B, N, K, a, K, W, K, ep);
+      HIP_TRY((kr_gemm<false, false, KR_EPI_BIAS_GELU>(B, N, K, a, K, W, K, ep, st)));
       a = q->al[l];
     } else {
       ep.outf = q->out;
-      hipLaunchKernelGGL((kr_gemm_bf16<false, false, KR_EPI_BIAS>), gemm_grid(B, N), dim3(256), 0, st, B,
-                         N, K, a, K, W, K, ep);
+      HIP_TRY((kr_gemm<false, false, KR_EPI_BIAS>(B, N, K, a, K, W, K, ep, st)));
     }
     HIP_TRY(hipGetLastError());
     K = N;
@@ -425,10 +509,23 @@ static int guess_backward(kr_guess *q, int B, hipStream_t st) {
     ep.outf = q->g + q->w_off[l];
     ep.ldc = K;
     /* dW_l[n][k] = sum_b dz[b][n] a[b][k] */
-    hipLaunchKernelGGL((kr_gemm_bf16<true, true, KR_EPI_STORE>), gemm_grid(N, K), dim3(256), 0, st, N, K, B,
-                       q->dzb[cur], N, ain, K, ep);
+    /* dW over KR_SPLITS slices of the batch, then summed in order */
+    KrEpi ep_s = ep;
+    ep_s.outf = q->part;
+    ep_s.zstride = (long long)N * K;
+    HIP_TRY((kr_gemm<true, true, KR_EPI_STORE>(N, K, B, q->dzb[cur], N, ain, K, ep_s, st, KR_SPLITS)));
+    const int kchunk = ((B + KR_SPLITS - 1) / KR_SPLITS + KR_BK - 1) / KR_BK * KR_BK;
+    const int nz = (B + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL(kr_sum_slices, dim3((N * K + 255) / 256), dim3(256), 0, st, (long)N * K, nz, q->part,
+                       q->g + q->w_off[l]);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(kr_col_sum, dim3((N + 255) / 256), dim3(256), 0, st, B, N, N, q->dzf[cur],
+    /* db the same way: column sums over row slices, then the slices in order */
+    const int rows_per = (B + KR_SPLITS - 1) / KR_SPLITS;
+    const int ny = (B + rows_per - 1) / rows_per;
+    hipLaunchKernelGGL(kr_col_sum, dim3((N + 63) / 64, ny), dim3(256), 0, st, B, N, N, rows_per, q->dzf[cur],
+                       q->part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(kr_sum_slices, dim3((N + 255) / 256), dim3(256), 0, st, (long)N, ny, q->part,
                        q->g + q->b_off[l]);
     HIP_TRY(hipGetLastError());
     if (l > 0) {
@@ -438,9 +535,7 @@ static int guess_backward(kr_guess *q, int B, hipStream_t st) {
       e2.outb = q->dzb[cur ^ 1];
       e2.zprev = q->zl[l - 1];
       e2.ldc = K;
-      hipLaunchKernelGGL((kr_gemm_bf16<false, true, KR_EPI_DGELU>), gemm_grid(B, K), dim3(256), 0, st, B, K,
-                         N, q->dzb[cur], N, q->wb + q->w_off[l], K, e2);
-      HIP_TRY(hipGetLastError());
+      HIP_TRY((kr_gemm<false, true, KR_EPI_DGELU>(B, K, N, q->dzb[cur], N, q->wb + q->w_off[l], K, e2, st)));
       cur ^= 1;
     }
   }
