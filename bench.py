@@ -9,7 +9,12 @@ one kr_chem_integrate call over all cells from the same initial batch (the
 initial state is restored on the device before each step, a copy of ~100 MB
 that is <0.1% of a step).
 
-Prints one JSON line (the contract of this repository's driver), with a
+Variants: plain FP64 (the headline), the FP32 LU form with FP64
+refinement, the same with the learned Newton guess, and the paper's single-
+and mixed-precision modes (FP32 integration; the latter with the final
+abundance update in FP64).
+
+Prints one JSON line (metric, value, configuration and variants), with a
 roofline object for the integrator kernel (FP64 VALU bound, algorithmic
 flops from the per-cell Newton/substep counts the kernel returns, timed with
 HIP events on the launch stream) and the CPU oracle timed on a bounded
@@ -363,8 +368,8 @@ def run_large(args):
 def run_h_he(args):
     """Small case: 4096 cells of the 5-species H/He/charge network (10
     reversible reactions, 6 unknowns), each cell's step 1e3 times its own
-    fastest timescale, adaptive, rtol 1e-6; plain FP64 and the FP32 LU
-    form, one cell per lane."""
+    fastest timescale, adaptive, rtol 1e-6; plain FP64, the FP32 LU form
+    and the paper's single- and mixed-precision modes."""
     import torch
     import paper_2504_04941_amd as kr
     import synthetic as sy
@@ -383,8 +388,10 @@ def run_h_he(args):
     f_it, f_rhs = flops_per_unit(desc)
     stream = torch.cuda.current_stream()
     results, gpu_out = {}, {}
-    for variant in ("fp64", "fp32lu"):
-        opts = kr.default_options(precision=kr.KR_FP64 if variant == "fp64" else kr.KR_FP32LU_REFINE)
+    for variant in args.variants.split(","):
+        if net.wide and variant in ("single", "mixed"):
+            continue                      # the FP32 modes run in the lane layout only
+        opts = kr.default_options(precision=variant)
 
         def step():
             n.copy_(n0)
@@ -592,7 +599,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=1 << 20)
-    ap.add_argument("--variants", default="fp64,fp32lu,fp32lu+mlp")
+    ap.add_argument("--variants", default="fp64,fp32lu,fp32lu+mlp,single,mixed")
     ap.add_argument("--train-pairs", type=int, default=1 << 24)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--cpu-sample", type=int, default=8192)
@@ -615,12 +622,14 @@ def main():
     if args.workload == "h_he":
         if args.cells == 1 << 20:
             args.cells = 4096
+        if args.variants == ap.get_default("variants"):
+            args.variants = "fp64,fp32lu,single,mixed"
         run_h_he(args)
         return
     if args.workload == "large48":
         if args.cells == 1 << 20:
             args.cells = 1 << 18
-        if args.variants == "fp64,fp32lu,fp32lu+mlp":
+        if args.variants == ap.get_default("variants"):
             args.variants = "fp64,fp32lu"
         if args.cpu_sample == 8192:
             args.cpu_sample = 48
@@ -719,7 +728,8 @@ def main():
     xs = torch.empty((args.cells, desc.n_species + 2), dtype=torch.float32, device=dev)
     for variant in args.variants.split(","):
         prec = {"fp64": kr.KR_FP64, "fp32lu": kr.KR_FP32LU_REFINE,
-                "fp32lu+mlp": kr.KR_FP32LU_REFINE, "fp64+mlp": kr.KR_FP64}[variant]
+                "fp32lu+mlp": kr.KR_FP32LU_REFINE, "fp64+mlp": kr.KR_FP64,
+                "single": kr.KR_SINGLE, "mixed": kr.KR_MIXED}[variant]
         use_guess = "mlp" in variant
         opts = (kr.guess_options(guess, precision=prec, order=_order(args)) if use_guess
                 else kr.default_options(precision=prec, order=_order(args)))

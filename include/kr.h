@@ -187,7 +187,23 @@ int kr_network_check_ex(const kr_network_desc *desc, const kr_build_opts *opt, i
 /* Integration                                                               */
 /* ------------------------------------------------------------------------ */
 
-enum { KR_FP64 = 0, KR_FP32LU_REFINE = 1 };  /* precision of the linear solve */
+/* Precision of the per-cell integration:
+ *   KR_FP64           everything in FP64
+ *   KR_FP32LU_REFINE  the LU in FP32; residual, iterative refinement and the
+ *                     element projection in FP64 (same root as KR_FP64)
+ *   KR_SINGLE         the paper's full single-precision mode (Sec. 2): the
+ *                     cell's integration in FP32 (rates with the hardware's
+ *                     exp2/log2, Jacobian, LU, iterate, error estimate; the
+ *                     substep clock stays FP64), post-processing in FP64
+ *   KR_MIXED          the paper's mixed-precision mode: as KR_SINGLE, but the
+ *                     final abundance update of the call is FP64 (n_out =
+ *                     n_in + the FP32 change); lane layout only (n_species <
+ *                     KR_WIDE_MIN_SPECIES or KR_LAYOUT_LANE), as KR_SINGLE
+ * In the FP32 modes a Newton iteration also stops once its update is within
+ * 4 FP32 ulps of the iterate, and the retry thresholds (element residual,
+ * negative abundance) are 1e-5 instead of 1e-10: rtol well below 1e-5 asks
+ * for more than FP32 holds. */
+enum { KR_FP64 = 0, KR_FP32LU_REFINE = 1, KR_SINGLE = 2, KR_MIXED = 3 };
 enum { KR_ADAPTIVE = 0, KR_FIXED_STEP = 1 }; /* substep control */
 /* Order in which the persistent kernel hands out a batch's cells.  Results
  * per cell are the same either way.  KR_ORDER_WORK first sorts the cells by
@@ -226,9 +242,8 @@ typedef struct {
 } kr_stats;
 
 typedef struct {
-  int32_t precision;    /* KR_FP64 (default) or KR_FP32LU_REFINE: LU in FP32,
-                           residual, iterative refinement and the element
-                           projection in FP64 */
+  int32_t precision;    /* KR_FP64 (default), KR_FP32LU_REFINE, KR_SINGLE
+                           or KR_MIXED (see above) */
   int32_t mode;         /* KR_ADAPTIVE (default) or KR_FIXED_STEP */
   int32_t n_fixed;      /* substeps per cell in KR_FIXED_STEP (>= 1) */
   int32_t max_newton;   /* Newton iterations per substep (default 10) */

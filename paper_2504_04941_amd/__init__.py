@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkr.so")
 
 KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
-KR_FP64, KR_FP32LU_REFINE = 0, 1
+KR_FP64, KR_FP32LU_REFINE, KR_SINGLE, KR_MIXED = 0, 1, 2, 3
 KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
 KR_ORDER_INPUT, KR_ORDER_WORK = 0, 1
 KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
@@ -179,7 +179,7 @@ def default_options(**kw) -> Options:
     lib().kr_default_options(C.byref(o))
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
-            v = {"fp64": KR_FP64, "fp32lu": KR_FP32LU_REFINE}[v]
+            v = {"fp64": KR_FP64, "fp32lu": KR_FP32LU_REFINE, "single": KR_SINGLE, "mixed": KR_MIXED}[v]
         if k == "mode" and isinstance(v, str):
             v = {"adaptive": KR_ADAPTIVE, "fixed": KR_FIXED_STEP}[v]
         setattr(o, k, v)

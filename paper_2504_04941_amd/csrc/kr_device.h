@@ -72,17 +72,25 @@ __device__ __forceinline__ double kr_rcp_w(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-/* A lane's slot in a per-wave LDS array laid out [index][lane], so that a
- * wave's 64 accesses to one index hit 64 consecutive doubles. */
-struct KrSlot {
-  double *base;
-  __device__ __forceinline__ double &operator[](int i) const { return base[i * 64]; }
-};
+/* 1/x of the working precision: FP64 as kr_rcp, FP32 the hardware estimate
+ * (1 ulp). */
+__device__ __forceinline__ double kr_rcp_r(double x) { return kr_rcp(x); }
+__device__ __forceinline__ float kr_rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ double kr_heat_capacity(const double (&y)[KR_N]) {
-  double c = 0.0;
+/* A lane's slot in a per-wave LDS array laid out [index][lane], so that a
+ * wave's 64 accesses to one index hit 64 consecutive values. */
+template <typename R>
+struct KrSlotT {
+  R *base;
+  __device__ __forceinline__ R &operator[](int i) const { return base[i * 64]; }
+};
+typedef KrSlotT<double> KrSlot;
+
+template <typename R>
+__device__ __forceinline__ R kr_heat_capacity(const R (&y)[KR_N]) {
+  R c = R(0);
 #pragma unroll
-  for (int s = 0; s < KR_S; ++s) c += kr_cv[s] * y[s];
+  for (int s = 0; s < KR_S; ++s) c += R(kr_cv[s]) * y[s];
   return c;
 }
 
@@ -93,17 +101,18 @@ __device__ __forceinline__ double kr_heat_capacity(const double (&y)[KR_N]) {
 /* Solves a x = b in place (b <- x) for one lane's matrix, by Gaussian
  * elimination of the augmented system with threshold partial pivoting.
  * Returns false for a zero row or a zero / non-finite pivot. */
-__device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)[KR_N],
+template <typename R>
+__device__ __forceinline__ bool kr_lu_solve(R (&a)[KR_N][KR_N], R (&b)[KR_N],
                                             unsigned long long *swap_count) {
   /* inverse row scales only steer the pivot choice: FP32 is plenty */
   float sc[KR_N];
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) {
-    double v = 0.0;
+    R v = R(0);
 #pragma unroll
     for (int k = 0; k < KR_N; ++k) v = fmax(v, fabs(a[i][k]));
-    ok = ok && (v > 0.0) && kr_finite(v);
+    ok = ok && (v > R(0)) && kr_finite((double)v);
     sc[i] = __builtin_amdgcn_rcpf((float)v);
   }
 #pragma unroll
@@ -130,11 +139,11 @@ __device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)
         bool sw = need && bi == i;
 #pragma unroll
         for (int k = j; k < KR_N; ++k) {
-          double u = a[j][k], w = a[i][k];
+          R u = a[j][k], w = a[i][k];
           a[j][k] = sw ? w : u;
           a[i][k] = sw ? u : w;
         }
-        double u = b[j], w = b[i];
+        R u = b[j], w = b[i];
         b[j] = sw ? w : u;
         b[i] = sw ? u : w;
         float su = sc[j], sw2 = sc[i];
@@ -142,13 +151,13 @@ __device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)
         sc[i] = sw ? su : sw2;
       }
     }
-    const double piv = a[j][j];
-    ok = ok && (piv != 0.0) && kr_finite(piv);
-    const double d = kr_rcp(piv);
+    const R piv = a[j][j];
+    ok = ok && (piv != R(0)) && kr_finite((double)piv);
+    const R d = kr_rcp_r(piv);
     a[j][j] = d;                      /* reciprocal pivot kept on the diagonal */
 #pragma unroll
     for (int i = j + 1; i < KR_N; ++i) {
-      const double l = a[i][j] * d;
+      const R l = a[i][j] * d;
 #pragma unroll
       for (int k = j + 1; k < KR_N; ++k) a[i][k] = fma(-l, a[j][k], a[i][k]);
       b[i] = fma(-l, b[j], b[i]);
@@ -156,7 +165,7 @@ __device__ __forceinline__ bool kr_lu_solve(double (&a)[KR_N][KR_N], double (&b)
   }
 #pragma unroll
   for (int i = KR_N - 1; i >= 0; --i) {
-    double x = b[i];
+    R x = b[i];
 #pragma unroll
     for (int k = i + 1; k < KR_N; ++k) x = fma(-a[i][k], b[k], x);
     b[i] = x * a[i][i];
@@ -382,27 +391,25 @@ __device__ __forceinline__ int kr_postprocess(const double (&E0)[KR_NROWS > 0 ? 
  * the starting point -- a learned guess need not conserve; this restores it
  * after the FP32 factorisation.  (The paper's projector P = V V^T is the
  * W = I case, applied to a d whose start already conserves.) */
-__device__ __forceinline__ void kr_project(const double (&y)[KR_N], const double (&yn)[KR_N], double atol,
-                                           double (&d)[KR_N]) {
-  if (KR_NROWS == 0) return;
+/* the correction of d for the conserved-row misfit r = N (y + d) - target,
+ * in the working precision R: d <- d - W N^T (N W N^T)^-1 r */
+template <typename R>
+__device__ __forceinline__ void kr_project_core(const R (&y)[KR_N], R atol, R (&r)[KR_NROWS > 0 ? KR_NROWS : 1],
+                                                R (&d)[KR_N]) {
   constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
-  double W[KR_S];
+  constexpr R tiny = sizeof(R) == 4 ? R(1e-37) : R(1e-300);
+  R W[KR_S];
 #pragma unroll
   for (int s = 0; s < KR_S; ++s) W[s] = fmax(fabs(y[s]), atol);
-  double G[V][V], r[V];
+  R G[V][V];
 #pragma unroll
   for (int a = 0; a < V; ++a) {
-    double t = 0.0;
-#pragma unroll
-    for (int s = 0; s < KR_S; ++s)
-      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * (d[s] + (y[s] - yn[s]));
-    r[a] = t;
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      double g = 0.0;
+      R g = R(0);
 #pragma unroll
       for (int s = 0; s < KR_S; ++s)
-        if (kr_comp[a][s] != 0 && kr_comp[b][s] != 0) g += (double)(kr_comp[a][s] * kr_comp[b][s]) * W[s];
+        if (kr_comp[a][s] != 0 && kr_comp[b][s] != 0) g += (R)(kr_comp[a][s] * kr_comp[b][s]) * W[s];
       G[a][b] = g;
     }
   }
@@ -411,44 +418,102 @@ __device__ __forceinline__ void kr_project(const double (&y)[KR_N], const double
   for (int a = 0; a < V; ++a) {
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      double t = G[a][b];
+      R t = G[a][b];
 #pragma unroll
       for (int k = 0; k < b; ++k) t -= G[a][k] * G[b][k];
-      if (a == b) G[a][a] = sqrt(fmax(t, 1e-300));
+      if (a == b) G[a][a] = sqrt(fmax(t, tiny));
       else G[a][b] = t / G[b][b];
     }
   }
 #pragma unroll
   for (int a = 0; a < V; ++a) {
-    double t = r[a];
+    R t = r[a];
 #pragma unroll
     for (int k = 0; k < a; ++k) t -= G[a][k] * r[k];
     r[a] = t / G[a][a];
   }
 #pragma unroll
   for (int a = V - 1; a >= 0; --a) {
-    double t = r[a];
+    R t = r[a];
 #pragma unroll
     for (int k = a + 1; k < V; ++k) t -= G[k][a] * r[k];
     r[a] = t / G[a][a];
   }
 #pragma unroll
   for (int s = 0; s < KR_S; ++s) {
-    double t = 0.0;
+    R t = R(0);
 #pragma unroll
     for (int a = 0; a < V; ++a)
-      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * r[a];
+      if (kr_comp[a][s] != 0) t += (R)kr_comp[a][s] * r[a];
     d[s] -= W[s] * t;
   }
+}
+
+__device__ __forceinline__ void kr_project(const double (&y)[KR_N], const double (&yn)[KR_N], double atol,
+                                           double (&d)[KR_N]) {
+  if (KR_NROWS == 0) return;
+  double r[KR_NROWS > 0 ? KR_NROWS : 1];
+#pragma unroll
+  for (int a = 0; a < KR_NROWS; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s)
+      if (kr_comp[a][s] != 0) t += kr_comp[a][s] * (d[s] + (y[s] - yn[s]));
+    r[a] = t;
+  }
+  kr_project_core(y, atol, r, d);
+}
+
+/* The same projection onto fixed totals E (the cell's input totals), in the
+ * working precision: the single- and mixed-precision integrations keep
+ * every iterate within a rounding of the input's conserved totals, where a
+ * projection onto the substep start would let the FP32 roundings of
+ * thousands of substeps add up. */
+template <typename R>
+__device__ __forceinline__ void kr_project_to(const R (&y)[KR_N], const KrSlotT<R> &E, R atol, R (&d)[KR_N]) {
+  if (KR_NROWS == 0) return;
+  R r[KR_NROWS > 0 ? KR_NROWS : 1];
+#pragma unroll
+  for (int a = 0; a < KR_NROWS; ++a) {
+    R t = -E[a];
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s)
+      if (kr_comp[a][s] != 0) t += (R)kr_comp[a][s] * (y[s] + d[s]);
+    r[a] = t;
+  }
+  kr_project_core(y, atol, r, d);
 }
 
 /* ------------------------------------------------------------------------ */
 /* the integrator                                                            */
 /* ------------------------------------------------------------------------ */
 
-struct KrLane {
+/* Working precision of the integrator's per-substep arithmetic (rates,
+ * Jacobian, Newton matrix, LU and solve, iterate, error estimate):
+ *   KR_P_FP64   plain FP64
+ *   KR_P_FP32LU FP64, but the LU in FP32 with FP64 refinement and projection
+ *   KR_P_SINGLE the paper's full single-precision mode: FP32 throughout the
+ *               cell's integration (the substep clock h, t and the norms'
+ *               weights stay FP64)
+ *   KR_P_MIXED  the paper's mixed-precision mode: as KR_P_SINGLE, with the
+ *               final abundance update of the call in FP64 (n_out = n_in +
+ *               (y_end - y_start), the change taken in FP32)
+ * The checks that send a cell to the retry scale with the working
+ * precision: an element residual above 1e-10 (FP64) or 1e-5 (FP32), an
+ * abundance below -1e-10 (FP64) or -1e-5 (FP32) times the nuclei density.
+ * FP32 Newton iterations also stop when the update no longer moves the
+ * iterate beyond 4 FP32 ulps (it cannot get smaller in that precision). */
+enum { KR_P_FP64 = 0, KR_P_FP32LU = 1, KR_P_SINGLE = 2, KR_P_MIXED = 3 };
+
+template <int PREC> struct KrReal { typedef double type; };
+template <> struct KrReal<KR_P_SINGLE> { typedef float type; };
+template <> struct KrReal<KR_P_MIXED> { typedef float type; };
+
+template <typename R>
+struct KrLaneT {
   long long cell;
-  KrSlot y, yn, gn;             /* iterate, substep start and its rates: LDS */
+  KrSlotT<R> y, yn, gn;         /* iterate, substep start and its rates: LDS */
+  KrSlotT<R> e0;                /* FP32 modes: the input's conserved totals (LDS) */
   KrSlot hx;                    /* LDS: [0] the controller's length before the
                                    last substep was clipped to land on dt,
                                    then the proposed next length */
@@ -458,11 +523,24 @@ struct KrLane {
   int gstate;                   /* 1 guess pending, 2 Newton running from it */
   int acc, iters, rej, nfail;
 };
+typedef KrLaneT<double> KrLane;
 
-__device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLane &L, const double (&y0)[KR_N]) {
+template <typename R>
+__device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLaneT<R> &L, const double (&y0)[KR_N]) {
+  R yr[KR_N];
 #pragma unroll
-  for (int i = 0; i < KR_N; ++i) { L.y[i] = y0[i]; L.yn[i] = y0[i]; }
-  L.eps_n = y0[KR_S] * kr_heat_capacity(y0);
+  for (int i = 0; i < KR_N; ++i) { yr[i] = (R)y0[i]; L.y[i] = yr[i]; L.yn[i] = yr[i]; }
+  if constexpr (sizeof(R) == 4) {
+#pragma unroll
+    for (int v = 0; v < KR_NROWS; ++v) {
+      double t = 0.0;
+#pragma unroll
+      for (int s = 0; s < KR_S; ++s)
+        if (kr_comp[v][s] != 0) t += kr_comp[v][s] * y0[s];
+      L.e0[v] = (R)t;
+    }
+  }
+  L.eps_n = yr[KR_S] * kr_heat_capacity(yr);
   L.t = 0.0;
   if (p.mode == 1) {
     L.h = L.dt / (double)p.n_fixed;
@@ -488,7 +566,8 @@ __device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLane &L, c
  * cell (nlog: accepted substeps of the attempt that produced the result, 0
  * for a reverted cell or one with nothing to integrate; resid: its element
  * residual after post-processing, 0 if it has none). */
-__device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLane &L, int code, int nlog,
+template <typename R>
+__device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLaneT<R> &L, int code, int nlog,
                                                  double resid) {
   if (p.status) p.status[L.cell] = code;
   if (p.cell_stats) {
@@ -512,7 +591,8 @@ __device__ __forceinline__ void kr_write_outcome(const KrParams &p, const KrLane
 
 /* The attempt failed: retry once with a reduced first substep and tighter
  * step control, else revert (inputs untouched, status 2). */
-__device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) {
+template <typename R>
+__device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLaneT<R> &L) {
   if (L.attempt == 0 && p.mode == 0) {
     double y0[KR_N], dt;
     kr_load_input(p, L.cell, y0, dt);
@@ -525,18 +605,25 @@ __device__ __forceinline__ void kr_attempt_failed(const KrParams &p, KrLane &L) 
   }
 }
 
-__device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
+template <int PREC, typename R>
+__device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLaneT<R> &L) {
   double y0[KR_N], dt, y[KR_N];
   kr_load_input(p, L.cell, y0, dt);
 #pragma unroll
-  for (int i = 0; i < KR_N; ++i) y[i] = L.y[i];
+  for (int i = 0; i < KR_N; ++i) {
+    y[i] = (double)L.y[i];
+    /* mixed precision: the change over the call, taken in the working
+     * precision, added to the input in FP64 */
+    if (PREC == KR_P_MIXED) y[i] = y0[i] + (y[i] - (double)(R)y0[i]);
+  }
   const double nn = kr_nuclei(y0);
+  constexpr double lim = sizeof(R) == 4 ? 1e-5 : 1e-10;
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) ok = ok && kr_finite(y[i]);
 #pragma unroll
-  for (int s = 0; s < KR_S; ++s) ok = ok && !(y[s] < -1e-10 * nn);
-  ok = ok && kr_element_resid(y0, y) <= 1e-10;
+  for (int s = 0; s < KR_S; ++s) ok = ok && !(y[s] < -lim * nn);
+  ok = ok && kr_element_resid(y0, y) <= lim;
   if (!ok) { kr_attempt_failed(p, L); return; }
   double E0[KR_NROWS > 0 ? KR_NROWS : 1];
 #pragma unroll
@@ -557,7 +644,8 @@ __device__ __forceinline__ void kr_finish_cell(const KrParams &p, KrLane &L) {
 }
 
 /* Takes the next cell for an idle lane.  Returns false when none is left. */
-__device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
+template <typename R>
+__device__ __forceinline__ bool kr_claim(const KrParams &p, KrLaneT<R> &L) {
   const unsigned long long c = atomicAdd(p.counter, 1ull);
   if (c >= (unsigned long long)p.n_cells) return false;
   L.cell = (long long)c;
@@ -588,14 +676,16 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLane &L) {
   return true;
 }
 
-__device__ __forceinline__ double kr_weight(const KrParams &p, const KrLane &L, int i, double yi) {
+template <typename R>
+__device__ __forceinline__ double kr_weight(const KrParams &p, const KrLaneT<R> &L, int i, double yi) {
   const double a = i < KR_S ? L.atol : 0.0;
-  return a + p.rtol * fmax(fabs(L.yn[i]), fabs(yi));
+  return a + p.rtol * fmax(fabs((double)L.yn[i]), fabs(yi));
 }
 
 /* Newton failure: quarter the substep and restart it from y_n (adaptive);
  * a fixed substep sequence cannot shrink, so the attempt fails. */
-__device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
+template <typename R>
+__device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLaneT<R> &L) {
   if (L.gstate == 2) {
     /* Newton failed from the learned guess: redo the same substep from
      * the plain starting point, without cutting the step */
@@ -615,20 +705,25 @@ __device__ __forceinline__ void kr_newton_failed(const KrParams &p, KrLane &L) {
   L.phase = KR_PH_RESTART;
 }
 
-template <bool MIXED>
+template <int PREC>
 __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
-  __shared__ double s_y[KR_N * 64], s_yn[KR_N * 64], s_gn[KR_N * 64], s_hx[64];
-  KrLane L;
+  typedef typename KrReal<PREC>::type R;
+  constexpr bool MIXED = PREC == KR_P_FP32LU;
+  __shared__ R s_y[KR_N * 64], s_yn[KR_N * 64], s_gn[KR_N * 64];
+  __shared__ double s_hx[64];
+  __shared__ R s_e0[(sizeof(R) == 4 && KR_NROWS > 0 ? KR_NROWS : 1) * 64];
+  KrLaneT<R> L;
   L.cell = -1;
   L.phase = KR_PH_NONE;
   L.y.base = s_y + threadIdx.x;
   L.yn.base = s_yn + threadIdx.x;
   L.gn.base = s_gn + threadIdx.x;
   L.hx.base = s_hx + threadIdx.x;
+  L.e0.base = s_e0 + threadIdx.x;
   L.hx[0] = 0.0;
   bool exhausted = false;
 #pragma unroll
-  for (int i = 0; i < KR_N; ++i) { L.y[i] = 1.0; L.yn[i] = 1.0; L.gn[i] = 0.0; }
+  for (int i = 0; i < KR_N; ++i) { L.y[i] = R(1); L.yn[i] = R(1); L.gn[i] = R(0); }
   L.h = L.t = L.dt = L.atol = L.eps_n = L.prev = 0.0;
   L.safety = 0.9; L.growth = 5.0;
   L.attempt = L.k = L.grow = L.attempts = L.fin = L.gstate = L.acc0 = 0;
@@ -645,12 +740,12 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
     if (!active) continue;
 
     /* rates and Jacobian at the lane's current point */
-    double g[KR_N], J[KR_N][KR_N], yv[KR_N];
+    R g[KR_N], J[KR_N][KR_N], yv[KR_N];
 #pragma unroll
     for (int i = 0; i < KR_N; ++i) yv[i] = L.y[i];
     kr_eval(yv, g, J);
-    const double cv = kr_heat_capacity(yv);
-    const double icv = kr_rcp(cv);
+    const R cv = kr_heat_capacity(yv);
+    const R icv = kr_rcp_r(cv);
     const int ph = L.phase;
 
     if (ph == KR_PH_CHECK) {
@@ -660,14 +755,15 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         L.eps_n = yv[KR_S] * cv;
         if (p.h_log && L.acc - L.acc0 < p.h_log_cap) p.h_log[(long long)(L.acc - L.acc0) * p.h_log_ld + L.cell] = L.h;
         L.acc++;
-        if (L.acc >= p.n_fixed) kr_finish_cell(p, L);
+        if (L.acc >= p.n_fixed) kr_finish_cell<PREC>(p, L);
         else L.phase = KR_PH_START;
       } else {
         double err = 0.0;
+        const R hh = (R)(0.5 * L.h);
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) {
-          const double gi = i < KR_S ? g[i] : g[KR_S] * icv;
-          const double e = fabs(0.5 * L.h * (gi - L.gn[i])) * kr_rcp_w(kr_weight(p, L, i, yv[i]));
+          const R gi = i < KR_S ? g[i] : g[KR_S] * icv;
+          const double e = (double)fabs(hh * (gi - L.gn[i])) * kr_rcp_w(kr_weight(p, L, i, (double)yv[i]));
           err = e > err ? e : err;
         }
         if (!kr_finite(err)) {
@@ -691,7 +787,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
              * substep, or the unclipped length if that was larger */
             const double hf = L.hx[0];
             L.hx[0] = hf > hnew ? hf : hnew;
-            kr_finish_cell(p, L);
+            kr_finish_cell<PREC>(p, L);
           } else {
             L.t += L.h;
             L.h = hnew;
@@ -732,7 +828,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
           /* first substep: start Newton from the learned guess (evaluated
            * on the next trip) */
 #pragma unroll
-          for (int i = 0; i < KR_N; ++i) L.y[i] = p.guess[(long long)i * p.guess_ld + L.cell];
+          for (int i = 0; i < KR_N; ++i) L.y[i] = (R)p.guess[(long long)i * p.guess_ld + L.cell];
           L.gstate = 2;
           L.phase = KR_PH_GUESS;
           if (p.counters) atomicAdd(&p.counters[0], 1ull);
@@ -746,11 +842,11 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 
     if (L.phase == KR_PH_NEWTON) {
       /* residual and Newton matrix M = dR/dy, assembled over J in place */
-      const double h = L.h;
-      double b[KR_N];
+      const R h = (R)L.h;
+      R b[KR_N];
 #pragma unroll
       for (int s = 0; s < KR_S; ++s) b[s] = -(yv[s] - L.yn[s] - h * g[s]);
-      b[KR_S] = -(yv[KR_S] * cv - L.eps_n - h * g[KR_S]);
+      b[KR_S] = -(yv[KR_S] * cv - (R)L.eps_n - h * g[KR_S]);
       if (ph == KR_PH_GUESS && L.gstate == 2) {
         /* residual gate: keep the learned starting point only if its BE
          * residual is smaller (weighted max norm) than the plain start's,
@@ -758,13 +854,13 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
         double rg = 0.0, rp = 0.0;
 #pragma unroll
         for (int s = 0; s < KR_S; ++s) {
-          const double w = kr_rcp(L.atol + p.rtol * fabs(L.yn[s]));
-          rg = fmax(rg, fabs(b[s]) * w);
-          rp = fmax(rp, h * fabs(L.gn[s]) * w);
+          const double w = kr_rcp(L.atol + p.rtol * fabs((double)L.yn[s]));
+          rg = fmax(rg, (double)fabs(b[s]) * w);
+          rp = fmax(rp, L.h * (double)fabs(L.gn[s]) * w);
         }
         const double wE = kr_rcp(p.rtol * L.eps_n);
-        rg = fmax(rg, fabs(b[KR_S]) * wE);
-        rp = fmax(rp, h * fabs(L.gn[KR_S] * L.eps_n / L.yn[KR_S]) * wE);
+        rg = fmax(rg, (double)fabs(b[KR_S]) * wE);
+        rp = fmax(rp, L.h * fabs((double)L.gn[KR_S] * L.eps_n / (double)L.yn[KR_S]) * wE);
         if (!(rg < rp)) {
           kr_newton_failed(p, L);   /* falls back to the plain start */
           goto kr_trip_end;
@@ -773,15 +869,19 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
       for (int s = 0; s < KR_S; ++s)
 #pragma unroll
-        for (int m = 0; m < KR_N; ++m) J[s][m] = (s == m ? 1.0 : 0.0) - h * J[s][m];
+        for (int m = 0; m < KR_N; ++m) J[s][m] = (s == m ? R(1) : R(0)) - h * J[s][m];
 #pragma unroll
-      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = kr_cv[m] * yv[KR_S] - h * J[KR_S][m];
+      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = R(kr_cv[m]) * yv[KR_S] - h * J[KR_S][m];
       J[KR_S][KR_S] = cv - h * J[KR_S][KR_S];
       L.iters++;
 
       bool ok;
-      if (!MIXED) {
+      if constexpr (!MIXED) {
         ok = kr_lu_solve(J, b, swaps);
+        /* FP32 modes: the update lands on the input's conserved totals */
+        if constexpr (sizeof(R) == 4) {
+          if (ok) kr_project_to(yv, L.e0, (R)L.atol, b);
+        }
       } else {
         /* FP32 LU of the row-equilibrated matrix; FP64 residual and
          * iterative refinement against the FP64 matrix; FP64 projection */
@@ -871,18 +971,22 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       } else {
         bool fin = true;
         double norm = 0.0;
+        bool flat = true;   /* FP32: the update is within 4 ulps of the iterate */
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) {
-          const double yi = L.y[i] + b[i];
+          const R yo = L.y[i];
+          const R yi = yo + b[i];
           L.y[i] = yi;
-          fin = fin && kr_finite(b[i]) && kr_finite(yi);
-          const double e = fabs(b[i]) * kr_rcp_w(kr_weight(p, L, i, yi));
+          fin = fin && kr_finite((double)b[i]) && kr_finite((double)yi);
+          const double e = (double)fabs(b[i]) * kr_rcp_w(kr_weight(p, L, i, (double)yi));
           norm = e > norm ? e : norm;
+          if (sizeof(R) == 4)
+            flat = flat && (double)fabs(b[i]) <= 4.0 * 0x1p-23 * (double)fabs(yo) + (i < KR_S ? L.atol : 0.0);
         }
-        if (!fin || !(L.y[KR_S] > 0.0)) {
+        if (!fin || !(L.y[KR_S] > R(0))) {
           kr_newton_failed(p, L);
         } else {
-          if (norm <= p.newton_tol) {
+          if (norm <= p.newton_tol || (sizeof(R) == 4 && flat)) {
             L.phase = KR_PH_CHECK;
             L.gstate = 0;
           } else {
@@ -995,11 +1099,19 @@ extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_timescale(K
 }
 
 extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp64(KrParams p) {
-  kr_integrate_body<false>(p);
+  kr_integrate_body<KR_P_FP64>(p);
 }
 
 extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_fp32lu(KrParams p) {
-  kr_integrate_body<true>(p);
+  kr_integrate_body<KR_P_FP32LU>(p);
+}
+
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_single(KrParams p) {
+  kr_integrate_body<KR_P_SINGLE>(p);
+}
+
+extern "C" __global__ void __launch_bounds__(64, KR_WAVES_PER_EU) kr_integrate_mixed(KrParams p) {
+  kr_integrate_body<KR_P_MIXED>(p);
 }
 
 extern "C" __global__ void kr_reset_counter(unsigned long long *c) {

@@ -125,8 +125,9 @@ struct kr_network {
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
+  hipFunction_t f_single = nullptr, f_mixed = nullptr;   /* lane layout only */
   hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr, f_adv = nullptr;
-  int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0;
+  int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0, occ_single = 0, occ_mixed = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
   bool wide = false;            /* one wavefront per cell */
   OrderBufs ord;
@@ -249,7 +250,7 @@ static SideCode side_code(const std::string &k, const int *slots) {
 static std::string coef(int nu) {
   if (nu == 1) return "";
   if (nu == -1) return "-";
-  return std::to_string(nu) + ".0 * ";
+  return "R(" + std::to_string(nu) + ") * ";
 }
 
 static std::string network_tables(const kr_network *n);
@@ -459,15 +460,18 @@ static std::string network_tables(const kr_network *n) {
 /* k = A T^b exp(-C/T) as 2^(log2 A + b log2 T - C log2(e) / T) (kr_math.h):
  * the generated code holds log2 A and C log2(e), rounded once from extended
  * precision; l2T and iT are the evaluation point's log2 T and 1/T. */
+/* A constant of the working precision R of the generated code. */
+static std::string lit(double v) { return "R(" + hexd(v) + ")"; }
+
 static std::string arrhenius_code(const double *abc) {
   const long double log2e = 1.4426950408889634073599246810018921L;
   const double a2 = (double)log2l((long double)abc[0]);
   const double b = abc[1];
   const double c2 = (double)((long double)abc[2] * log2e);
-  if (b == 0.0 && c2 == 0.0) return hexd(abc[0]);
-  std::string x = hexd(a2);
-  if (b != 0.0) x = "fma(" + hexd(b) + ", l2T, " + x + ")";
-  if (c2 != 0.0) x = "fma(" + hexd(-c2) + ", iT, " + x + ")";
+  if (b == 0.0 && c2 == 0.0) return lit(abc[0]);
+  std::string x = lit(a2);
+  if (b != 0.0) x = "fma(" + lit(b) + ", l2T, " + x + ")";
+  if (c2 != 0.0) x = "fma(" + lit(-c2) + ", iT, " + x + ")";
   return "kr_exp2(" + x + ")";
 }
 
@@ -479,12 +483,17 @@ static std::string generate_network(const kr_network *n) {
        " conserved rows, " + std::to_string(n->R) + " reactions */\n";
   o += network_tables(n);
 
-  /* rates and analytic Jacobian, one block per reaction */
-  o += "__device__ __forceinline__ void kr_eval(const double (&y)[KR_S + 1], double (&g)[KR_S + 1],\n"
-       "                                        double (&J)[KR_S + 1][KR_S + 1]) {\n"
-       "#pragma unroll\n  for (int i = 0; i <= KR_S; ++i) {\n    g[i] = 0.0;\n"
-       "#pragma unroll\n    for (int j = 0; j <= KR_S; ++j) J[i][j] = 0.0;\n  }\n"
-       "  const double T = y[KR_S];\n  const double l2T = kr_log2(T);\n  const double iT = 1.0 / T;\n";
+  /* rates and analytic Jacobian, one block per reaction, in the working
+   * precision R (FP64; FP32 for the single- and mixed-precision modes, whose
+   * exp2 and log2 are the hardware's) */
+  o += "__device__ __forceinline__ float kr_exp2(float x) { return __builtin_amdgcn_exp2f(x); }\n"
+       "__device__ __forceinline__ float kr_log2(float x) { return __builtin_amdgcn_logf(x); }\n";
+  o += "template <typename R>\n"
+       "__device__ __forceinline__ void kr_eval(const R (&y)[KR_S + 1], R (&g)[KR_S + 1],\n"
+       "                                        R (&J)[KR_S + 1][KR_S + 1]) {\n"
+       "#pragma unroll\n  for (int i = 0; i <= KR_S; ++i) {\n    g[i] = R(0);\n"
+       "#pragma unroll\n    for (int j = 0; j <= KR_S; ++j) J[i][j] = R(0);\n  }\n"
+       "  const R T = y[KR_S];\n  const R l2T = kr_log2(T);\n  const R iT = R(1) / T;\n";
   const std::string ST = std::to_string(S);
   for (int r = 0; r < n->R; ++r) {
     const double *pf = &n->par[6 * (size_t)r], *pr = pf + 3;
@@ -503,11 +512,11 @@ static std::string generate_network(const kr_network *n) {
       const double *pp = dir ? pr : pf;
       if (pp[0] == 0.0) continue;
       const std::string k = dir ? "kr" : "kf";
-      o += "    const double " + k + " = " + arrhenius_code(pp) + ";\n";
+      o += "    const R " + k + " = " + arrhenius_code(pp) + ";\n";
       SideCode c = side_code(k, dir ? &n->prod[3 * r] : &n->reac[3 * r]);
       const std::string q = dir ? "qr" : "qf";
-      o += "    const double " + q + " = " + c.q + ";\n";
-      o += "    const double " + q + "T = " + q + " * (" + hexd(pp[1]) + " + " + hexd(pp[2]) + " * iT) * iT;\n";
+      o += "    const R " + q + " = " + c.q + ";\n";
+      o += "    const R " + q + "T = " + q + " * (" + lit(pp[1]) + " + " + lit(pp[2]) + " * iT) * iT;\n";
       w += (dir ? " - " : (w.empty() ? "" : " + ")) + q;
       dwdT += (dir ? " - " : (dwdT.empty() ? "" : " + ")) + q + "T";
       for (auto &t : c.dq) {
@@ -518,11 +527,11 @@ static std::string generate_network(const kr_network *n) {
       }
     }
     if (w.empty()) { o += "  }\n"; continue; }
-    if (w[0] == ' ') w = "0.0" + w;
-    if (dwdT[0] == ' ') dwdT = "0.0" + dwdT;
-    o += "    const double w = " + w + ";\n";
-    o += "    const double wT = " + dwdT + ";\n";
-    for (auto &t : dw) o += "    const double w" + std::to_string(t.first) + " = 0.0" + t.second + ";\n";
+    if (w[0] == ' ') w = "R(0)" + w;
+    if (dwdT[0] == ' ') dwdT = "R(0)" + dwdT;
+    o += "    const R w = " + w + ";\n";
+    o += "    const R wT = " + dwdT + ";\n";
+    for (auto &t : dw) o += "    const R w" + std::to_string(t.first) + " = R(0)" + t.second + ";\n";
     for (int s = 0; s < S; ++s) {
       if (!nu[s]) continue;
       const std::string c = coef(nu[s]), ss = std::to_string(s);
@@ -531,7 +540,7 @@ static std::string generate_network(const kr_network *n) {
       o += "    J[" + ss + "][" + ST + "] += " + c + "wT;\n";
     }
     if (qhat != 0.0) {
-      const std::string qh = hexd(qhat);
+      const std::string qh = lit(qhat);
       o += "    g[" + ST + "] += " + qh + " * w;\n";
       for (auto &t : dw) o += "    J[" + ST + "][" + std::to_string(t.first) + "] += " + qh + " * w" + std::to_string(t.first) + ";\n";
       o += "    J[" + ST + "][" + ST + "] += " + qh + " * wT;\n";
@@ -724,6 +733,12 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
     CREATE_TRY(hipModuleGetFunction(&n->f_adv, n->module, "kr_advect"));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
+    if (!n->wide) {
+      CREATE_TRY(hipModuleGetFunction(&n->f_single, n->module, "kr_integrate_single"));
+      CREATE_TRY(hipModuleGetFunction(&n->f_mixed, n->module, "kr_integrate_mixed"));
+      CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_single, n->f_single, 64, 0));
+      CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_mixed, n->f_mixed, 64, 0));
+    }
     CREATE_TRY(hipMalloc(&n->d_counter, 2 * sizeof(unsigned long long)));
     CREATE_TRY(hipMalloc(&n->d_max, sizeof(unsigned long long)));
     CREATE_TRY(hipMalloc(&n->d_totals, 16 * sizeof(unsigned long long)));
@@ -954,11 +969,13 @@ static int integrate_impl(const kr_network *net, int64_t n_cells, double *states
   kr_options o;
   kr_default_options(&o);
   if (opt) o = *opt;
-  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+  if ((o.precision < KR_FP64 || o.precision > KR_MIXED) ||
       (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
       o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
       !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
     return fail(KR_EINVAL, "bad options");
+  if (o.precision >= KR_SINGLE && net->wide)
+    return fail(KR_EINVAL, "the single- and mixed-precision modes need the lane layout");
   if (n_cells == 0) return KR_OK;
   if (!states || !T) return fail(KR_EINVAL, "null state arrays");
   if (!dt && !(dt_scalar >= 0.0 && std::isfinite(dt_scalar))) return fail(KR_EINVAL, "bad dt_scalar");
@@ -1006,8 +1023,10 @@ static int integrate_impl(const kr_network *net, int64_t n_cells, double *states
   unsigned long long *cnt = ws.counter;
   void *rargs[] = {&cnt};
   HIP_TRY(hipModuleLaunchKernel(net->f_reset, 1, 1, 1, 64, 1, 1, 0, st, rargs, nullptr));
-  hipFunction_t f = o.precision == KR_FP64 ? net->f_fp64 : net->f_fp32;
-  const int occ = o.precision == KR_FP64 ? net->occ_fp64 : net->occ_fp32;
+  const hipFunction_t fs[4] = {net->f_fp64, net->f_fp32, net->f_single, net->f_mixed};
+  const int occs[4] = {net->occ_fp64, net->occ_fp32, net->occ_single, net->occ_mixed};
+  hipFunction_t f = fs[o.precision];
+  const int occ = occs[o.precision];
   long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
   const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
   if (blocks > need) blocks = need;
@@ -1220,11 +1239,15 @@ extern "C" int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_c
     HIP_TRY(hipSetDevice(net->device));
     KrAdvParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho, flux, xc, xf,
                       base, dt, base ? alpha : 0.0, beta, mode};
-    const int chunk = net->S <= 16 ? 256 : 64;
-    const long long blocks = std::min<long long>(n_lines * ((n_cells + chunk - 1) / chunk),
-                                                 (long long)net->cu_count * 16);
+    /* up to 16 species: 60 cells per wavefront, 4 independent wavefronts
+     * per workgroup; more: one LDS-staged chunk of 64 cells per workgroup
+     * (the kernel's KR_ADV_REG / KR_ADV_CHUNK) */
+    const bool reg = net->S <= 16;
+    const int per = reg ? 60 : 64, threads = reg ? 256 : 64;
+    const long long units = n_lines * ((n_cells + per - 1) / per);
+    const long long blocks = std::min<long long>(reg ? (units + 3) / 4 : units, (long long)net->cu_count * 64);
     void *args[] = {&p};
-    HIP_TRY(hipModuleLaunchKernel(net->f_adv, (unsigned)blocks, 1, 1, chunk, 1, 1, 0, (hipStream_t)stream, args,
+    HIP_TRY(hipModuleLaunchKernel(net->f_adv, (unsigned)blocks, 1, 1, threads, 1, 1, 0, (hipStream_t)stream, args,
                                   nullptr));
     return KR_OK;
   } KR_CATCH
@@ -1375,7 +1398,8 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
       for (size_t j = 0; j < mem.size(); ++j) {
         const int k = mem[j];
         s += "      case " + std::to_string(j) + ": if (" + std::to_string(k) + " < m.n_nets) kr_m" + std::to_string(k) +
-             (nets[k]->wide ? "::kr_wintegrate<" : "::kr_integrate_body<") + (mixed ? "true" : "false") +
+             (nets[k]->wide ? (mixed ? "::kr_wintegrate<true" : "::kr_wintegrate<false")
+                            : (mixed ? "::kr_integrate_body<1" : "::kr_integrate_body<0")) +
              ">(m.net[" + std::to_string(k) + "]); break;\n";
       }
       s += "      default: break;\n    }\n  }\n}\n";
@@ -1525,7 +1549,7 @@ static int fill_params(const kr_network *net, const kr_batch &b, double rtol, co
 }
 
 static int validate_options(const kr_options &o) {
-  if ((o.precision != KR_FP64 && o.precision != KR_FP32LU_REFINE) ||
+  if ((o.precision < KR_FP64 || o.precision > KR_MIXED) ||
       (o.mode != KR_ADAPTIVE && o.mode != KR_FIXED_STEP) || (o.mode == KR_FIXED_STEP && o.n_fixed < 1) ||
       o.max_newton < 1 || o.max_substeps < 1 || !(o.floor >= 0.0) || !(o.newton_tol > 0.0) ||
       !(o.rho_floor >= 0.0) || (o.order != KR_ORDER_INPUT && o.order != KR_ORDER_WORK))
@@ -1544,6 +1568,8 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
     int rc = validate_options(o);
     if (rc) return rc;
     if (o.guess) return fail(KR_EINVAL, "a learned guess is not supported in multi-network launches");
+    if (o.precision >= KR_SINGLE)
+      return fail(KR_EINVAL, "the single- and mixed-precision modes are not supported in multi-network launches");
     if (o.h_hint || o.h_log || o.h_log_n)
       return fail(KR_EINVAL, "per-cell step hints and substep logs are not supported in multi-network launches");
     KrMultiHost h{};

@@ -71,7 +71,7 @@ def test_generated_code_is_straight_line():
     assert "#define KR_S 9" in src and "kr_eval" in src
     # one block per reaction, only compile-time indices into the matrix
     assert src.count("/* reaction ") == 24
-    body = src.split("const double T = y[KR_S];")[1].split("kr_device.h")[0]
+    body = src.split("const R T = y[KR_S];")[1].split("kr_device.h")[0]
     assert re.search(r"(J|g|y)\[[a-zA-Z_]", body) is None
 
 
@@ -89,7 +89,7 @@ def test_derived_reverse_parameters_match_oracle(oracle_lib):
     src = kr.network_check(desc)
     par = oracle_lib.OracleNet(desc).arrhenius()
     # k = 2^(log2 A + b log2 T - C log2(e) / T): literals -C log2(e), b, log2 A
-    lits = re.findall(r"const double kr = kr_exp2\(fma\((\S+), iT, fma\((\S+), l2T, (\S+)\)\)\);", src)
+    lits = re.findall(r"const R kr = kr_exp2\(fma\(R\((\S+)\), iT, fma\(R\((\S+)\), l2T, R\((\S+)\)\)\)\);", src)
     assert len(lits) == desc.n_reactions
     for r, (mc2, b, a2) in enumerate(lits):
         # log2 A is rounded once: A carries ~|log2 A| ulp of relative error
