@@ -62,6 +62,10 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                      C.c_double, C.POINTER(C.c_int)]
         L.kro_net_destroy.argtypes = [C.c_void_p]
+        L.kro_net_set_heat_capacity.argtypes = [C.c_void_p, C.c_double, C.c_void_p]
+        L.kro_net_set_tables.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                         C.c_void_p, C.c_void_p]
+        L.kro_species_thermo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
         for name in ("kro_arrhenius",):
             getattr(L, name).argtypes = [C.c_void_p, C.c_void_p]
         L.kro_rate_coeffs.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
@@ -129,6 +133,20 @@ class OracleNet:
                                   float(desc.p_ref), float(desc.T_min), float(desc.T_max), C.byref(err))
         if not self.h:
             raise ValueError(f"oracle rejected the network (code {err.value})")
+        cvp = getattr(desc, "cv_poly", None)
+        if cvp is not None:
+            cvp = np.ascontiguousarray(cvp, np.float64).reshape(self.S, 2, 5)
+            self._keep.append(cvp)
+            if L.kro_net_set_heat_capacity(self.h, float(desc.T_mid), cvp.ctypes.data):
+                raise ValueError("oracle rejected the heat-capacity polynomials")
+        tab_of = getattr(desc, "tab_of", None)
+        if tab_of is not None:
+            tab_of = np.ascontiguousarray(tab_of, np.int32)
+            tab = np.ascontiguousarray(desc.tab_log2k, np.float64)
+            self._keep += [tab_of, tab]
+            if L.kro_net_set_tables(self.h, int(tab.shape[0]), int(tab.shape[1]), float(desc.tab_log2T0),
+                                    float(desc.tab_dlog2T), tab_of.ctypes.data, tab.ctypes.data):
+                raise ValueError("oracle rejected the rate tables")
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -140,6 +158,12 @@ class OracleNet:
         out = np.zeros((self.R, 2, 3))
         lib().kro_arrhenius(self.h, out.ctypes.data)
         return out
+
+    def species_thermo(self, T: float):
+        """(e_s(T), c_V,s(T)) per species, k_B units."""
+        e, c = np.zeros(self.S), np.zeros(self.S)
+        lib().kro_species_thermo(self.h, float(T), e.ctypes.data, c.ctypes.data)
+        return e, c
 
     def rate_coeffs(self, T: float):
         kf, kr = np.zeros(self.R), np.zeros(self.R)

@@ -55,6 +55,16 @@ struct kro_net {
   double *par;       /* [R][2][3] (A, b, E) forward / reverse */
   double *qhat;      /* [R] heat released per forward event (K) */
   double T_min, T_max;
+  int explicit_rev;  /* reverse parameters given, not by detailed balance */
+  /* temperature-dependent heat capacities (cvp NULL: constant cv) */
+  double *cvp;       /* [S][2][5] c_V/k_B = sum_k a_k T^k, T < T_mid / >= */
+  double *econ;      /* [S] constant of the upper piece of e_s(T) */
+  double T_mid;
+  /* tabulated rate factors (tab_of NULL: none) */
+  int n_tab, n_nodes;
+  int32_t *tab_of;   /* [R] table of reaction r, or -1 */
+  double *tab;       /* [n_tab][n_nodes] log2 of the factor at the nodes */
+  double tab_x0, tab_dx;   /* node i at log2 T = tab_x0 + i tab_dx */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -119,6 +129,7 @@ kro_net *kro_net_create(int S, int n_rows, int n_elem, const int32_t *comp,
     n->qhat[r] = -dH;
     double *pf = n->par + 6 * r, *pr = pf + 3;
     pf[0] = arr_f[3 * r]; pf[1] = arr_f[3 * r + 1]; pf[2] = arr_f[3 * r + 2];
+    n->explicit_rev = arr_r != NULL;
     if (arr_r) {
       pr[0] = arr_r[3 * r]; pr[1] = arr_r[3 * r + 1]; pr[2] = arr_r[3 * r + 2];
     } else {
@@ -142,12 +153,92 @@ kro_net *kro_net_create(int S, int n_rows, int n_elem, const int32_t *comp,
 void kro_net_destroy(kro_net *n) {
   if (!n) return;
   free(n->comp); free(n->res); free(n->cv); free(n->h); free(n->s);
+  free(n->cvp); free(n->econ); free(n->tab_of); free(n->tab);
   free(n->reac); free(n->prod); free(n->nu); free(n->par); free(n->qhat);
   free(n);
 }
 
 void kro_arrhenius(const kro_net *n, double *out) {
   memcpy(out, n->par, sizeof(double) * (size_t)(6 * n->R));
+}
+
+/* e_s(T) = integral from 0 to T of c_V,s: on the lower piece the integral of
+ * its polynomial, on the upper piece the integral of that one plus the
+ * constant that makes e_s continuous at T_mid. */
+static double poly_energy(const double *a, double T) {
+  double e = 0.0, Tk = T;
+  for (int k = 0; k < 5; ++k) {
+    e += a[k] * Tk / (k + 1);
+    Tk *= T;
+  }
+  return e;
+}
+
+int kro_net_set_heat_capacity(kro_net *n, double T_mid, const double *cv_poly) {
+  if (!(T_mid > 0.0) || !isfinite(T_mid) || !cv_poly) return 1;
+  const int S = n->S;
+  for (int i = 0; i < 10 * S; ++i)
+    if (!isfinite(cv_poly[i])) return 1;
+  free(n->cvp); free(n->econ);
+  n->cvp = (double *)malloc(sizeof(double) * 10 * (size_t)S);
+  n->econ = (double *)malloc(sizeof(double) * (size_t)S);
+  memcpy(n->cvp, cv_poly, sizeof(double) * 10 * (size_t)S);
+  n->T_mid = T_mid;
+  for (int s = 0; s < S; ++s)
+    n->econ[s] = poly_energy(n->cvp + 10 * s, T_mid) - poly_energy(n->cvp + 10 * s + 5, T_mid);
+  return 0;
+}
+
+int kro_net_set_tables(kro_net *n, int n_tab, int n_nodes, double log2T0, double dlog2T,
+                       const int32_t *tab_of, const double *tab) {
+  if (n_tab < 1 || n_nodes < 2 || !(dlog2T > 0.0) || !isfinite(log2T0) || !tab_of || !tab) return 1;
+  for (int r = 0; r < n->R; ++r)
+    if (tab_of[r] < -1 || tab_of[r] >= n_tab) return 1;
+  for (long i = 0; i < (long)n_tab * n_nodes; ++i)
+    if (!isfinite(tab[i])) return 1;
+  free(n->tab_of); free(n->tab);
+  n->tab_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n->R + 1));
+  n->tab = (double *)malloc(sizeof(double) * (size_t)n_tab * n_nodes);
+  memcpy(n->tab_of, tab_of, sizeof(int32_t) * (size_t)n->R);
+  memcpy(n->tab, tab, sizeof(double) * (size_t)n_tab * n_nodes);
+  n->n_tab = n_tab; n->n_nodes = n_nodes;
+  n->tab_x0 = log2T0; n->tab_dx = dlog2T;
+  return 0;
+}
+
+/* c_V,s(T) and e_s(T) of one species (constant cv: c_s and c_s T). */
+static void species_thermo(const kro_net *n, int s, double T, double *e, double *c) {
+  if (!n->cvp) {
+    *c = n->cv[s];
+    *e = n->cv[s] * T;
+    return;
+  }
+  const int upper = T >= n->T_mid;
+  const double *a = n->cvp + 10 * s + 5 * upper;
+  double cc = 0.0, Tk = 1.0;
+  for (int k = 0; k < 5; ++k) {
+    cc += a[k] * Tk;
+    Tk *= T;
+  }
+  *c = cc;
+  *e = poly_energy(a, T) + (upper ? n->econ[s] : 0.0);
+}
+
+void kro_species_thermo(const kro_net *n, double T, double *e, double *c) {
+  for (int s = 0; s < n->S; ++s) species_thermo(n, s, T, &e[s], &c[s]);
+}
+
+/* Tabulated factor tau(T) of table t: log2 tau linear in log2 T between
+ * nodes (the end segments extended); *slope = d ln tau / d ln T. */
+static double table_factor(const kro_net *n, int t, double T, double *slope) {
+  const double *L = n->tab + (size_t)t * n->n_nodes;
+  const double u = (log2(T) - n->tab_x0) / n->tab_dx;
+  int i = (int)floor(u);
+  if (i < 0) i = 0;
+  if (i > n->n_nodes - 2) i = n->n_nodes - 2;
+  const double f = u - i;
+  *slope = (L[i + 1] - L[i]) / n->tab_dx;
+  return exp2(L[i] + f * (L[i + 1] - L[i]));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -159,10 +250,28 @@ static double arrhenius(const double *p, double T) {
   return p[0] * exp(p[1] * log(T) - p[2] / T);
 }
 
+/* Rate coefficient of direction dir (0 forward, 1 reverse) of reaction r
+ * and, if dk is given, its derivative in T: the Arrhenius form, times the
+ * reaction's tabulated factor (both directions with detailed-balance reverse
+ * rates, so that the equilibrium constant is untouched; the forward one only
+ * when the reverse parameters were given). */
+static double rate_coeff(const kro_net *n, int r, int dir, double T, double *dk) {
+  const double *p = n->par + 6 * r + 3 * dir;
+  double k = arrhenius(p, T);
+  double tl = p[1] + p[2] / T;          /* T dk/dT / k */
+  if (n->tab_of && n->tab_of[r] >= 0 && (dir == 0 || !n->explicit_rev)) {
+    double slope;
+    k *= table_factor(n, n->tab_of[r], T, &slope);
+    tl += slope;
+  }
+  if (dk) *dk = k * tl / T;
+  return k;
+}
+
 void kro_rate_coeffs(const kro_net *n, double T, double *kf, double *kr) {
   for (int r = 0; r < n->R; ++r) {
-    kf[r] = arrhenius(n->par + 6 * r, T);
-    kr[r] = arrhenius(n->par + 6 * r + 3, T);
+    kf[r] = rate_coeff(n, r, 0, T, NULL);
+    kr[r] = rate_coeff(n, r, 1, T, NULL);
   }
 }
 
@@ -193,7 +302,7 @@ void kro_rhs(const kro_net *n, const double *y, double *f, double *Q) {
   for (int s = 0; s < S; ++s) f[s] = 0.0;
   double q = 0.0;
   for (int r = 0; r < n->R; ++r) {
-    double kf = arrhenius(n->par + 6 * r, T), kr = arrhenius(n->par + 6 * r + 3, T);
+    double kf = rate_coeff(n, r, 0, T, NULL), kr = rate_coeff(n, r, 1, T, NULL);
     double w = side_rate(kf, n->reac + 3 * r, y) - side_rate(kr, n->prod + 3 * r, y);
     for (int s = 0; s < S; ++s) f[s] += n->nu[r * S + s] * w;
     q += n->qhat[r] * w;
@@ -206,12 +315,11 @@ void kro_jacobian(const kro_net *n, const double *y, double *J) {
   const double T = y[S];
   memset(J, 0, sizeof(double) * (size_t)(N * N));
   for (int r = 0; r < n->R; ++r) {
-    const double *pf = n->par + 6 * r, *pr = pf + 3;
-    double kf = arrhenius(pf, T), kr = arrhenius(pr, T);
+    double dkf, dkr;
+    double kf = rate_coeff(n, r, 0, T, &dkf), kr = rate_coeff(n, r, 1, T, &dkr);
     const int32_t *rc = n->reac + 3 * r, *pd = n->prod + 3 * r;
-    double qf = side_rate(kf, rc, y), qr = side_rate(kr, pd, y);
-    /* d k/dT = k (b + E/T) / T for each direction */
-    double dwdT = qf * (pf[1] + pf[2] / T) / T - qr * (pr[1] + pr[2] / T) / T;
+    /* d q/dT = (d k/dT) times the same product of abundances */
+    double dwdT = side_rate(dkf, rc, y) - side_rate(dkr, pd, y);
     double dwdn[KRO_MAXN];
     for (int m = 0; m < S; ++m)
       dwdn[m] = side_rate_dn(kf, rc, y, m) - side_rate_dn(kr, pd, y, m);
@@ -226,10 +334,27 @@ void kro_jacobian(const kro_net *n, const double *y, double *J) {
   }
 }
 
+/* c_V = sum_s n_s c_V,s(T) */
 static double heat_capacity(const kro_net *n, const double *y) {
   double c = 0.0;
-  for (int s = 0; s < n->S; ++s) c += n->cv[s] * y[s];
+  for (int s = 0; s < n->S; ++s) {
+    double es, cs;
+    species_thermo(n, s, y[n->S], &es, &cs);
+    c += cs * y[s];
+  }
   return c;
+}
+
+/* thermal energy eps = sum_s n_s e_s(T) (= T c_V for constant cv) */
+static double thermal_energy(const kro_net *n, const double *y) {
+  if (!n->cvp) return y[n->S] * heat_capacity(n, y);
+  double e = 0.0;
+  for (int s = 0; s < n->S; ++s) {
+    double es, cs;
+    species_thermo(n, s, y[n->S], &es, &cs);
+    e += es * y[s];
+  }
+  return e;
 }
 
 void kro_residual(const kro_net *n, const double *y, const double *yn, double h,
@@ -238,7 +363,7 @@ void kro_residual(const kro_net *n, const double *y, const double *yn, double h,
   double f[KRO_MAXN], Q;
   kro_rhs(n, y, f, &Q);
   for (int s = 0; s < S; ++s) R[s] = y[s] - yn[s] - h * f[s];
-  R[S] = y[S] * heat_capacity(n, y) - yn[S] * heat_capacity(n, yn) - h * Q;
+  R[S] = thermal_energy(n, y) - thermal_energy(n, yn) - h * Q;
 }
 
 void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
@@ -248,8 +373,12 @@ void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
   for (int s = 0; s < S; ++s) {
     for (int m = 0; m < N; ++m) M[s * N + m] = (s == m ? 1.0 : 0.0) - h * J[s * N + m];
   }
-  /* d eps / d n_m = c_m T ; d eps / d T = c_V */
-  for (int m = 0; m < S; ++m) M[S * N + m] = n->cv[m] * y[S] - h * J[S * N + m];
+  /* d eps / d n_m = e_m(T) ; d eps / d T = c_V */
+  for (int m = 0; m < S; ++m) {
+    double em, cm;
+    species_thermo(n, m, y[S], &em, &cm);
+    M[S * N + m] = em - h * J[S * N + m];
+  }
   M[S * N + S] = heat_capacity(n, y) - h * J[S * N + S];
 }
 

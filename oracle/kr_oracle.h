@@ -10,7 +10,8 @@
  * post-processing and retry, Algorithm algo:lu-decomp for the LU):
  * backward-Euler substeps solved by Newton iteration on the unknowns
  * y = (n_1..n_S, T), with mass-action Arrhenius rates, detailed-balance
- * reverse rates and an energy equation written in eps = T * sum_s c_s n_s.
+ * reverse rates, optional tabulated rate factors, and an energy equation
+ * written in eps = sum_s n_s e_s(T) (T sum_s c_s n_s for constant c_s).
  *
  * Conventions: cgs; energies divided by k_B (so in K); row-major matrices.
  */
@@ -34,6 +35,24 @@ kro_net *kro_net_create(int S, int n_rows, int n_elem, const int32_t *comp,
                         const double *arr_f, const double *arr_r,
                         double p_ref, double T_min, double T_max, int *err);
 void kro_net_destroy(kro_net *net);
+
+/* Optional temperature-dependent heat capacities (paper Sec. 4.2: c_V as
+ * NASA-style piecewise polynomials in T): cv_poly[S][2][5] holds, per
+ * species, c_V/k_B = sum_k a_k T^k for T < T_mid and for T >= T_mid.  The
+ * thermal energy per particle is e_s(T) = its integral from 0 (upper piece
+ * shifted to be continuous at T_mid) and the energy equation is written in
+ * eps = sum_s n_s e_s(T).  Returns 0, or 1 for invalid input. */
+int kro_net_set_heat_capacity(kro_net *net, double T_mid, const double *cv_poly);
+/* Optional tabulated rate factors (paper Sec. 2.2.1, third rate type): the
+ * coefficient of reaction r with tab_of[r] = t >= 0 is its Arrhenius form
+ * times tau_t(T), log2 tau_t linear in log2 T between the nodes
+ * log2 T = log2T0 + i dlog2T (values tab[t][i], end segments extended); with
+ * detailed-balance reverse rates the reverse coefficient carries the same
+ * factor.  Returns 0, or 1 for invalid input. */
+int kro_net_set_tables(kro_net *net, int n_tab, int n_nodes, double log2T0, double dlog2T,
+                       const int32_t *tab_of, const double *tab);
+/* e_s(T) and c_V,s(T) of every species (k_B units). */
+void kro_species_thermo(const kro_net *net, double T, double *e, double *c);
 
 /* Arrhenius parameters actually used: out[r][dir][3] = (A, b, E), dir 0 fwd,
  * 1 reverse (derived by detailed balance unless given explicitly). */

@@ -27,6 +27,13 @@ Conventions (cgs, energies divided by k_B so they are in K):
                          density p_ref / (k_B T)), from which detailed balance
                          fixes the reverse rate.
   * cv                   per-particle heat capacity at constant volume [k_B].
+  * cv_poly, T_mid       optional temperature-dependent heat capacities:
+                         cv_poly[s][piece][k], c_V/k_B = sum_k a_k T^k on
+                         T < T_mid (piece 0) and T >= T_mid (piece 1).
+  * tab_of, tab_log2k,   optional tabulated rate factors: reaction r with
+    tab_log2T0,          tab_of[r] = t >= 0 has its coefficient multiplied by
+    tab_dlog2T           the factor whose log2 is tab_log2k[t][i] at
+                         log2 T = tab_log2T0 + i tab_dlog2T.
 """
 from __future__ import annotations
 
@@ -64,6 +71,12 @@ class NetworkDesc:
     T_min: float = 1.0
     T_max: float = 1.0e5
     meta: dict = field(default_factory=dict)
+    cv_poly: np.ndarray | None = None        # float64 [S, 2, 5]
+    T_mid: float = 1000.0
+    tab_of: np.ndarray | None = None         # int32 [R]
+    tab_log2k: np.ndarray | None = None      # float64 [n_tables, n_nodes]
+    tab_log2T0: float = 0.0
+    tab_dlog2T: float = 1.0
 
     @property
     def n_species(self) -> int:
@@ -357,6 +370,81 @@ def cells_h_o_n(net: NetworkDesc, n_cells: int, seed_index: int = 1,
     x /= x.sum(axis=0, keepdims=True)
     n = x * ntot[None, :]
     return CellStates(n, T, _rho(net, n), None, dt)
+
+
+def _einstein(T: np.ndarray, thetas: np.ndarray) -> np.ndarray:
+    """Heat capacity [k_B] of harmonic modes with vibrational temperatures
+    thetas at temperatures T (the Einstein function, summed over modes)."""
+    x = thetas[None, :] / T[:, None]
+    q = np.exp(-x)
+    return (x * x * q / (1.0 - q) ** 2).sum(axis=1)
+
+
+def heat_capacity_polys(cv0: np.ndarray, n_modes, rng, T_mid: float = 1000.0,
+                        pieces=((200.0, 1000.0), (1000.0, 6000.0))) -> np.ndarray:
+    """Synthetic NASA-style c_V(T) data (the paper's mechanism data are not
+    available): per species the rigid-rotor value cv0 plus n_modes harmonic
+    vibrational modes with vibrational temperatures ~U[800, 6000] K, fitted
+    by a quartic in T (least squares on 200 points) on each piece.  Returns
+    [S, 2, 5] ascending-power coefficients."""
+    S = len(cv0)
+    out = np.zeros((S, 2, 5))
+    for s in range(S):
+        thetas = rng.uniform(800.0, 6000.0, int(n_modes[s]))
+        for piece, (lo, hi) in enumerate(pieces):
+            T = np.linspace(lo, hi, 200)
+            c = cv0[s] + (_einstein(T, thetas) if thetas.size else 0.0)
+            if thetas.size == 0:
+                out[s, piece, 0] = cv0[s]
+                continue
+            coef = np.polynomial.polynomial.Polynomial.fit(T, c, 4).convert().coef
+            out[s, piece, :coef.size] = coef
+    return out
+
+
+def network_h_o_n_tcv(seed_index: int = 1, n_tables: int = 4, n_nodes: int = 48) -> NetworkDesc:
+    """The 9-species combustion network with temperature-dependent heat
+    capacities (vibrational modes: 3 atoms - 5 linear, 3 atoms - 6 otherwise)
+    and n_tables reactions whose forward coefficient is tabulated: a second,
+    lower-barrier channel A2 T^b2 exp(-E2/T) added to the drawn Arrhenius
+    one and sampled at n_nodes nodes uniform in log2 T over [200, 1e4] K
+    (arr_f of those reactions becomes (1, 0, 0): the table is the whole
+    forward coefficient).  E2 is at least the reaction's energy change, so
+    the detailed-balance reverse of the extra channel has no negative
+    barrier."""
+    net = network_h_o_n(seed_index)
+    rng = rng_for(seed_index, salt=7)
+    atoms = net.composition.sum(axis=0)
+    linear = [True, True, True, True, True, False, False, False, True]
+    modes = [0 if a <= 1 else (3 * a - 5 if l else 3 * a - 6) for a, l in zip(atoms, linear)]
+    net.cv_poly = heat_capacity_polys(net.cv, modes, rng)
+    net.T_mid = 1000.0
+    R = net.n_reactions
+    x0, x1 = np.log2(200.0), np.log2(1.0e4)
+    dx = (x1 - x0) / (n_nodes - 1)
+    Tn = 2.0 ** (x0 + dx * np.arange(n_nodes))
+    nu = net.stoich()
+    picks = np.sort(rng.choice(R, n_tables, replace=False))
+    tab_of = np.full(R, -1, np.int32)
+    tab = np.zeros((n_tables, n_nodes))
+    arr = net.arr_f.copy()
+    for t, r in enumerate(picks):
+        A, b, E = arr[r]
+        dH = float(nu[r] @ net.h_form)
+        A2 = A * 10.0 ** rng.uniform(-2.0, 0.0)
+        b2 = b + rng.uniform(-1.0, 1.0)
+        E2 = max(E * rng.uniform(0.2, 0.6), dH, 0.0)
+        # log of the two-channel sum, in log space (no underflow)
+        tab[t] = np.logaddexp(np.log(A) + b * np.log(Tn) - E / Tn,
+                              np.log(A2) + b2 * np.log(Tn) - E2 / Tn) / np.log(2.0)
+        arr[r] = (1.0, 0.0, 0.0)
+        tab_of[r] = t
+    net.arr_f = arr
+    net.tab_of, net.tab_log2k = tab_of, tab
+    net.tab_log2T0, net.tab_dlog2T = float(x0), float(dx)
+    net.name = "h_o_n_tcv_9sp"
+    net.meta = dict(net.meta, tabulated=picks.tolist())
+    return net
 
 
 def network_astro23(seed_index: int = 2) -> NetworkDesc:
