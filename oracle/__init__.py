@@ -33,7 +33,8 @@ def build(force: bool = True) -> str:
 
 class Extras(C.Structure):
     _fields_ = [("h_hint", C.c_void_p), ("h_log", C.c_void_p), ("h_log_ld", C.c_int64),
-                ("h_log_cap", C.c_int32), ("h_log_n", C.c_void_p), ("post", C.c_void_p)]
+                ("h_log_cap", C.c_int32), ("h_log_n", C.c_void_p), ("post", C.c_void_p),
+                ("photo_flux", C.c_void_p), ("photo_length", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -66,6 +67,10 @@ def lib():
         L.kro_net_set_tables.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
                                          C.c_void_p, C.c_void_p]
         L.kro_species_thermo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
+        L.kro_net_set_photo.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.kro_rhs_photo.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                    C.POINTER(C.c_double)]
+        L.kro_jacobian_photo.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]
         for name in ("kro_arrhenius",):
             getattr(L, name).argtypes = [C.c_void_p, C.c_void_p]
         L.kro_rate_coeffs.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
@@ -147,6 +152,16 @@ class OracleNet:
             if L.kro_net_set_tables(self.h, int(tab.shape[0]), int(tab.shape[1]), float(desc.tab_log2T0),
                                     float(desc.tab_dlog2T), tab_of.ctypes.data, tab.ctypes.data):
                 raise ValueError("oracle rejected the rate tables")
+        sig = getattr(desc, "sigma_abs", None)
+        photo = getattr(desc, "photo", None)
+        qx = getattr(desc, "heat_extra", None)
+        if sig is not None or photo is not None or qx is not None:
+            arrs = [None if sig is None else np.ascontiguousarray(sig, np.float64),
+                    None if photo is None else np.ascontiguousarray(photo, np.int32),
+                    None if qx is None else np.ascontiguousarray(qx, np.float64).reshape(-1, 3)]
+            self._keep += arrs
+            if L.kro_net_set_photo(self.h, *[None if a is None else a.ctypes.data for a in arrs]):
+                raise ValueError("oracle rejected the photoreaction data")
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -242,12 +257,27 @@ class OracleNet:
             raise ValueError("oracle rejected the integrate arguments")
         return n, T, status, stats
 
+    def rhs_photo(self, y, F, L):
+        y = np.ascontiguousarray(y, np.float64)
+        f = np.zeros(self.S)
+        Q = C.c_double(0.0)
+        lib().kro_rhs_photo(self.h, y.ctypes.data, float(F), float(L), f.ctypes.data, C.byref(Q))
+        return f, Q.value
+
+    def jacobian_photo(self, y, F, L):
+        y = np.ascontiguousarray(y, np.float64)
+        J = np.zeros((self.N, self.N))
+        lib().kro_jacobian_photo(self.h, y.ctypes.data, float(F), float(L), J.ctypes.data)
+        return J
+
     def integrate_ex(self, n, T, rho=None, dt=None, dt_scalar=0.0, opts=None, nthreads=0,
-                     h_hint=None, log_cap=0, replay=None, replay_n=None):
+                     h_hint=None, log_cap=0, replay=None, replay_n=None, photo_flux=None,
+                     photo_length=None):
         """kro_integrate_ex on copies of the batch.  h_hint: per-cell first
         substep (in/out copy).  log_cap > 0 records the accepted substep
         lengths (first log_cap per cell).  replay, replay_n: the substep
         lengths [cap, n_cells] and counts to replay (sets mode KRO_REPLAY).
+        photo_flux, photo_length: per-cell radiation field (photoreactions).
         Returns a dict with n, T, status, stats, h_hint, h_log, h_log_n,
         post."""
         o = opts or default_opts()
@@ -275,6 +305,11 @@ class OracleNet:
         ex.h_log_cap = log.shape[0]
         ex.h_log_n = log_n.ctypes.data
         ex.post = post.ctypes.data
+        pf = None if photo_flux is None else np.ascontiguousarray(np.broadcast_to(photo_flux, (ncell,)), np.float64)
+        pl = None if photo_length is None else np.ascontiguousarray(np.broadcast_to(photo_length, (ncell,)),
+                                                                   np.float64)
+        ex.photo_flux = None if pf is None else pf.ctypes.data
+        ex.photo_length = None if pl is None else pl.ctypes.data
         rc = lib().kro_integrate_ex(self.h, ncell, n.ctypes.data, ncell, T.ctypes.data,
                                     None if rho_a is None else rho_a.ctypes.data,
                                     None if dt_a is None else dt_a.ctypes.data, float(dt_scalar),

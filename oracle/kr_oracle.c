@@ -65,7 +65,17 @@ struct kro_net {
   int32_t *tab_of;   /* [R] table of reaction r, or -1 */
   double *tab;       /* [n_tab][n_nodes] log2 of the factor at the nodes */
   double tab_x0, tab_dx;   /* node i at log2 T = tab_x0 + i tab_dx */
+  /* photoreactions and radiative heat terms (NULL: none) */
+  double *sigma;     /* [S] photo-absorption cross-section (cm^2) */
+  int32_t *photo;    /* [R] 1: forward coefficient A F_eff, no reverse */
+  double *qx;        /* [R][3] extra gas heating per event q0 + q1 T + q2 T ln T (K) */
 };
+
+/* The radiation field of one cell: the optically thin photon flux F
+ * (cm^-2 s^-1) and the path length L (cm) of the cell along the rays. */
+typedef struct {
+  double F, L;
+} kro_rad;
 
 /* ------------------------------------------------------------------------ */
 /* network                                                                   */
@@ -154,6 +164,7 @@ void kro_net_destroy(kro_net *n) {
   if (!n) return;
   free(n->comp); free(n->res); free(n->cv); free(n->h); free(n->s);
   free(n->cvp); free(n->econ); free(n->tab_of); free(n->tab);
+  free(n->sigma); free(n->photo); free(n->qx);
   free(n->reac); free(n->prod); free(n->nu); free(n->par); free(n->qhat);
   free(n);
 }
@@ -228,6 +239,78 @@ void kro_species_thermo(const kro_net *n, double T, double *e, double *c) {
   for (int s = 0; s < n->S; ++s) species_thermo(n, s, T, &e[s], &c[s]);
 }
 
+int kro_net_set_photo(kro_net *n, const double *sigma, const int32_t *photo, const double *heat_extra) {
+  const int S = n->S, R = n->R;
+  if (!sigma && !photo && !heat_extra) return 1;
+  if (photo) {
+    if (!sigma) return 1;
+    for (int r = 0; r < R; ++r) {
+      if (photo[r] != 0 && photo[r] != 1) return 1;
+      /* a photoreaction's forward coefficient is A F_eff: no T dependence */
+      if (photo[r] && (n->par[6 * r + 1] != 0.0 || n->par[6 * r + 2] != 0.0)) return 1;
+    }
+  }
+  if (sigma)
+    for (int s = 0; s < S; ++s)
+      if (!(sigma[s] >= 0.0) || !isfinite(sigma[s])) return 1;
+  if (heat_extra)
+    for (int i = 0; i < 3 * R; ++i)
+      if (!isfinite(heat_extra[i])) return 1;
+  free(n->sigma); free(n->photo); free(n->qx);
+  n->sigma = NULL; n->photo = NULL; n->qx = NULL;
+  if (sigma) {
+    n->sigma = (double *)malloc(sizeof(double) * (size_t)S);
+    memcpy(n->sigma, sigma, sizeof(double) * (size_t)S);
+  }
+  if (photo) {
+    n->photo = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R + 1));
+    memcpy(n->photo, photo, sizeof(int32_t) * (size_t)R);
+  }
+  if (heat_extra) {
+    n->qx = (double *)malloc(sizeof(double) * (size_t)(3 * R + 1));
+    memcpy(n->qx, heat_extra, sizeof(double) * (size_t)(3 * R));
+  }
+  return 0;
+}
+
+/* Effective photon flux of a cell whose own absorbers have inverse
+ * absorption length linv (eq. method-rad-equiv-flux, the path average over
+ * the cell): F_eff = F (1 - exp(-tau)) / tau with tau = L linv; *dF =
+ * d F_eff / d linv.  Below tau = 1e-4 the two-term series of both. */
+static double photo_flux(const kro_rad *rad, double linv, double *dF) {
+  *dF = 0.0;
+  if (!rad || rad->F == 0.0) return 0.0;
+  const double tau = rad->L * linv;
+  double g, dg;
+  if (tau < 1e-4) {
+    g = 1.0 - tau / 2.0 + tau * tau / 6.0;
+    dg = -0.5 + tau / 3.0 - tau * tau / 8.0;
+  } else {
+    const double em = expm1(-tau);
+    g = -em / tau;
+    dg = (tau * exp(-tau) + em) / (tau * tau);
+  }
+  *dF = rad->F * rad->L * dg;
+  return rad->F * g;
+}
+
+/* inverse absorption length sum_s sigma_s n_s */
+static double absorption(const kro_net *n, const double *y) {
+  double l = 0.0;
+  if (n->sigma)
+    for (int s = 0; s < n->S; ++s) l += n->sigma[s] * y[s];
+  return l;
+}
+
+/* extra heat per event of reaction r at T and its T derivative */
+static double extra_heat(const kro_net *n, int r, double T, double *dq) {
+  if (!n->qx) { *dq = 0.0; return 0.0; }
+  const double *q = n->qx + 3 * r;
+  const double lnT = log(T);
+  *dq = q[1] + q[2] * (lnT + 1.0);
+  return q[0] + q[1] * T + q[2] * T * lnT;
+}
+
 /* Tabulated factor tau(T) of table t: log2 tau linear in log2 T between
  * nodes (the end segments extended); *slope = d ln tau / d ln T. */
 static double table_factor(const kro_net *n, int t, double T, double *slope) {
@@ -296,42 +379,90 @@ static double side_rate_dn(double k, const int32_t *side, const double *nn, int 
   return d;
 }
 
-void kro_rhs(const kro_net *n, const double *y, double *f, double *Q) {
+/* Coefficients of reaction r's two directions at y: photoreactions take
+ * A F_eff (no reverse), the others rate_coeff; dk receive d/dT. */
+static void coeffs(const kro_net *n, int r, const double *y, double Feff, double *kf, double *kr,
+                   double *dkf, double *dkr) {
+  const double T = y[n->S];
+  if (n->photo && n->photo[r]) {
+    *kf = n->par[6 * r] * Feff;
+    *kr = 0.0;
+    if (dkf) *dkf = 0.0;
+    if (dkr) *dkr = 0.0;
+    return;
+  }
+  *kf = rate_coeff(n, r, 0, T, dkf);
+  *kr = rate_coeff(n, r, 1, T, dkr);
+}
+
+static void rhs_rad(const kro_net *n, const double *y, const kro_rad *rad, double *f, double *Q) {
   const int S = n->S;
   const double T = y[S];
+  double dF;
+  const double Feff = photo_flux(rad, absorption(n, y), &dF);
   for (int s = 0; s < S; ++s) f[s] = 0.0;
   double q = 0.0;
   for (int r = 0; r < n->R; ++r) {
-    double kf = rate_coeff(n, r, 0, T, NULL), kr = rate_coeff(n, r, 1, T, NULL);
+    double kf, kr, dq;
+    coeffs(n, r, y, Feff, &kf, &kr, NULL, NULL);
     double w = side_rate(kf, n->reac + 3 * r, y) - side_rate(kr, n->prod + 3 * r, y);
     for (int s = 0; s < S; ++s) f[s] += n->nu[r * S + s] * w;
-    q += n->qhat[r] * w;
+    q += (n->qhat[r] + extra_heat(n, r, T, &dq)) * w;
   }
   *Q = q;
 }
 
-void kro_jacobian(const kro_net *n, const double *y, double *J) {
+/* The analytic Jacobian.  A photoreaction's coefficient depends on the
+ * abundances through F_eff(lambda^-1): its derivative in n_i is taken as
+ * A (dF_eff / dlambda^-1) sigma_i min{1, n_i sigma_i / lambda^-1} (the
+ * paper's dominant-absorber cutoff, Sec. 2.2.1; 1 where lambda^-1 = 0). */
+static void jacobian_rad(const kro_net *n, const double *y, const kro_rad *rad, double *J) {
   const int S = n->S, N = S + 1;
   const double T = y[S];
   memset(J, 0, sizeof(double) * (size_t)(N * N));
+  double dF;
+  const double linv = absorption(n, y);
+  const double Feff = photo_flux(rad, linv, &dF);
   for (int r = 0; r < n->R; ++r) {
-    double dkf, dkr;
-    double kf = rate_coeff(n, r, 0, T, &dkf), kr = rate_coeff(n, r, 1, T, &dkr);
+    double dkf, dkr, kf, kr;
+    coeffs(n, r, y, Feff, &kf, &kr, &dkf, &dkr);
     const int32_t *rc = n->reac + 3 * r, *pd = n->prod + 3 * r;
     /* d q/dT = (d k/dT) times the same product of abundances */
     double dwdT = side_rate(dkf, rc, y) - side_rate(dkr, pd, y);
     double dwdn[KRO_MAXN];
     for (int m = 0; m < S; ++m)
       dwdn[m] = side_rate_dn(kf, rc, y, m) - side_rate_dn(kr, pd, y, m);
+    if (n->photo && n->photo[r] && dF != 0.0) {
+      const double prod = side_rate(n->par[6 * r] * dF, rc, y);   /* A dF prod n */
+      for (int m = 0; m < S; ++m) {
+        if (n->sigma[m] == 0.0) continue;
+        const double cut = linv > 0.0 ? fmin(1.0, y[m] * n->sigma[m] / linv) : 1.0;
+        dwdn[m] += prod * n->sigma[m] * cut;
+      }
+    }
+    double dq;
+    const double qr = n->qhat[r] + extra_heat(n, r, T, &dq);
+    const double w = side_rate(kf, rc, y) - side_rate(kr, pd, y);
     for (int s = 0; s < S; ++s) {
       int v = n->nu[r * S + s];
       if (!v) continue;
       for (int m = 0; m < S; ++m) J[s * N + m] += v * dwdn[m];
       J[s * N + S] += v * dwdT;
     }
-    for (int m = 0; m < S; ++m) J[S * N + m] += n->qhat[r] * dwdn[m];
-    J[S * N + S] += n->qhat[r] * dwdT;
+    for (int m = 0; m < S; ++m) J[S * N + m] += qr * dwdn[m];
+    J[S * N + S] += qr * dwdT + dq * w;
   }
+}
+
+void kro_rhs(const kro_net *n, const double *y, double *f, double *Q) { rhs_rad(n, y, NULL, f, Q); }
+void kro_jacobian(const kro_net *n, const double *y, double *J) { jacobian_rad(n, y, NULL, J); }
+void kro_rhs_photo(const kro_net *n, const double *y, double F, double L, double *f, double *Q) {
+  const kro_rad rad = {F, L};
+  rhs_rad(n, y, &rad, f, Q);
+}
+void kro_jacobian_photo(const kro_net *n, const double *y, double F, double L, double *J) {
+  const kro_rad rad = {F, L};
+  jacobian_rad(n, y, &rad, J);
 }
 
 /* c_V = sum_s n_s c_V,s(T) */
@@ -357,19 +488,24 @@ static double thermal_energy(const kro_net *n, const double *y) {
   return e;
 }
 
-void kro_residual(const kro_net *n, const double *y, const double *yn, double h,
-                  double *R) {
+static void residual_rad(const kro_net *n, const double *y, const double *yn, double h,
+                         const kro_rad *rad, double *R) {
   const int S = n->S;
   double f[KRO_MAXN], Q;
-  kro_rhs(n, y, f, &Q);
+  rhs_rad(n, y, rad, f, &Q);
   for (int s = 0; s < S; ++s) R[s] = y[s] - yn[s] - h * f[s];
   R[S] = thermal_energy(n, y) - thermal_energy(n, yn) - h * Q;
 }
 
-void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
+void kro_residual(const kro_net *n, const double *y, const double *yn, double h, double *R) {
+  residual_rad(n, y, yn, h, NULL, R);
+}
+
+static void newton_matrix_rad(const kro_net *n, const double *y, double h, const kro_rad *rad,
+                              double *M) {
   const int S = n->S, N = S + 1;
   double J[KRO_MAXN * KRO_MAXN];
-  kro_jacobian(n, y, J);
+  jacobian_rad(n, y, rad, J);
   for (int s = 0; s < S; ++s) {
     for (int m = 0; m < N; ++m) M[s * N + m] = (s == m ? 1.0 : 0.0) - h * J[s * N + m];
   }
@@ -380,6 +516,10 @@ void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
     M[S * N + m] = em - h * J[S * N + m];
   }
   M[S * N + S] = heat_capacity(n, y) - h * J[S * N + S];
+}
+
+void kro_newton_matrix(const kro_net *n, const double *y, double h, double *M) {
+  newton_matrix_rad(n, y, h, NULL, M);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -501,8 +641,9 @@ void kro_default_opts(kro_opts *o) {
  * w_i = atol_i + rtol * max(|yn_i|, |y_i|).  Fails on a singular matrix, a
  * non-finite value, T <= 0, two consecutive growths of the update norm, or
  * no convergence within max_newton iterations. */
-int kro_be_substep(const kro_net *n, const kro_opts *o, const double *yn,
-                   const double *atol, double h, double *y, int32_t *iters) {
+static int be_substep_rad(const kro_net *n, const kro_opts *o, const double *yn,
+                          const double *atol, double h, const kro_rad *rad, double *y,
+                          int32_t *iters) {
   const int N = n->S + 1;
   double R[KRO_MAXN], M[KRO_MAXN * KRO_MAXN], d[KRO_MAXN];
   int32_t p[KRO_MAXN];
@@ -510,8 +651,8 @@ int kro_be_substep(const kro_net *n, const kro_opts *o, const double *yn,
   double prev = INFINITY;
   int grow = 0;
   for (int k = 0; k < o->max_newton; ++k) {
-    kro_residual(n, y, yn, h, R);
-    kro_newton_matrix(n, y, h, M);
+    residual_rad(n, y, yn, h, rad, R);
+    newton_matrix_rad(n, y, h, rad, M);
     *iters += 1;
     if (kro_lu_decompose(N, M, p) != 0) return -1;
     for (int i = 0; i < N; ++i) d[i] = -R[i];
@@ -539,10 +680,15 @@ int kro_be_substep(const kro_net *n, const kro_opts *o, const double *yn,
   return -1;
 }
 
+int kro_be_substep(const kro_net *n, const kro_opts *o, const double *yn,
+                   const double *atol, double h, double *y, int32_t *iters) {
+  return be_substep_rad(n, o, yn, atol, h, NULL, y, iters);
+}
+
 /* g = (f_0..f_{S-1}, Q / c_V): the rate of change of each unknown */
-static void unknown_rates(const kro_net *n, const double *y, double *g) {
+static void unknown_rates(const kro_net *n, const double *y, const kro_rad *rad, double *g) {
   double Q;
-  kro_rhs(n, y, g, &Q);
+  rhs_rad(n, y, rad, g, &Q);
   g[n->S] = Q / heat_capacity(n, y);
 }
 
@@ -577,7 +723,7 @@ static void log_substep(substep_log *lg, double h) {
  * if it is larger.  Fixed mode: n_fixed substeps of dt / n_fixed.  Replay
  * mode: the n_replay given lengths in order, no error control. */
 static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *y0,
-                             const double *atol, double dt, attempt_params ap,
+                             const double *atol, double dt, const kro_rad *rad, attempt_params ap,
                              const double *replay, int64_t replay_ld, int32_t n_replay,
                              double *y_out, int32_t *st, substep_log *lg) {
   const int N = n->S + 1;
@@ -589,7 +735,7 @@ static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *
     const int m = o->mode == KRO_FIXED ? o->n_fixed : n_replay;
     for (int k = 0; k < m; ++k) {
       double h = o->mode == KRO_FIXED ? dt / (double)o->n_fixed : replay[k * replay_ld];
-      if (kro_be_substep(n, o, yn, atol, h, y, &st[1]) != 0) { st[3]++; return -1; }
+      if (be_substep_rad(n, o, yn, atol, h, rad, y, &st[1]) != 0) { st[3]++; return -1; }
       memcpy(yn, y, sizeof(double) * (size_t)N);
       st[0]++;
       log_substep(lg, h);
@@ -597,7 +743,7 @@ static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *
     memcpy(y_out, yn, sizeof(double) * (size_t)N);
     return 0;
   }
-  unknown_rates(n, yn, gn);
+  unknown_rates(n, yn, rad, gn);
   double t = 0.0, h = ap.h0;
   int attempts = 0;
   for (;;) {
@@ -607,12 +753,12 @@ static int integrate_attempt(const kro_net *n, const kro_opts *o, const double *
     if (h >= dt - t) { h = dt - t; final = 1; }
     else if (h < 1e-12 * dt) return -1;
     attempts++;
-    if (kro_be_substep(n, o, yn, atol, h, y, &st[1]) != 0) {
+    if (be_substep_rad(n, o, yn, atol, h, rad, y, &st[1]) != 0) {
       st[3]++;
       h *= 0.25;
       continue;
     }
-    unknown_rates(n, y, g);
+    unknown_rates(n, y, rad, g);
     double err = 0.0;
     for (int i = 0; i < N; ++i) {
       double w = atol[i] + o->rtol * fmax(fabs(yn[i]), fabs(y[i]));
@@ -743,7 +889,7 @@ void kro_postprocess(const kro_net *n, const double *E0, double *nn) {
 double kro_fastest_timescale(const kro_net *n, const double *y) {
   const int S = n->S, N = S + 1;
   double J[KRO_MAXN * KRO_MAXN];
-  kro_jacobian(n, y, J);
+  jacobian_rad(n, y, NULL, J);
   /* the largest self-coupling rate: species diagonal, and the thermal mode
    * d(Q/c_V)/dT ~ (dQ/dT)/c_V */
   double m = 0.0;
@@ -776,6 +922,7 @@ typedef struct {
   int32_t cap;
   int32_t *h_log_n;
   int32_t *post;
+  kro_rad rad;          /* the cell's radiation field (F = 0: none) */
 } cell_extras;
 
 static int32_t integrate_cell(const kro_net *n, const kro_opts *o, double *nn,
@@ -827,7 +974,7 @@ static int32_t integrate_cell(const kro_net *n, const kro_opts *o, double *nn,
   attempt_params ap[2] = {{h0, 0.9, 5.0}, {dt / 100.0, 0.5, 2.0}};
   int32_t status = 2;
   for (int a = 0; a < 2; ++a) {
-    if (integrate_attempt(n, o, y0, atol, dt, ap[a], replay, ex->log_ld, n_replay, y, st, &lg) == 0 &&
+    if (integrate_attempt(n, o, y0, atol, dt, &ex->rad, ap[a], replay, ex->log_ld, n_replay, y, st, &lg) == 0 &&
         cell_ok(n, y0, y, n_nuc)) {
       status = a;
       break;
@@ -868,7 +1015,8 @@ int kro_integrate_ex(const kro_net *n, int64_t n_cells, double *states, int64_t 
     double step = dt ? dt[c] : dt_scalar;
     cell_extras ce = {ex->h_hint ? ex->h_hint + c : NULL, ex->h_log ? ex->h_log + c : NULL,
                       ex->h_log_ld, ex->h_log_cap, ex->h_log_n ? ex->h_log_n + c : NULL,
-                      ex->post ? ex->post + c : NULL};
+                      ex->post ? ex->post + c : NULL,
+                      {ex->photo_flux ? ex->photo_flux[c] : 0.0, ex->photo_length ? ex->photo_length[c] : 0.0}};
     int32_t code = integrate_cell(n, o, nn, &Tc, rho ? rho[c] : 0.0, step, st, &ce);
     if (code != 2) {
       for (int s = 0; s < n->S; ++s) states[s * ld + c] = nn[s];

@@ -51,6 +51,24 @@ int kro_net_set_heat_capacity(kro_net *net, double T_mid, const double *cv_poly)
  * factor.  Returns 0, or 1 for invalid input. */
 int kro_net_set_tables(kro_net *net, int n_tab, int n_nodes, double log2T0, double dlog2T,
                        const int32_t *tab_of, const double *tab);
+/* Optional photoreactions and radiative heat terms (paper Sec. 2.2.1, the
+ * second rate type, and the heating/cooling of eq. method-ode-thermochem):
+ *   sigma[S]           photo-absorption cross-section of each species (cm^2)
+ *   photo[R]           1: the forward coefficient is A F_eff (A the
+ *                      reaction's cross-section, b = E = 0), no reverse;
+ *                      F_eff = F (1 - exp(-tau)) / tau, tau = L sum_s
+ *                      sigma_s n_s, the path average over the cell of eq.
+ *                      method-rad-equiv-flux (F, L per cell: kro_extras)
+ *   heat_extra[R][3]   gas heating per net forward event besides the
+ *                      formation energies, q0 + q1 T + q2 T ln T (K): the
+ *                      absorbed photon energy, radiated recombination
+ *                      energy and the like.
+ * Any of the three may be NULL (photo needs sigma).  Returns 0 or 1. */
+int kro_net_set_photo(kro_net *net, const double *sigma, const int32_t *photo,
+                      const double *heat_extra);
+/* kro_rhs / kro_jacobian in a radiation field (F, L). */
+void kro_rhs_photo(const kro_net *net, const double *y, double F, double L, double *f, double *Q);
+void kro_jacobian_photo(const kro_net *net, const double *y, double F, double L, double *J);
 /* e_s(T) and c_V,s(T) of every species (k_B units). */
 void kro_species_thermo(const kro_net *net, double T, double *e, double *c);
 
@@ -122,6 +140,8 @@ typedef struct {
   int32_t h_log_cap;
   int32_t *h_log_n;
   int32_t *post;
+  const double *photo_flux;    /* [n_cells] optically thin photon flux (cm^-2 s^-1) */
+  const double *photo_length;  /* [n_cells] path length through the cell (cm) */
 } kro_extras;
 
 enum { KRO_POST_CLIPPED = 1,      /* stage 1 set a negative abundance to 0 */

@@ -30,6 +30,11 @@ Conventions (cgs, energies divided by k_B so they are in K):
   * cv_poly, T_mid       optional temperature-dependent heat capacities:
                          cv_poly[s][piece][k], c_V/k_B = sum_k a_k T^k on
                          T < T_mid (piece 0) and T >= T_mid (piece 1).
+  * sigma_abs, photo,    optional photoreactions: photo[r] = 1 makes the
+    heat_extra           forward coefficient A F_eff (A the reaction's
+                         cross-section) with no reverse; heat_extra[r] =
+                         (q0, q1, q2) adds q0 + q1 T + q2 T ln T of gas
+                         heating per net event (K), besides -dH.
   * tab_of, tab_log2k,   optional tabulated rate factors: reaction r with
     tab_log2T0,          tab_of[r] = t >= 0 has its coefficient multiplied by
     tab_dlog2T           the factor whose log2 is tab_log2k[t][i] at
@@ -77,6 +82,9 @@ class NetworkDesc:
     tab_log2k: np.ndarray | None = None      # float64 [n_tables, n_nodes]
     tab_log2T0: float = 0.0
     tab_dlog2T: float = 1.0
+    sigma_abs: np.ndarray | None = None      # float64 [S] photo-absorption cross-sections (cm^2)
+    photo: np.ndarray | None = None          # int32 [R] 1: photoreaction
+    heat_extra: np.ndarray | None = None     # float64 [R, 3] extra heat q0 + q1 T + q2 T ln T (K)
 
     @property
     def n_species(self) -> int:
@@ -444,6 +452,51 @@ def network_h_o_n_tcv(seed_index: int = 1, n_tables: int = 4, n_nodes: int = 48)
     net.tab_log2T0, net.tab_dlog2T = float(x0), float(dx)
     net.name = "h_o_n_tcv_9sp"
     net.meta = dict(net.meta, tabulated=picks.tolist())
+    return net
+
+
+E_V = 1.602176634e-12        # erg
+I_H_K = 13.6 * E_V / K_BOLTZ   # hydrogen ionisation energy / k_B (K)
+SIGMA_H = 6.3e-18            # H photo-ionisation cross-section at threshold (cm^2)
+H_NU_EV = 16.0               # photon energy of the monochromatic field (eV)
+
+
+def network_stromgren(isothermal: bool = False) -> NetworkDesc:
+    """The hydrogen chemistry of the paper's Stromgren-sphere test (Sec. 4.3,
+    eq. strom-chem): H + photon -> H+ + e- (photoreaction, cross-section
+    6.3e-18 cm^2), H + e- -> H+ + 2 e- (collisional ionisation, k_ci of
+    eq. thermo-strom: 1.05e-9 (T/300)^0.5 exp(-I_H/k_B T) cm^3 s^-1) and
+    H+ + e- -> H + photon (case-B recombination alpha = 3.5e-12 (T/300)^-0.75
+    cm^3 s^-1), all irreversible.  Energies: H+ lies I_H = 13.6 eV above H
+    (formation energies), the photoreaction adds the absorbed photon's
+    h nu = 16 eV, the recombination removes the radiated I_H + lambda_rec,
+    lambda_rec = [0.684 - 0.0416 ln(T / 1e4 K)] k_B T (eq. thermo-strom).
+    isothermal=True drops every energy term and gives the electron no heat
+    capacity, so that c_V does not change with ionisation: Q = 0 and T stays
+    put."""
+    species = ["H", "H+", "e-"]
+    rows = ["H", "charge"]
+    comp = np.array([[1, 1, 0], [0, 1, -1]], np.int32)
+    reservoir = np.array([0, 2], np.int32)
+    cv = np.array([1.5, 1.5, 0.0 if isothermal else 1.5])
+    h_form = np.array([0.0, 0.0 if isothermal else I_H_K, 0.0])
+    s_form = np.zeros(3)
+    reac = np.array([[0, -1, -1], [0, 2, -1], [1, 2, -1]], np.int32)
+    prod = np.array([[1, 2, -1], [1, 2, 2], [0, -1, -1]], np.int32)
+    arr_f = np.array([[SIGMA_H, 0.0, 0.0],
+                      [1.05e-9 * 300.0 ** -0.5, 0.5, I_H_K],
+                      [3.5e-12 * 300.0 ** 0.75, -0.75, 0.0]])
+    arr_r = np.zeros((3, 3))
+    heat = np.zeros((3, 3))
+    if not isothermal:
+        heat[0] = (H_NU_EV * E_V / K_BOLTZ, 0.0, 0.0)
+        heat[2] = (-I_H_K, -(0.684 + 0.0416 * np.log(1.0e4)), 0.0416)
+    net = NetworkDesc("stromgren_h" + ("_iso" if isothermal else ""), species, rows, 1, comp, reservoir, cv,
+                      h_form, s_form, reac, prod, arr_f, arr_r, p_ref=ATM, T_min=10.0, T_max=1.0e6,
+                      meta={"h_nu_eV": H_NU_EV})
+    net.sigma_abs = np.array([SIGMA_H, 0.0, 0.0])
+    net.photo = np.array([1, 0, 0], np.int32)
+    net.heat_extra = heat
     return net
 
 
