@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, flop/s
+PEAK_FP32 = 157.3e12         # MI355X FP32 vector, flop/s
 SHORT_DT = 1e-7              # the learned guess's short-step leg (s)
 C_EXP = 27.0                 # FP64 exp / log counted as 27 flops each (range
                              # reduction + degree-11 polynomial + scaling)
@@ -65,6 +66,16 @@ def flops_per_unit(desc):
         nnz = int(np.count_nonzero(nu[r])) + 1          # species rows + energy row
         f_eval += 2 + len(cols) + 2 * nnz * (len(cols) + 1) + 2 * nnz
         f_rhs += 1 + 2 * nnz
+    # temperature-dependent heat capacities: per species c_V and e (two
+    # degree-4/5 Horner chains) and the two sums; tabulated factors: the
+    # lookup (index, fraction, interpolation, slope) per tabulated reaction
+    if getattr(desc, "cv_poly", None) is not None:
+        f_eval += S * (8 + 10 + 4)
+        f_rhs += S * (8 + 10 + 4)
+    if getattr(desc, "tab_of", None) is not None:
+        n_tab = int(np.count_nonzero(np.asarray(desc.tab_of) >= 0))
+        f_eval += 8 * n_tab
+        f_rhs += 8 * n_tab
     f_it = f_eval + 2 * N * N + 3 * N + (2.0 / 3.0) * N ** 3 + 2 * N * N + 4 * N
     return f_it, f_rhs
 
@@ -444,6 +455,103 @@ def run_h_he(args):
     net.close()
 
 
+def run_stromgren(args):
+    """Photo-ionisation chemistry (Sec. 4.3's hydrogen network: photo- and
+    collisional ionisation, case-B recombination, photo-heating and
+    recombination cooling) on 2^20 cells of an H II region around the
+    fiducial source (synthetic.cells_stromgren: per-cell flux, path length,
+    density, ionised fraction, temperature and step), one cell per lane."""
+    import torch
+    import paper_2504_04941_amd as kr
+    import synthetic as sy
+
+    dev = torch.device("cuda", 0)
+    desc = sy.network_stromgren()
+    cs, F_h, L_h = sy.cells_stromgren(desc, args.cells)
+    net = kr.Network(desc)
+    n0 = torch.tensor(cs.n, device=dev)
+    T0 = torch.tensor(cs.T, device=dev)
+    dt = torch.tensor(cs.dt, device=dev)
+    F = torch.tensor(F_h, device=dev)
+    L = torch.tensor(L_h, device=dev)
+    n, T = torch.empty_like(n0), torch.empty_like(T0)
+    status = torch.empty(args.cells, dtype=torch.int32, device=dev)
+    stats = torch.empty((args.cells, 4), dtype=torch.int32, device=dev)
+    f_it, f_rhs = flops_per_unit(desc)
+    stream = torch.cuda.current_stream()
+    results, gpu_out = {}, {}
+    for variant in args.variants.split(","):
+        opts = kr.default_options(precision=variant, order=_order(args))
+
+        def step():
+            n.copy_(n0)
+            T.copy_(T0)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            kr.chem_integrate(net, n, T, dt=dt, rtol=1e-6, opts=opts, status=status, cell_stats=stats,
+                              stream=stream, photo_flux=F, photo_length=L)
+            ev1.record(stream)
+            return ev0, ev1
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_s = np.mean([a.elapsed_time(b) for a, b in evs]) * 1e-3
+        st = stats.cpu().numpy().astype(np.int64)
+        flops = st[:, 1].sum() * f_it + (st[:, 0] + st[:, 2]).sum() * f_rhs
+        resid = torch.empty(args.cells, dtype=torch.float64, device=dev)
+        kr.element_residual(net, n0, n, resid=resid)
+        gpu_out[variant] = (n.cpu().numpy(), T.cpu().numpy(), status.cpu().numpy(), st[:, 1])
+        results[variant] = {"ms_per_step": wall / args.steps * 1e3, "value": args.cells * args.steps / wall,
+                            "kernel_ms": kernel_s * 1e3, "achieved_tflops": flops / kernel_s / 1e12,
+                            "newton_iters_per_cell": float(st[:, 1].mean()),
+                            "substeps_per_cell": float(st[:, 0].mean()), "max_substeps": int(st[:, 0].max()),
+                            "status_counts": np.bincount(status.cpu().numpy(), minlength=3).tolist(),
+                            "max_element_residual": float(resid.max().item())}
+        print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
+    head_name = "fp64" if "fp64" in results else next(iter(results))
+    head = results[head_name]
+    peak = PEAK_FP32 if head_name in ("single", "mixed") else PEAK_FP64
+    out = {"metric": "cell-steps/s implicit chem update, photo-ionisation (Stromgren) network, 1 GPU",
+           "value": head["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if peak == PEAK_FP32 else "f64",
+           "data": "synthetic",
+           "config": {"workload": f"stromgren: {args.cells} cells, H/H+/e- with photo- and collisional ionisation, "
+                                  "recombination, photo-heating and recombination cooling, per-cell flux and path "
+                                  "length (Phi = 1e49 s^-1 source, 1/4 pc cells), dt log-uniform [1e8, 1e12] s, "
+                                  "rtol 1e-6, one cell per lane", "cell_order": args.order},
+           "variants": results,
+           "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / peak, "traffic": None,
+                        "kernel": "kr_integrate_" + head_name, "flops_per_newton_iteration": f_it,
+                        "flops_per_error_estimate": f_rhs}}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        k = min(args.cpu_sample, args.cells)
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(args.cells, size=k, replace=False))
+        on = oracle.OracleNet(desc)
+        cores = len(os.sched_getaffinity(0))
+        t1 = time.perf_counter()
+        r = on.integrate_ex(cs.n[:, idx], cs.T[idx], dt=cs.dt[idx], nthreads=cores, photo_flux=F_h[idx],
+                            photo_length=L_h[idx])
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": k / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{k} cells drawn uniformly (seed 7) from the same batch, FP64 C oracle, "
+                                         f"OpenMP over {cores} threads, {el:.1f} s",
+                               "parity": {v: parity(desc, cs, idx, g[0][:, idx], g[1][idx], g[2][idx],
+                                                    (r["n"], r["T"], r["status"]), r["stats"][:, 1])
+                                          for v, g in gpu_out.items()}}
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
 def run_advect(args):
     """Species advection (Sec. 2.1): one SSP-RK2 step (two kr_advect_plm
     stages) of the stoichiometry-compatible PLM over lines of cells with
@@ -577,7 +685,7 @@ def calibrate_mixed(args):
 # for the long, uneven cells of the combustion and 48-species batches; input
 # order (coalesced state accesses, no extra rate evaluation) for the mixed
 # batch, whose cells mostly take one substep
-_ORDER_DEFAULT = {"h_o_n": "work", "large48": "work", "mixed": "input", "calibrate": "input",
+_ORDER_DEFAULT = {"h_o_n": "work", "h_o_n_tcv": "work", "stromgren": "work", "large48": "work", "mixed": "input", "calibrate": "input",
                   "h_he": "input", "advect": "input"}
 
 
@@ -592,7 +700,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="h_o_n",
-                    choices=["h_o_n", "h_he", "mixed", "large48", "calibrate", "advect"])
+                    choices=["h_o_n", "h_o_n_tcv", "h_he", "mixed", "large48", "calibrate", "advect",
+                             "stromgren"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "lane", "wave"],
                     help="h_he workload: the integrator layout")
@@ -618,6 +727,13 @@ def main():
         return
     if args.workload == "advect":
         run_advect(args)
+        return
+    if args.workload == "stromgren":
+        if args.variants == ap.get_default("variants"):
+            args.variants = "fp64,fp32lu,single,mixed"
+        if args.cpu_sample == 8192:
+            args.cpu_sample = 4096
+        run_stromgren(args)
         return
     if args.workload == "h_he":
         if args.cells == 1 << 20:
@@ -645,7 +761,10 @@ def main():
     import paper_2504_04941_amd as kr
     import synthetic as sy
 
-    desc = sy.network_h_o_n(1)
+    tcv = args.workload == "h_o_n_tcv"
+    if tcv and args.variants == ap.get_default("variants"):
+        args.variants = "fp64,fp32lu,single,mixed"
+    desc = sy.network_h_o_n_tcv() if tcv else sy.network_h_o_n(1)
     cs = sy.cells_h_o_n(desc, args.cells, 1)
     dt_scalar = cs.dt_scalar
     net = kr.Network(desc)
@@ -784,9 +903,16 @@ def main():
         }
         print(f"# {variant}: {results[variant]}", file=sys.stderr, flush=True)
 
-    head = results.get("fp64") or next(iter(results.values()))
+    head_name = "fp64" if "fp64" in results else next(iter(results))
+    head = results[head_name]
+    # the FP32 modes run their arithmetic on the FP32 vector ALUs
+    fp32_head = head_name in ("single", "mixed")
+    peak = PEAK_FP32 if fp32_head else PEAK_FP64
+    kernel_name = {"fp64": "kr_integrate_fp64", "single": "kr_integrate_single",
+                   "mixed": "kr_integrate_mixed"}.get(head_name, "kr_integrate_fp32lu")
     out = {
-        "metric": "cell-steps/s implicit chem update @1e-6 rel: plain FP64 vs mixed+MLP, 1 GPU",
+        "metric": ("cell-steps/s implicit chem update, c_V(T) and tabulated rates, 1 GPU" if tcv else
+                   "cell-steps/s implicit chem update @1e-6 rel: plain FP64 vs mixed+MLP, 1 GPU"),
         "value": head["value"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
@@ -796,18 +922,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if fp32_head else "f64",
         "data": "synthetic",
-        "config": {"workload": "h_o_n 9-species/24-reaction network + energy (10x10 LU), "
-                               f"{args.cells} cells, T~U[900,2500] K, 1 atm, dt=1e-4 s adaptive BE, rtol 1e-6",
+        "config": {"workload": ("h_o_n 9-species/24-reaction network + energy (10x10 LU), "
+                                + ("NASA-style piecewise-polynomial c_V(T), 4 tabulated reactions (48 nodes), "
+                                   if tcv else "")
+                                + f"{args.cells} cells, T~U[900,2500] K, 1 atm, dt=1e-4 s adaptive BE, rtol 1e-6"),
                    "cells": args.cells, "unknowns": desc.n_unknowns, "reactions": desc.n_reactions,
                    "variant": "fp64" if "fp64" in results else args.variants, "cell_order": args.order},
         "variants": results,
         "learned_guess": learned_info,
-        "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / PEAK_FP64,
-                     "traffic": measured_traffic(kr.network_check(desc)),
-                     "kernel": "kr_integrate_fp64", "flops_per_newton_iteration": f_it,
+        "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": head["achieved_tflops"] * 1e12 / peak,
+                     "traffic": (measured_traffic(kr.network_check(desc))
+                                 if head_name == "fp64" and not tcv else None),
+                     "kernel": kernel_name, "flops_per_newton_iteration": f_it,
                      "flops_per_error_estimate": f_rhs, "exp_log_flops": C_EXP},
     }
     if not args.no_cpu_baseline:

@@ -81,8 +81,57 @@ enum {
  *                                    K_eq = (p_ref/(k_B T))^dnu exp(dS - dH/T).
  *   T_min, T_max                     temperature limits applied to the input
  *                                    state (Sec. 2.2.2).
+ *   cv_poly [n_species][2][5]        optional (NULL: c_V constant, cv):
+ *                                    temperature-dependent heat capacities,
+ *                                    c_V/k_B = sum_k a_k T^k with one set of
+ *                                    coefficients for T < T_mid and one for
+ *                                    T >= T_mid (Sec. 4.2: NASA-style
+ *                                    piecewise polynomials; cv is then
+ *                                    unused).  The energy equation is written
+ *                                    in eps = sum_s n_s e_s(T), e_s the
+ *                                    integral of c_V,s from 0 (its upper
+ *                                    piece shifted to be continuous at
+ *                                    T_mid).
+ *   tab_of [n_reactions], tab_log2k [n_tables][n_tab_nodes]
+ *                                    optional (tab_of NULL: none): tabulated
+ *                                    rate factors (Sec. 2.2.1, third rate
+ *                                    type).  Reaction r with tab_of[r] = t >=
+ *                                    0 has its forward coefficient multiplied
+ *                                    by tau_t(T), log2 tau_t linear in log2 T
+ *                                    between the nodes log2 T = tab_log2T0 +
+ *                                    i tab_dlog2T (values tab_log2k[t][i];
+ *                                    the end segments extended beyond the
+ *                                    nodes); with detailed-balance reverse
+ *                                    rates (arr_r NULL) the reverse
+ *                                    coefficient carries the same factor.
+ *                                    Set arr_f[r] = (1, 0, 0) for a purely
+ *                                    tabulated coefficient.
+ *   sigma_abs [n_species], photo [n_reactions]
+ *                                    optional (NULL: none): photoreactions
+ *                                    (Sec. 2.2.1, second rate type).
+ *                                    photo[r] = 1 makes reaction r's forward
+ *                                    coefficient A F_eff (arr_f[r] = (A, 0,
+ *                                    0), A its cross-section in cm^2) and
+ *                                    its reverse coefficient 0; F_eff is the
+ *                                    cell's photon flux averaged over its
+ *                                    path, attenuated by the absorbers
+ *                                    sigma_abs (cm^2) of the cell
+ *                                    (kr_options.photo_flux, photo_length).
+ *                                    The Jacobian takes the flux derivative
+ *                                    in n_i times min{1, n_i sigma_i /
+ *                                    lambda^-1} (the paper's dominant-
+ *                                    absorber cutoff).  Lane layout only.
+ *   heat_extra [n_reactions][3]      optional (NULL: none): gas heating per
+ *                                    net forward event besides the
+ *                                    formation energies, q0 + q1 T + q2 T ln
+ *                                    T (K): absorbed photon energy, radiated
+ *                                    recombination energy (the heating and
+ *                                    cooling of eq. method-ode-thermochem).
+ *                                    Lane layout only.
  * Limits: 1 <= n_species <= KR_MAX_SPECIES, 0 <= n_rows <= KR_MAX_ROWS,
- * n_reactions >= 0. */
+ * n_reactions >= 0, 2 <= n_tab_nodes <= KR_MAX_TAB_NODES, n_tables <=
+ * n_reactions. */
+#define KR_MAX_TAB_NODES 1024
 #define KR_MAX_SPECIES 63
 #define KR_MAX_ROWS 8
 
@@ -103,6 +152,17 @@ typedef struct {
   double p_ref;
   double T_min;
   double T_max;
+  const double *cv_poly;
+  double T_mid;
+  int32_t n_tables;
+  int32_t n_tab_nodes;
+  const int32_t *tab_of;
+  const double *tab_log2k;
+  double tab_log2T0;
+  double tab_dlog2T;
+  const double *sigma_abs;
+  const int32_t *photo;
+  const double *heat_extra;
 } kr_network_desc;
 
 typedef struct kr_network kr_network;
@@ -291,6 +351,15 @@ typedef struct {
                            substeps of that attempt (may exceed h_log_cap;
                            0 for reverted cells and cells with dt = 0) */
   kr_stats *stats;      /* host, or NULL: totals of this call (synchronises) */
+  const double *photo_flux;   /* device [n_cells] or NULL (no radiation):
+                           each cell's optically thin photon flux F (cm^-2
+                           s^-1) for the network's photoreactions */
+  const double *photo_length; /* device [n_cells] or NULL (optically thin):
+                           each cell's path length L (cm) along the rays;
+                           the photoreactions see F_eff = F (1 - e^-tau) /
+                           tau, tau = L sum_s sigma_s n_s (Sec. 2.2.1 and
+                           eq. method-rad-equiv-flux: the path average over
+                           the cell) */
 } kr_options;
 
 void kr_default_options(kr_options *opt);

@@ -55,7 +55,11 @@ class _Desc(C.Structure):
                 ("reservoir", C.c_void_p), ("cv", C.c_void_p), ("h_form", C.c_void_p),
                 ("s_form", C.c_void_p), ("reac", C.c_void_p), ("prod", C.c_void_p),
                 ("arr_f", C.c_void_p), ("arr_r", C.c_void_p), ("p_ref", C.c_double),
-                ("T_min", C.c_double), ("T_max", C.c_double)]
+                ("T_min", C.c_double), ("T_max", C.c_double), ("cv_poly", C.c_void_p),
+                ("T_mid", C.c_double), ("n_tables", C.c_int32), ("n_tab_nodes", C.c_int32),
+                ("tab_of", C.c_void_p), ("tab_log2k", C.c_void_p), ("tab_log2T0", C.c_double),
+                ("tab_dlog2T", C.c_double), ("sigma_abs", C.c_void_p), ("photo", C.c_void_p),
+                ("heat_extra", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -78,7 +82,7 @@ class Options(C.Structure):
                 ("guess", C.c_void_p), ("guess_ld", C.c_int64), ("counters", C.c_void_p),
                 ("h_hint", C.c_void_p), ("h_log", C.c_void_p), ("h_log_ld", C.c_int64),
                 ("h_log_cap", C.c_int32), ("reserved", C.c_int32), ("h_log_n", C.c_void_p),
-                ("stats", C.POINTER(Stats))]
+                ("stats", C.POINTER(Stats)), ("photo_flux", C.c_void_p), ("photo_length", C.c_void_p)]
 
 
 class BuildOpts(C.Structure):
@@ -205,6 +209,32 @@ def _pack_desc(desc):
      d.arr_f) = (a.ctypes.data for a in keep[:8])
     d.arr_r = None if arr_r is None else arr_r.ctypes.data
     d.p_ref, d.T_min, d.T_max = float(desc.p_ref), float(desc.T_min), float(desc.T_max)
+    sig, photo, qx = (getattr(desc, k, None) for k in ("sigma_abs", "photo", "heat_extra"))
+    if sig is not None:
+        sig = np.ascontiguousarray(sig, np.float64)
+        keep.append(sig)
+        d.sigma_abs = sig.ctypes.data
+    if photo is not None:
+        photo = np.ascontiguousarray(photo, np.int32)
+        keep.append(photo)
+        d.photo = photo.ctypes.data
+    if qx is not None:
+        qx = np.ascontiguousarray(qx, np.float64).reshape(-1, 3)
+        keep.append(qx)
+        d.heat_extra = qx.ctypes.data
+    cvp = getattr(desc, "cv_poly", None)
+    if cvp is not None:
+        cvp = np.ascontiguousarray(cvp, np.float64)
+        keep.append(cvp)
+        d.cv_poly, d.T_mid = cvp.ctypes.data, float(desc.T_mid)
+    tab_of = getattr(desc, "tab_of", None)
+    if tab_of is not None:
+        tab_of = np.ascontiguousarray(tab_of, np.int32)
+        tab = np.ascontiguousarray(desc.tab_log2k, np.float64)
+        keep += [tab_of, tab]
+        d.tab_of, d.tab_log2k = tab_of.ctypes.data, tab.ctypes.data
+        d.n_tables, d.n_tab_nodes = tab.shape
+        d.tab_log2T0, d.tab_dlog2T = float(desc.tab_log2T0), float(desc.tab_dlog2T)
     return d, keep
 
 
@@ -297,7 +327,7 @@ def _stream_ptr(stream):
 def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,
                    rtol: float = 1e-6, opts: Options | None = None, status=None,
                    cell_stats=None, stream=None, h_hint=None, h_log=None, h_log_n=None,
-                   stats: bool = False, noalloc: bool = False):
+                   stats: bool = False, noalloc: bool = False, photo_flux=None, photo_length=None):
     """kr_chem_integrate on device tensors.
 
     states: float64 [S, ld] with unit stride along cells (row stride = ld);
@@ -307,9 +337,11 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
     [n_cells].  Asynchronous on the stream unless stats=True, which returns
     the call's kr_stats totals as a dict (and synchronises).  noalloc=True
     calls kr_chem_integrate_noalloc (no allocation; a static per-GPU
-    workspace)."""
+    workspace).  photo_flux, photo_length: float64 [n_cells], the cells'
+    radiation field for networks with photoreactions."""
     import torch
-    if h_hint is not None or h_log is not None or h_log_n is not None or stats:
+    if (h_hint is not None or h_log is not None or h_log_n is not None or stats or photo_flux is not None
+            or photo_length is not None):
         o = Options.from_buffer_copy(opts if opts is not None else default_options())
         n_cells = int(T.numel())
         if h_hint is not None:
@@ -326,6 +358,11 @@ def chem_integrate(net: Network, states, T, rho=None, dt=None, dt_scalar: float 
             if h_log_n.numel() != n_cells:
                 raise ValueError("h_log_n must be int32 [n_cells]")
             o.h_log_n = _dev_ptr(h_log_n, torch.int32, "h_log_n")
+        for name, arr in (("photo_flux", photo_flux), ("photo_length", photo_length)):
+            if arr is not None:
+                if arr.numel() != n_cells or not arr.is_contiguous():
+                    raise ValueError(f"{name} must be float64 [n_cells]")
+                setattr(o, name, _dev_ptr(arr, torch.float64, name))
         st = Stats()
         if stats:
             o.stats = C.pointer(st)

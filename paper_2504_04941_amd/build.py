@@ -37,6 +37,7 @@ def build(verbose: bool = False) -> str:
     _embed("kr_math.h", "kr_math_src.inc")
     _embed("kr_order.h", "kr_order_src.inc")
     _embed("kr_advect.h", "kr_advect_src.inc")
+    _embed("kr_thermo.h", "kr_thermo_src.inc")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-result",

@@ -86,12 +86,49 @@ struct KrSlotT {
 };
 typedef KrSlotT<double> KrSlot;
 
+/* The cell's radiation field for the photoreactions (0, 0 without one):
+ * optically thin photon flux and path length; false for an invalid one
+ * (negative or non-finite). */
+__device__ __forceinline__ bool kr_cell_rad(const KrParams &p, long long c, double &F, double &L) {
+  F = p.photo_flux ? p.photo_flux[c] : 0.0;
+  L = p.photo_length ? p.photo_length[c] : 0.0;
+  return F >= 0.0 && L >= 0.0 && __builtin_isfinite(F) && __builtin_isfinite(L);
+}
+
+/* c_V = sum_s c_s(T) n_s at y (kr_thermo.h) */
 template <typename R>
 __device__ __forceinline__ R kr_heat_capacity(const R (&y)[KR_N]) {
   R c = R(0);
+#if KR_CV_POLY
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) {
+    R es, cs;
+    kr_species_thermo(s, y[KR_S], es, cs);
+    c += cs * y[s];
+  }
+#else
 #pragma unroll
   for (int s = 0; s < KR_S; ++s) c += R(kr_cv[s]) * y[s];
+#endif
   return c;
+}
+
+/* thermal energy eps = sum_s n_s e_s(T) at y (T c_V for constant heat
+ * capacities) */
+template <typename R>
+__device__ __forceinline__ R kr_thermal_energy(const R (&y)[KR_N]) {
+#if KR_CV_POLY
+  R e = R(0);
+#pragma unroll
+  for (int s = 0; s < KR_S; ++s) {
+    R es, cs;
+    kr_species_thermo(s, y[KR_S], es, cs);
+    e += es * y[s];
+  }
+  return e;
+#else
+  return y[KR_S] * kr_heat_capacity(y);
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -522,6 +559,9 @@ struct KrLaneT {
   int acc0;                     /* accepted substeps before this attempt */
   int gstate;                   /* 1 guess pending, 2 Newton running from it */
   int acc, iters, rej, nfail;
+#if KR_PHOTO
+  double phF, phL;              /* the cell's radiation field */
+#endif
 };
 typedef KrLaneT<double> KrLane;
 
@@ -540,7 +580,7 @@ __device__ __forceinline__ void kr_start_attempt(const KrParams &p, KrLaneT<R> &
       L.e0[v] = (R)t;
     }
   }
-  L.eps_n = yr[KR_S] * kr_heat_capacity(yr);
+  L.eps_n = kr_thermal_energy(yr);
   L.t = 0.0;
   if (p.mode == 1) {
     L.h = L.dt / (double)p.n_fixed;
@@ -663,6 +703,13 @@ __device__ __forceinline__ bool kr_claim(const KrParams &p, KrLaneT<R> &L) {
     return true;
   }
   L.dt = dt;
+#if KR_PHOTO
+  if (!kr_cell_rad(p, L.cell, L.phF, L.phL)) {      /* invalid radiation field: revert */
+    kr_write_outcome(p, L, 2, 0, 0.0);
+    L.phase = KR_PH_NONE;
+    return true;
+  }
+#endif
   if (dt == 0.0) {                                  /* nothing to integrate */
 #pragma unroll
     for (int s = 0; s < KR_S; ++s) p.states[(long long)s * p.ld + L.cell] = y0[s];
@@ -725,6 +772,9 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
   for (int i = 0; i < KR_N; ++i) { L.y[i] = R(1); L.yn[i] = R(1); L.gn[i] = R(0); }
   L.h = L.t = L.dt = L.atol = L.eps_n = L.prev = 0.0;
+#if KR_PHOTO
+  L.phF = L.phL = 0.0;
+#endif
   L.safety = 0.9; L.growth = 5.0;
   L.attempt = L.k = L.grow = L.attempts = L.fin = L.gstate = L.acc0 = 0;
   L.acc = L.iters = L.rej = L.nfail = 0;
@@ -743,8 +793,28 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
     R g[KR_N], J[KR_N][KR_N], yv[KR_N];
 #pragma unroll
     for (int i = 0; i < KR_N; ++i) yv[i] = L.y[i];
+#if KR_PHOTO
+    kr_eval(yv, g, J, (R)L.phF, (R)L.phL);
+#else
     kr_eval(yv, g, J);
+#endif
+    /* heat capacity, thermal energy and d eps / d n_s = e_s(T) */
+#if KR_CV_POLY
+    R es[KR_S];
+    R cv = R(0), eps = R(0);
+#pragma unroll
+    for (int s = 0; s < KR_S; ++s) {
+      R cs;
+      kr_species_thermo(s, yv[KR_S], es[s], cs);
+      cv += cs * yv[s];
+      eps += es[s] * yv[s];
+    }
+#define KR_ES(m) es[m]
+#else
     const R cv = kr_heat_capacity(yv);
+    const R eps = yv[KR_S] * cv;
+#define KR_ES(m) (R(kr_cv[m]) * yv[KR_S])
+#endif
     const R icv = kr_rcp_r(cv);
     const int ph = L.phase;
 
@@ -752,7 +822,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       if (p.mode == 1) {                              /* fixed sequence */
 #pragma unroll
         for (int i = 0; i < KR_N; ++i) L.yn[i] = yv[i];
-        L.eps_n = yv[KR_S] * cv;
+        L.eps_n = eps;
         if (p.h_log && L.acc - L.acc0 < p.h_log_cap) p.h_log[(long long)(L.acc - L.acc0) * p.h_log_ld + L.cell] = L.h;
         L.acc++;
         if (L.acc >= p.n_fixed) kr_finish_cell<PREC>(p, L);
@@ -778,7 +848,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
             L.yn[i] = yv[i];
             L.gn[i] = i < KR_S ? g[i] : g[KR_S] * icv;
           }
-          L.eps_n = yv[KR_S] * cv;
+          L.eps_n = eps;
           if (p.h_log && L.acc - L.acc0 < p.h_log_cap) p.h_log[(long long)(L.acc - L.acc0) * p.h_log_ld + L.cell] = L.h;
           L.acc++;
           const double hnew = L.h * fmin(L.growth, fmax(0.2, L.safety / sqrt(fmax(err, 1e-10))));
@@ -846,7 +916,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
       R b[KR_N];
 #pragma unroll
       for (int s = 0; s < KR_S; ++s) b[s] = -(yv[s] - L.yn[s] - h * g[s]);
-      b[KR_S] = -(yv[KR_S] * cv - (R)L.eps_n - h * g[KR_S]);
+      b[KR_S] = -(eps - (R)L.eps_n - h * g[KR_S]);
       if (ph == KR_PH_GUESS && L.gstate == 2) {
         /* residual gate: keep the learned starting point only if its BE
          * residual is smaller (weighted max norm) than the plain start's,
@@ -871,7 +941,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
 #pragma unroll
         for (int m = 0; m < KR_N; ++m) J[s][m] = (s == m ? R(1) : R(0)) - h * J[s][m];
 #pragma unroll
-      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = R(kr_cv[m]) * yv[KR_S] - h * J[KR_S][m];
+      for (int m = 0; m < KR_S; ++m) J[KR_S][m] = KR_ES(m) - h * J[KR_S][m];
       J[KR_S][KR_S] = cv - h * J[KR_S][KR_S];
       L.iters++;
 
@@ -1005,6 +1075,7 @@ __device__ __forceinline__ void kr_integrate_body(const KrParams &p) {
     if (L.phase == KR_PH_RESTART) L.phase = KR_PH_START;
   }
 }
+#undef KR_ES
 
 #ifndef KR_WAVES_PER_EU
 #define KR_WAVES_PER_EU 1
@@ -1020,15 +1091,16 @@ __device__ __forceinline__ void kr_order_keys_body(const KrParams &p, unsigned c
     double y[KR_N], g[KR_N], J[KR_N][KR_N], dt;
     const bool ok = kr_load_input(p, c, y, dt);
     unsigned b = 0u;
-    if (ok && dt > 0.0) {
-      kr_eval(y, g, J);
+    double F, L;
+    if (ok && dt > 0.0 && kr_cell_rad(p, c, F, L)) {
+      kr_eval(y, g, J, F, L);
       double sf = 0.0, sn = 0.0;
 #pragma unroll
       for (int s = 0; s < KR_S; ++s) {
         sf += fabs(g[s]);
         sn += y[s];
       }
-      const double eps = y[KR_S] * kr_heat_capacity(y);
+      const double eps = kr_thermal_energy(y);
       b = kr_work_bucket(dt * (sf / sn + fabs(g[KR_S]) / eps));
     }
     bucket[c] = (unsigned char)b;
@@ -1044,7 +1116,9 @@ __device__ __forceinline__ void kr_timescale_body(const KrParams &p, double *out
        c += (long long)gridDim.x * blockDim.x) {
     double y[KR_N], g[KR_N], J[KR_N][KR_N], dt;
     kr_load_input(p, c, y, dt);
-    kr_eval(y, g, J);
+    double F, L;
+    kr_cell_rad(p, c, F, L);
+    kr_eval(y, g, J, F, L);
     double m = 0.0;
 #pragma unroll
     for (int s = 0; s < KR_S; ++s) m = fmax(m, fabs(J[s][s]));

@@ -50,6 +50,9 @@ static const char *kOrderSource =
 static const char *kAdvectSource =
 #include "kr_advect_src.inc"
     ;
+static const char *kThermoSource =
+#include "kr_thermo_src.inc"
+    ;
 
 static const double kBoltzmann = 1.380649e-16; /* erg / K */
 static const int KR_ORDER_NBUCKETS = 256;       /* KR_ORDER_BUCKETS of kr_order.h */
@@ -122,6 +125,21 @@ struct kr_network {
   std::vector<int32_t> comp, res, reac, prod;
   std::vector<double> cv, h, s, par; /* par: [R][2][3] */
   double p_ref = 0.0, T_min = 0.0, T_max = 0.0;
+  bool explicit_rev = false;
+  /* temperature-dependent heat capacities: cvp [S][2][5] (empty: constant),
+   * econ [S] the upper piece's energy constant */
+  std::vector<double> cvp, econ;
+  double T_mid = 0.0;
+  /* tabulated rate factors: tab_of [R] (empty: none), tab [n_tab][nodes] */
+  std::vector<int32_t> tab_of;
+  std::vector<double> tab;
+  int n_tab = 0, n_nodes = 0;
+  double tab_x0 = 0.0, tab_dx = 1.0;
+  /* photoreactions (photo empty: none) and extra heat per event (qx empty:
+   * none) */
+  std::vector<double> sigma, qx;
+  std::vector<int32_t> photo;
+  bool has_photo = false;
   std::string source;
   hipModule_t module = nullptr;
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
@@ -212,6 +230,64 @@ static int build_tables(const kr_network_desc *d, kr_network *n) {
       if (!std::isfinite(pf[k])) return fail(KR_EINVAL, "reaction %d: non-finite Arrhenius parameter", r);
     if (pf[0] < 0.0 || pr[0] < 0.0) return fail(KR_EINVAL, "reaction %d: negative pre-factor", r);
   }
+  n->explicit_rev = d->arr_r != nullptr;
+  if (d->cv_poly) {
+    if (!(d->T_mid > 0.0) || !std::isfinite(d->T_mid)) return fail(KR_EINVAL, "T_mid must be > 0");
+    n->cvp.assign(d->cv_poly, d->cv_poly + 10 * (size_t)S);
+    for (double v : n->cvp)
+      if (!std::isfinite(v)) return fail(KR_EINVAL, "non-finite heat-capacity coefficient");
+    n->T_mid = d->T_mid;
+    /* e_s(T) = sum_k a_k T^(k+1) / (k+1) on each piece; the upper piece
+     * shifted by econ so that e_s is continuous at T_mid */
+    auto energy = [](const double *a, long double T) {
+      long double e = 0.0L, Tk = T;
+      for (int k = 0; k < 5; ++k) { e += (long double)a[k] * Tk / (k + 1); Tk *= T; }
+      return e;
+    };
+    n->econ.resize(S);
+    for (int sp = 0; sp < S; ++sp)
+      n->econ[sp] = (double)(energy(&n->cvp[10 * (size_t)sp], d->T_mid) - energy(&n->cvp[10 * (size_t)sp + 5], d->T_mid));
+  }
+  if (d->tab_of) {
+    const int nt = d->n_tables, K = d->n_tab_nodes;
+    if (nt < 1 || nt > std::max(R, 1) || K < 2 || K > KR_MAX_TAB_NODES || !d->tab_log2k)
+      return fail(KR_EINVAL, "bad table sizes (%d tables of %d nodes)", nt, K);
+    if (!(d->tab_dlog2T > 0.0) || !std::isfinite(d->tab_dlog2T) || !std::isfinite(d->tab_log2T0))
+      return fail(KR_EINVAL, "bad table grid");
+    n->tab_of.assign(d->tab_of, d->tab_of + R);
+    for (int r = 0; r < R; ++r)
+      if (n->tab_of[r] < -1 || n->tab_of[r] >= nt) return fail(KR_EINVAL, "reaction %d: table index out of range", r);
+    n->tab.assign(d->tab_log2k, d->tab_log2k + (size_t)nt * K);
+    for (double v : n->tab)
+      if (!std::isfinite(v)) return fail(KR_EINVAL, "non-finite table value");
+    n->n_tab = nt; n->n_nodes = K;
+    n->tab_x0 = d->tab_log2T0; n->tab_dx = d->tab_dlog2T;
+  }
+  if (d->photo) {
+    if (!d->sigma_abs) return fail(KR_EINVAL, "photoreactions need sigma_abs");
+    n->photo.assign(d->photo, d->photo + R);
+    for (int r = 0; r < R; ++r) {
+      if (n->photo[r] != 0 && n->photo[r] != 1) return fail(KR_EINVAL, "reaction %d: photo flag not 0 or 1", r);
+      if (n->photo[r]) {
+        n->has_photo = true;
+        const double *pf = &n->par[6 * (size_t)r];
+        if (pf[1] != 0.0 || pf[2] != 0.0)
+          return fail(KR_EINVAL, "reaction %d: a photoreaction's coefficient is A F_eff (b = E = 0)", r);
+        /* no reverse direction */
+        for (int k = 3; k < 6; ++k) n->par[6 * (size_t)r + k] = 0.0;
+      }
+    }
+  }
+  if (d->sigma_abs) {
+    n->sigma.assign(d->sigma_abs, d->sigma_abs + S);
+    for (double v : n->sigma)
+      if (!(v >= 0.0) || !std::isfinite(v)) return fail(KR_EINVAL, "bad photo-absorption cross-section");
+  }
+  if (d->heat_extra) {
+    n->qx.assign(d->heat_extra, d->heat_extra + 3 * (size_t)R);
+    for (double v : n->qx)
+      if (!std::isfinite(v)) return fail(KR_EINVAL, "non-finite extra heat coefficient");
+  }
   return KR_OK;
 }
 
@@ -266,6 +342,7 @@ struct WideDir {
   double A, b, E;
   int slot[3];
   std::vector<int> nu;
+  int tab;                      /* tabulated factor of the direction, or -1 */
 };
 
 static std::vector<WideDir> wide_directions(const kr_network *n) {
@@ -276,7 +353,8 @@ static std::vector<WideDir> wide_directions(const kr_network *n) {
       if (pp[0] == 0.0) continue;
       const int32_t *re = dir ? &n->prod[3 * r] : &n->reac[3 * r];
       const int32_t *pr = dir ? &n->reac[3 * r] : &n->prod[3 * r];
-      WideDir d{pp[0], pp[1], pp[2], {re[0], re[1], re[2]}, std::vector<int>(n->S, 0)};
+      const int tab = n->tab_of.empty() || (dir == 1 && n->explicit_rev) ? -1 : n->tab_of[r];
+      WideDir d{pp[0], pp[1], pp[2], {re[0], re[1], re[2]}, std::vector<int>(n->S, 0), tab};
       for (int k = 0; k < 3; ++k) {
         if (re[k] >= 0) d.nu[re[k]] -= 1;
         if (pr[k] >= 0) d.nu[pr[k]] += 1;
@@ -320,6 +398,8 @@ static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pai
 
 static int check_wide(const kr_network *n) {
   if (n->S > 62) return fail(KR_EINVAL, "the wavefront layout takes at most 62 species (got %d)", n->S);
+  if (n->has_photo || !n->qx.empty())
+    return fail(KR_EINVAL, "photoreactions and extra heat terms need the lane layout");
   const size_t D = wide_directions(n).size();
   const size_t ndp = ((D + 63) / 64) * 64;
   if (5 * ndp > 4096)
@@ -367,6 +447,11 @@ static std::string generate_wide(const kr_network *n) {
                    : (q == 1 ? dirs[d].b : dirs[d].E);
       o += hexd(v) + (d + 1 < NDP ? "," : "");
     }
+    o += "};\n";
+  }
+  if (n->n_tab > 0) {
+    o += "__device__ static constexpr int kr_dtab[" + std::to_string(NDP) + "] = {";
+    for (int d = 0; d < NDP; ++d) o += std::to_string(d < (int)dirs.size() ? dirs[d].tab : -1) + (d + 1 < NDP ? "," : "");
     o += "};\n";
   }
   o += "__device__ static constexpr unsigned kr_dr[" + std::to_string(NDP) + "] = {";
@@ -418,6 +503,53 @@ static std::string network_tables(const kr_network *n) {
   o += "};\n";
   o += "__device__ static constexpr double kr_T_min = " + hexd(n->T_min) + ";\n";
   o += "__device__ static constexpr double kr_T_max = " + hexd(n->T_max) + ";\n";
+  /* temperature-dependent heat capacities: c_V coefficients and the energy's
+   * (a_k / (k + 1), then the piece's constant), per species and piece */
+  if (!n->cvp.empty()) {
+    o += "#define KR_CV_POLY 1\n";
+    o += "__device__ static constexpr double kr_T_mid = " + hexd(n->T_mid) + ";\n";
+    o += "__device__ static constexpr double kr_cvp[" + std::to_string(S) + "][2][5] = {";
+    std::string ev = "__device__ static constexpr double kr_evp[" + std::to_string(S) + "][2][6] = {";
+    for (int sp = 0; sp < S; ++sp) {
+      o += "{";
+      ev += "{";
+      for (int piece = 0; piece < 2; ++piece) {
+        const double *a = &n->cvp[10 * (size_t)sp + 5 * piece];
+        o += "{";
+        ev += "{";
+        for (int k = 0; k < 5; ++k) {
+          o += hexd(a[k]) + (k < 4 ? "," : "");
+          ev += hexd((double)((long double)a[k] / (k + 1))) + ",";
+        }
+        ev += hexd(piece ? n->econ[sp] : 0.0);
+        o += piece ? "}" : "},";
+        ev += piece ? "}" : "},";
+      }
+      o += sp + 1 < S ? "}," : "}";
+      ev += sp + 1 < S ? "}," : "}";
+    }
+    o += "};\n" + ev + "};\n";
+  }
+  /* tabulated rate factors: log2 values at nodes uniform in log2 T */
+  if (n->n_tab > 0) {
+    o += "#define KR_NTAB " + std::to_string(n->n_tab) + "\n#define KR_TAB_NODES " + std::to_string(n->n_nodes) + "\n";
+    o += "__device__ static constexpr double kr_tab_x0 = " + hexd(n->tab_x0) + ";\n";
+    o += "__device__ static constexpr double kr_tab_idx = " + hexd((double)(1.0L / (long double)n->tab_dx)) + ";\n";
+    o += "__device__ static constexpr double kr_tab[" + std::to_string(n->n_tab) + "][" + std::to_string(n->n_nodes) + "] = {";
+    for (int t = 0; t < n->n_tab; ++t) {
+      o += "{";
+      for (int i = 0; i < n->n_nodes; ++i) o += hexd(n->tab[(size_t)t * n->n_nodes + i]) + (i + 1 < n->n_nodes ? "," : "");
+      o += t + 1 < n->n_tab ? "}," : "}";
+    }
+    o += "};\n";
+  } else {
+    o += "#define KR_NTAB 0\n";
+  }
+  if (n->has_photo) {
+    o += "#define KR_PHOTO 1\n";
+  }
+  o += kThermoSource;
+  o += "\n";
   /* projector onto the stoichiometric space, the null space of the
    * element-species matrix (Sec. 2.1: P = V V^T), as I - Q^T Q with Q an
    * orthonormal basis of the conserved rows' span (modified Gram-Schmidt,
@@ -463,13 +595,16 @@ static std::string network_tables(const kr_network *n) {
 /* A constant of the working precision R of the generated code. */
 static std::string lit(double v) { return "R(" + hexd(v) + ")"; }
 
-static std::string arrhenius_code(const double *abc) {
+/* extra: the name of a log2 factor to add to the exponent (a tabulated
+ * factor), or empty. */
+static std::string arrhenius_code(const double *abc, const std::string &extra = "") {
   const long double log2e = 1.4426950408889634073599246810018921L;
   const double a2 = (double)log2l((long double)abc[0]);
   const double b = abc[1];
   const double c2 = (double)((long double)abc[2] * log2e);
-  if (b == 0.0 && c2 == 0.0) return lit(abc[0]);
+  if (b == 0.0 && c2 == 0.0 && extra.empty()) return lit(abc[0]);
   std::string x = lit(a2);
+  if (!extra.empty()) x = "(" + x + " + " + extra + ")";
   if (b != 0.0) x = "fma(" + lit(b) + ", l2T, " + x + ")";
   if (c2 != 0.0) x = "fma(" + lit(-c2) + ", iT, " + x + ")";
   return "kr_exp2(" + x + ")";
@@ -490,11 +625,27 @@ static std::string generate_network(const kr_network *n) {
        "__device__ __forceinline__ float kr_log2(float x) { return __builtin_amdgcn_logf(x); }\n";
   o += "template <typename R>\n"
        "__device__ __forceinline__ void kr_eval(const R (&y)[KR_S + 1], R (&g)[KR_S + 1],\n"
-       "                                        R (&J)[KR_S + 1][KR_S + 1]) {\n"
+       "                                        R (&J)[KR_S + 1][KR_S + 1], R phF = R(0), R phL = R(0)) {\n"
        "#pragma unroll\n  for (int i = 0; i <= KR_S; ++i) {\n    g[i] = R(0);\n"
        "#pragma unroll\n    for (int j = 0; j <= KR_S; ++j) J[i][j] = R(0);\n  }\n"
        "  const R T = y[KR_S];\n  const R l2T = kr_log2(T);\n  const R iT = R(1) / T;\n";
   const std::string ST = std::to_string(S);
+  /* photoreactions: the cell's inverse absorption length, the effective
+   * flux and its derivative, and the dominant-absorber cutoff per absorber */
+  if (n->has_photo) {
+    std::string li;
+    for (int s = 0; s < S; ++s)
+      if (n->sigma[s] > 0.0) li += (li.empty() ? "" : " + ") + lit(n->sigma[s]) + " * y[" + std::to_string(s) + "]";
+    o += "  const R linv = " + (li.empty() ? std::string("R(0)") : li) + ";\n";
+    o += "  R Fe, dFe;\n  kr_photo_flux(phF, phL, linv, Fe, dFe);\n";
+    for (int s = 0; s < S; ++s)
+      if (n->sigma[s] > 0.0)
+        o += "  const R cut" + std::to_string(s) + " = linv > R(0) ? fmin(R(1), y[" + std::to_string(s) + "] * " +
+             lit(n->sigma[s]) + " / linv) : R(1);\n";
+  } else {
+    o += "  (void)phF;\n  (void)phL;\n";
+  }
+  if (!n->qx.empty()) o += "  const R lnT = l2T * " + lit(0.69314718055994530942) + ";\n";
   for (int r = 0; r < n->R; ++r) {
     const double *pf = &n->par[6 * (size_t)r], *pr = pf + 3;
     std::vector<int> nu(S, 0);
@@ -506,17 +657,28 @@ static std::string generate_network(const kr_network *n) {
     for (int s = 0; s < S; ++s) dH += nu[s] * n->h[s];
     const double qhat = -dH;
     o += "  { /* reaction " + std::to_string(r) + " */\n";
+    /* a tabulated factor (both directions with detailed-balance reverse
+     * rates, the forward one only otherwise): its log2 joins the exponent,
+     * its log-log slope the temperature derivative */
+    const int tab = n->tab_of.empty() ? -1 : n->tab_of[r];
+    if (tab >= 0) o += "    R st;\n    const R lt = kr_tab_log2(" + std::to_string(tab) + ", l2T, st);\n";
     std::vector<std::pair<int, std::string>> dw; /* dw/dy_m terms */
     std::string w, dwdT;
     for (int dir = 0; dir < 2; ++dir) {
       const double *pp = dir ? pr : pf;
       if (pp[0] == 0.0) continue;
+      const bool tabbed = tab >= 0 && (dir == 0 || !n->explicit_rev);
+      const bool ph = dir == 0 && !n->photo.empty() && n->photo[r];
       const std::string k = dir ? "kr" : "kf";
-      o += "    const R " + k + " = " + arrhenius_code(pp) + ";\n";
+      if (ph)
+        o += "    const R kf = " + lit(pp[0]) + " * Fe;\n";
+      else
+        o += "    const R " + k + " = " + arrhenius_code(pp, tabbed ? "lt" : "") + ";\n";
       SideCode c = side_code(k, dir ? &n->prod[3 * r] : &n->reac[3 * r]);
       const std::string q = dir ? "qr" : "qf";
       o += "    const R " + q + " = " + c.q + ";\n";
-      o += "    const R " + q + "T = " + q + " * (" + lit(pp[1]) + " + " + lit(pp[2]) + " * iT) * iT;\n";
+      o += "    const R " + q + "T = " + q + " * (" + lit(pp[1]) + (tabbed ? " + st" : "") + " + " + lit(pp[2]) +
+           " * iT) * iT;\n";
       w += (dir ? " - " : (w.empty() ? "" : " + ")) + q;
       dwdT += (dir ? " - " : (dwdT.empty() ? "" : " + ")) + q + "T";
       for (auto &t : c.dq) {
@@ -524,6 +686,19 @@ static std::string generate_network(const kr_network *n) {
         const std::string term = (dir ? " - " : " + ") + t.second;
         if (it == dw.end()) dw.push_back({t.first, term});
         else it->second += term;
+      }
+      if (ph) {
+        /* the coefficient's own dependence on the absorbers, with the
+         * dominant-absorber cutoff */
+        o += "    const R kpd = " + lit(pp[0]) + " * dFe;\n";
+        const std::string pq = side_code("kpd", &n->reac[3 * r]).q;
+        for (int m = 0; m < S; ++m) {
+          if (!(n->sigma[m] > 0.0)) continue;
+          const std::string term = " + " + pq + " * " + lit(n->sigma[m]) + " * cut" + std::to_string(m);
+          auto it = std::find_if(dw.begin(), dw.end(), [&](const std::pair<int, std::string> &e) { return e.first == m; });
+          if (it == dw.end()) dw.push_back({m, term});
+          else it->second += term;
+        }
       }
     }
     if (w.empty()) { o += "  }\n"; continue; }
@@ -539,7 +714,15 @@ static std::string generate_network(const kr_network *n) {
       for (auto &t : dw) o += "    J[" + ss + "][" + std::to_string(t.first) + "] += " + c + "w" + std::to_string(t.first) + ";\n";
       o += "    J[" + ss + "][" + ST + "] += " + c + "wT;\n";
     }
-    if (qhat != 0.0) {
+    const double *qx = n->qx.empty() ? nullptr : &n->qx[3 * (size_t)r];
+    if (qx && (qx[0] != 0.0 || qx[1] != 0.0 || qx[2] != 0.0)) {
+      /* heat per event: -dH plus the extra q0 + q1 T + q2 T ln T */
+      o += "    const R qx = " + lit(qhat + qx[0]) + " + T * (" + lit(qx[1]) + " + " + lit(qx[2]) + " * lnT);\n";
+      o += "    const R dqx = " + lit(qx[1]) + " + " + lit(qx[2]) + " * (lnT + R(1));\n";
+      o += "    g[" + ST + "] += qx * w;\n";
+      for (auto &t : dw) o += "    J[" + ST + "][" + std::to_string(t.first) + "] += qx * w" + std::to_string(t.first) + ";\n";
+      o += "    J[" + ST + "][" + ST + "] += qx * wT + dqx * w;\n";
+    } else if (qhat != 0.0) {
       const std::string qh = lit(qhat);
       o += "    g[" + ST + "] += " + qh + " * w;\n";
       for (auto &t : dw) o += "    J[" + ST + "][" + std::to_string(t.first) + "] += " + qh + " * w" + std::to_string(t.first) + ";\n";
@@ -667,7 +850,8 @@ static std::string full_source(const kr_network *n, const kr_build_opts &o) {
            kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + lu_mfma_define(n, o) +
            generate_wide(n) + "\n" + kWideSource + "\n" + kAdvectSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" + kDeviceSource +
+         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" +
+         kDeviceSource +
          "\n" + kAdvectSource;
 }
 
@@ -999,6 +1183,7 @@ static int integrate_impl(const kr_network *net, int64_t n_cells, double *states
   p.order = nullptr;
   p.h_hint = o.h_hint; p.h_log = o.h_log; p.h_log_ld = o.h_log_ld; p.h_log_cap = o.h_log_cap;
   p.h_log_n = o.h_log_n;
+  p.photo_flux = o.photo_flux; p.photo_length = o.photo_length;
   p.totals = nullptr;
   if (o.stats) {
     /* totals and this call's statistics counters in the workspace's block,
@@ -1378,10 +1563,11 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
            "\n" + kWideSource +
            "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n#undef KR_LDJ\n#undef KR_NDR\n"
            "#undef KR_NC\n#undef KR_NF\n#undef KR_NDP\n#undef KR_NOTPIV\n#undef KR_LU_MFMA\n#undef KR_USE_LU_MFMA\n"
-           "#undef KR_PF\n";
+           "#undef KR_PF\n#undef KR_CV_POLY\n#undef KR_NTAB\n#undef KR_TAB_NODES\n";
     else
-      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" + kDeviceSource +
-           "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n";
+      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_network(nets[k]) + "\n" +
+           kDeviceSource + "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n"
+           "#undef KR_CV_POLY\n#undef KR_NTAB\n#undef KR_TAB_NODES\n";
   }
   s += "struct KrMulti { KrParams net[" + std::to_string(KR_MAX_NETS) + "]; int n_nets; };\n";
   const auto groups = multi_groups(nets, o);
@@ -1434,6 +1620,8 @@ extern "C" int kr_multi_create(const kr_network *const *nets, int32_t n_nets, co
     if (!nets || n_nets < 1 || n_nets > KR_MAX_NETS) return fail(KR_EINVAL, "n_nets out of [1, %d]", KR_MAX_NETS);
     for (int k = 0; k < n_nets; ++k) {
       if (!nets[k]) return fail(KR_EINVAL, "null network %d", k);
+      if (nets[k]->has_photo)
+        return fail(KR_EINVAL, "network %d has photoreactions: not supported in multi-network launches", k);
     }
     kr_build_opts bo;
     kr_default_build_options(&bo);
@@ -1501,6 +1689,8 @@ extern "C" int kr_multi_check(const kr_network_desc *const *descs, int32_t n_net
     for (int k = 0; k < n_nets; ++k) {
       int rc = build_tables(descs[k], &tabs[k]);
       if (rc != KR_OK) return rc;
+      if (tabs[k].has_photo)
+        return fail(KR_EINVAL, "network %d has photoreactions: not supported in multi-network launches", k);
       ptrs.push_back(&tabs[k]);
     }
     kr_build_opts bo;

@@ -39,6 +39,8 @@ struct KrParams {
   int h_log_cap;
   int *h_log_n;          /* [n_cells] number of accepted substeps logged, or null */
   unsigned long long *totals; /* [8] per-call totals (see KR_TOT_*), or null */
+  const double *photo_flux;   /* [n_cells] optically thin photon flux, or null */
+  const double *photo_length; /* [n_cells] path length, or null */
 };
 
 /* Per-call totals accumulated by the integrators (each wave flushes its own

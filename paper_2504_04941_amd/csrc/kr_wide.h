@@ -163,12 +163,23 @@ __device__ __forceinline__ void kr_wdirections(KrWave &w) {
 #pragma unroll
   for (int j = 0; j < KR_NDR; ++j) {
     const int d = lane + 64 * j;
-    const double a2 = kr_da2[d], b = kr_db[d], E = kr_dE[d];
+    double a2 = kr_da2[d], b = kr_db[d];
+    const double E = kr_dE[d];
+#if KR_NTAB > 0
+    /* a tabulated factor: its log2 joins the exponent, its log-log slope
+     * the temperature derivative */
+    const int tb = kr_dtab[d];
+    if (tb >= 0) {
+      double st;
+      a2 += kr_tab_log2(tb, l2T, st);
+      b += st;
+    }
+#endif
     const unsigned rr = kr_dr[d];
     const double n0 = w.y[rr & 63u], n1 = w.y[(rr >> 8) & 63u], n2 = w.y[(rr >> 16) & 63u];
     /* k = A T^b exp(-E/T) = 2^(log2 A + b log2 T - E log2(e) / T) */
     const double eiT = E * iT;
-    const double k = kr_exp2(fma(-eiT, 0x1.71547652b82fep+0, fma(b, l2T, a2)));
+    const double k = kr_exp2(fma(-eiT, 0x1.71547652b82fep+0, fma(kr_db[d], l2T, a2)));
     const double q = k * n0 * n1 * n2;
     double *P = w.P + 5 * d;
     P[0] = q;
@@ -250,10 +261,44 @@ __device__ __forceinline__ void kr_wrhs(KrWave &w, double yl) {
   kr_wenergy(w, KR_S + 1, KR_S + 1);
 }
 
-/* sum_s c_s n_s over the lane-distributed point */
+/* This lane's species thermal energy e_l(T) and heat capacity c_l(T) (0
+ * beyond the species) at the temperature T of the point. */
+__device__ __forceinline__ void kr_wspecies(double T, double &el, double &cl) {
+  const int lane = threadIdx.x;
+  el = cl = 0.0;
+#if KR_CV_POLY
+  if (lane < KR_S) kr_species_thermo(lane, T, el, cl);
+#else
+  if (lane < KR_S) {
+    cl = kr_cv[lane];
+    el = cl * T;
+  }
+#endif
+}
+
+/* c_V = sum_s c_s(T) n_s over the lane-distributed point */
 __device__ __forceinline__ double kr_wheatcap(double yl) {
   const int lane = threadIdx.x;
+#if KR_CV_POLY
+  double el, cl;
+  kr_wspecies(kr_bcast(yl, KR_S), el, cl);
+  return kr_wsum(lane < KR_S ? cl * yl : 0.0);
+#else
   return kr_wsum(lane < KR_S ? kr_cv[lane] * yl : 0.0);
+#endif
+}
+
+/* thermal energy eps = sum_s n_s e_s(T) of the lane-distributed point (T
+ * c_V for constant heat capacities) */
+__device__ __forceinline__ double kr_wenergy_of(double yl) {
+#if KR_CV_POLY
+  const int lane = threadIdx.x;
+  double el, cl;
+  kr_wspecies(kr_bcast(yl, KR_S), el, cl);
+  return kr_u(kr_wsum(lane < KR_S ? el * yl : 0.0));
+#else
+  return kr_bcast(yl, KR_S) * kr_u(kr_wheatcap(yl));
+#endif
 }
 
 /* g = (f, Q / c_V) for lane i, after kr_wrhs or kr_weval */
@@ -617,19 +662,35 @@ __device__ __forceinline__ bool kr_wnewton(const KrParams &p, KrWave &w, KrWCell
   const int max_newton = kr_ui(p.max_newton);
   for (int it = 0; it < max_newton; ++it) {
     kr_weval(w, y);
-    const double cv = kr_u(kr_wheatcap(y));
     const double T = kr_bcast(y, KR_S);
+#if KR_CV_POLY
+    double el, cl;
+    kr_wspecies(T, el, cl);
+    const double cv = kr_u(kr_wsum(lane < KR_S ? cl * y : 0.0));
+    const double eps = kr_u(kr_wsum(lane < KR_S ? el * y : 0.0));
+#else
+    const double cv = kr_u(kr_wheatcap(y));
+    const double eps = T * cv;
+#endif
     /* residual (negated) and Newton matrix row of this lane */
     double b = 0.0;
     if (lane < KR_S) b = -(y - yn - h * w.J[lane * KR_LDJ + KR_S + 1]);
-    else if (lane == KR_S) b = -(T * cv - C.eps_n - h * w.J[KR_S * KR_LDJ + KR_S + 1]);
+    else if (lane == KR_S) b = -(eps - C.eps_n - h * w.J[KR_S * KR_LDJ + KR_S + 1]);
     const int row = lane < KR_N ? lane : KR_S;
     double a[KR_N];
 #pragma unroll
     for (int k = 0; k < KR_N; ++k) a[k] = w.J[row * KR_LDJ + k];
     const bool er = lane == KR_S;
 #pragma unroll
-    for (int k = 0; k < KR_S; ++k) a[k] = (er ? kr_cv[k] * T : (lane == k ? 1.0 : 0.0)) - h * a[k];
+    for (int k = 0; k < KR_S; ++k) {
+      /* d eps / d n_k = e_k(T), from lane k */
+#if KR_CV_POLY
+      const double ek = kr_bcast(el, k);
+#else
+      const double ek = kr_cv[k] * T;
+#endif
+      a[k] = (er ? ek : (lane == k ? 1.0 : 0.0)) - h * a[k];
+    }
     a[KR_S] = (er ? cv : 0.0) - h * a[KR_S];
     if (lane >= KR_N) {
 #pragma unroll
@@ -734,14 +795,14 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
   double yn = y0;
   nacc = 0;
   hnext = 0.0;
-  C.eps_n = kr_bcast(y0, KR_S) * kr_u(kr_wheatcap(y0));
+  C.eps_n = kr_wenergy_of(y0);
   if (kr_ui(p.mode) == 1) {
     const int nf = kr_ui(p.n_fixed);
     const double h = C.dt / (double)nf;
     for (int k = 0; k < nf; ++k) {
       if (!kr_wnewton<MIXED>(p, w, C, yn, h, y)) { C.nfail++; return false; }
       yn = y;
-      C.eps_n = kr_bcast(yn, KR_S) * kr_u(kr_wheatcap(yn));
+      C.eps_n = kr_wenergy_of(yn);
       kr_wlog(p, C, k, h);
       C.acc++;
     }
@@ -774,7 +835,11 @@ __device__ __forceinline__ bool kr_wattempt(const KrParams &p, KrWave &w, KrWCel
     if (err <= 1.0) {
       yn = y;
       gn = g;
+#if KR_CV_POLY
+      C.eps_n = kr_wenergy_of(y);
+#else
       C.eps_n = kr_bcast(y, KR_S) * cv;
+#endif
       kr_wlog(p, C, nacc, h);
       nacc++;
       C.acc++;
@@ -1053,7 +1118,7 @@ __device__ __forceinline__ void kr_worder_keys(const KrParams &p, unsigned char 
     unsigned b = 0u;
     if (!kr_uany(bad) && dt > 0.0) {
       kr_wrhs(w, y);
-      const double eps = kr_bcast(y, KR_S) * kr_u(kr_wheatcap(y));
+      const double eps = kr_wenergy_of(y);
       const double sf = kr_u(kr_wsum(lane < KR_S ? fabs(w.J[lane * KR_LDJ + KR_S + 1]) : 0.0));
       const double sn = kr_u(kr_wsum(lane < KR_S ? y : 0.0));
       const double Q = w.J[KR_S * KR_LDJ + KR_S + 1];

@@ -500,6 +500,31 @@ def network_stromgren(isothermal: bool = False) -> NetworkDesc:
     return net
 
 
+PARSEC = 3.0857e18          # cm
+
+
+def cells_stromgren(net: NetworkDesc, n_cells: int, seed_index: int = 6):
+    """Cells of an H II region around the paper's fiducial source (Sec. 4.3:
+    Phi = 1e49 photons/s, cells of 1/4 pc): radius log-uniform [0.1, 16] pc,
+    optical depth to the source log-uniform [1e-4, 30], so F = Phi / (4 pi
+    r^2) e^-tau; n_H log-uniform [10, 1e4] cm^-3, ionised fraction x with
+    log10(x / (1 - x)) ~ U[-4, 4], T log-uniform [3e3, 5e4] K; path length
+    L = 1/4 pc; per-cell step log-uniform [1e8, 1e12] s.  Returns
+    (CellStates, photo_flux, photo_length)."""
+    rng = rng_for(seed_index, salt=3)
+    r = PARSEC * 10.0 ** rng.uniform(-1.0, np.log10(16.0), n_cells)
+    tau = 10.0 ** rng.uniform(-4.0, np.log10(30.0), n_cells)
+    F = 1.0e49 / (4.0 * np.pi * r * r) * np.exp(-tau)
+    nH = 10.0 ** rng.uniform(1.0, 4.0, n_cells)
+    lx = rng.uniform(-4.0, 4.0, n_cells)
+    x = 1.0 / (1.0 + 10.0 ** -lx)
+    T = 10.0 ** rng.uniform(np.log10(3e3), np.log10(5e4), n_cells)
+    n = np.vstack([nH * (1.0 - x), nH * x, nH * x])
+    dt = 10.0 ** rng.uniform(8.0, 12.0, n_cells)
+    L = np.full(n_cells, 0.25 * PARSEC)
+    return CellStates(n, T, _rho(net, n), dt), F, L
+
+
 def network_astro23(seed_index: int = 2) -> NetworkDesc:
     """23 species over rows H, He, C, O and charge (an astrochemistry-shaped
     ion-molecule network); 64 reversible reactions with at most 3 species

@@ -97,3 +97,78 @@ def test_derived_reverse_parameters_match_oracle(oracle_lib):
         assert abs(2.0 ** a2 / par[r, 1, 0] - 1.0) <= 2.5e-16 * (abs(a2) + 1.0)
         assert float.fromhex(b) == par[r, 1, 1]
         np.testing.assert_allclose(-float.fromhex(mc2) / np.log2(np.e), par[r, 1, 2], rtol=1e-15)
+
+
+def _literals(src, name):
+    body = src.split(f"kr_{name}[")[1].split("= {", 1)[1].split("};", 1)[0]
+    return np.array([float.fromhex(x) for x in re.findall(r"-?0x[0-9a-fp.+-]+", body)])
+
+
+def test_generated_heat_capacity_and_table_data():
+    """The network compiler carries c_V(T) and the tables into the device
+    source: the c_V coefficients as given, the energy's a_k / (k + 1), its
+    upper-piece constant making e_s continuous at T_mid, and the table values
+    as given (checked on the generated literals, no device needed)."""
+    kr = _kr()
+    desc = sy.network_h_o_n_tcv()
+    src = kr.network_check(desc)
+    assert "#define KR_CV_POLY 1" in src and "#define KR_NTAB 4" in src
+    S = desc.n_species
+    cvp = _literals(src, "cvp").reshape(S, 2, 5)
+    np.testing.assert_array_equal(cvp, desc.cv_poly)
+    evp = _literals(src, "evp").reshape(S, 2, 6)
+    k1 = np.arange(1, 6)
+    np.testing.assert_allclose(evp[:, :, :5], desc.cv_poly / k1, rtol=1e-15)
+    assert np.all(evp[:, 0, 5] == 0.0)
+    Tm = desc.T_mid
+    for s in range(S):
+        lo = Tm * np.polyval(evp[s, 0, 4::-1], Tm)
+        hi = Tm * np.polyval(evp[s, 1, 4::-1], Tm) + evp[s, 1, 5]
+        assert abs(lo - hi) <= 1e-12 * abs(lo)
+    tab = _literals(src, "tab").reshape(desc.tab_log2k.shape)
+    np.testing.assert_array_equal(tab, desc.tab_log2k)
+    # a network without them generates neither
+    plain = kr.network_check(sy.network_h_o_n(1))
+    assert "KR_CV_POLY 1" not in plain and "#define KR_NTAB 0" in plain
+
+
+def test_invalid_heat_capacity_and_tables_rejected():
+    kr = _kr()
+    for mutate in (lambda d: setattr(d, "T_mid", 0.0),
+                   lambda d: d.cv_poly.__setitem__((0, 0, 0), np.nan),
+                   lambda d: d.tab_of.__setitem__(3, 9),
+                   lambda d: d.tab_log2k.__setitem__((0, 0), np.inf),
+                   lambda d: setattr(d, "tab_dlog2T", -1.0)):
+        desc = sy.network_h_o_n_tcv()
+        mutate(desc)
+        with pytest.raises(kr.KrError) as e:
+            kr.network_check(desc)
+        assert e.value.code == kr.KR_EINVAL
+
+
+def test_photoreaction_code_and_validation():
+    """The network compiler emits the effective-flux evaluation, one cutoff
+    per absorber and the photoreaction's coefficient A F_eff (no reverse
+    direction), and refuses inconsistent photoreaction data."""
+    kr = _kr()
+    desc = sy.network_stromgren()
+    src = kr.network_check(desc)
+    assert "#define KR_PHOTO 1" in src and "kr_photo_flux(phF, phL, linv, Fe, dFe);" in src
+    assert src.count("const R cut") == 1                  # H is the only absorber
+    block = src.split("/* reaction 0 */")[1].split("/* reaction 1 */")[0]
+    assert "* Fe;" in block and "const R kr " not in block
+    assert float.fromhex(re.search(r"const R kf = R\((\S+)\) \* Fe;", block).group(1)) == sy.SIGMA_H
+    # extra heat: reaction 2 carries q0 + q1 T + q2 T ln T
+    assert "const R qx" in src.split("/* reaction 2 */")[1]
+    plain = kr.network_check(sy.network_h_o_n(1))
+    assert "KR_PHOTO 1" not in plain
+    for mutate in (lambda d: setattr(d, "sigma_abs", None),
+                   lambda d: d.arr_f.__setitem__((0, 1), 0.5),
+                   lambda d: d.photo.__setitem__(1, 2),
+                   lambda d: d.heat_extra.__setitem__((2, 0), np.inf)):
+        bad = sy.network_stromgren()
+        bad.arr_f = bad.arr_f.copy()
+        mutate(bad)
+        with pytest.raises(kr.KrError) as e:
+            kr.network_check(bad)
+        assert e.value.code == kr.KR_EINVAL
