@@ -610,6 +610,15 @@ static std::string arrhenius_code(const double *abc, const std::string &extra = 
   return "kr_exp2(" + x + ")";
 }
 
+/* FP32 overloads of the base-2 exponential and logarithm for the single- and
+ * mixed-precision modes (the hardware's instructions).  They sit at global
+ * scope beside the FP64 ones of kr_math.h: inside a network's namespace of a
+ * several-network source they would hide the FP64 overloads, and FP64
+ * arguments would silently round to FP32. */
+static const char kFloatMathSource[] =
+    "__device__ __forceinline__ float kr_exp2(float x) { return __builtin_amdgcn_exp2f(x); }\n"
+    "__device__ __forceinline__ float kr_log2(float x) { return __builtin_amdgcn_logf(x); }\n";
+
 /* The network-specific section of the lane-per-cell device source. */
 static std::string generate_network(const kr_network *n) {
   const int S = n->S, V = n->n_rows;
@@ -620,9 +629,7 @@ static std::string generate_network(const kr_network *n) {
 
   /* rates and analytic Jacobian, one block per reaction, in the working
    * precision R (FP64; FP32 for the single- and mixed-precision modes, whose
-   * exp2 and log2 are the hardware's) */
-  o += "__device__ __forceinline__ float kr_exp2(float x) { return __builtin_amdgcn_exp2f(x); }\n"
-       "__device__ __forceinline__ float kr_log2(float x) { return __builtin_amdgcn_logf(x); }\n";
+   * exp2 and log2 are the hardware's: kFloatMathSource) */
   o += "template <typename R>\n"
        "__device__ __forceinline__ void kr_eval(const R (&y)[KR_S + 1], R (&g)[KR_S + 1],\n"
        "                                        R (&J)[KR_S + 1][KR_S + 1], R phF = R(0), R phL = R(0)) {\n"
@@ -850,7 +857,8 @@ static std::string full_source(const kr_network *n, const kr_build_opts &o) {
            kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + lu_mfma_define(n, o) +
            generate_wide(n) + "\n" + kWideSource + "\n" + kAdvectSource;
   return std::string("/* per-cell implicit thermochemistry: network-specialised device code */\n") +
-         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_network(n) + "\n" +
+         build_prefix(w, o) + kParamsSource + "\n" + kMathSource + "\n" + kFloatMathSource + kOrderSource + "\n" +
+         generate_network(n) + "\n" +
          kDeviceSource +
          "\n" + kAdvectSource;
 }
@@ -1556,7 +1564,8 @@ static int multi_waves_per_eu(const std::vector<const kr_network *> &nets, const
 
 static std::string multi_source(const std::vector<const kr_network *> &nets, const kr_build_opts &o) {
   std::string s = "/* per-cell implicit thermochemistry: several networks in one launch */\n" +
-                  build_prefix(multi_waves_per_eu(nets, o), o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n";
+                  build_prefix(multi_waves_per_eu(nets, o), o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" +
+                  kMathSource + "\n" + kFloatMathSource + kOrderSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
     if (nets[k]->wide)
       s += "namespace kr_m" + std::to_string(k) + " {\n" + lu_mfma_define(nets[k], o) + generate_wide(nets[k]) +

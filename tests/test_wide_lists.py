@@ -155,6 +155,21 @@ def test_multi_kernels_grouped_by_occupancy_target():
     assert kernels([sy.network_astro23(2)]) == [("2", "0")]
 
 
+def test_fp32_math_overloads_outside_network_namespaces():
+    """The FP32 overloads of kr_exp2 / kr_log2 are declared once, at global
+    scope beside the FP64 ones: declared inside a network's namespace of a
+    several-network source, they would hide the FP64 overloads there and turn
+    every FP64 rate coefficient into an FP32 one."""
+    kr = _kr()
+    descs = [sy.network_h_he(0), sy.network_h_o_n_tcv(), sy.network_astro23(2)]
+    for src in (kr.multi_check(descs), kr.network_check(descs[1])):
+        first_ns = src.find("namespace kr_m")
+        for f in ("float kr_exp2(float", "float kr_log2(float"):
+            assert src.count(f) == 1, f
+            assert first_ns < 0 or src.index(f) < first_ns, f
+        assert src.index("double kr_exp2(double") < src.index("float kr_exp2(float")
+
+
 def test_blocked_lu_build_option():
     """lu_mfma=1 selects the blocked FP32 LU (MFMA trailing updates) where it
     applies -- the 48-species network in the wavefront layout -- and is
