@@ -220,7 +220,9 @@ def run_mixed(args):
                      "cell_stats": torch.empty((n, 4), dtype=torch.int32, device=dev)})
     setup_s = time.perf_counter() - t0
     report = None
-    layouts = [kr.KR_LAYOUT_AUTO] * len(descs)
+    layouts = [_layout_code(kr, L) for L in args.mix_layouts.split(",")]
+    if len(layouts) != len(descs):
+        raise SystemExit(f"--mix-layouts needs {len(descs)} entries")
     if args.autotune:
         # tuned on the whole batch: the layouts' relative speed depends on how
         # many cells each lane or wavefront gets (a 1/64 sample picked the
@@ -279,7 +281,7 @@ def run_mixed(args):
                                   f"dt = tau_fast*10^U[range] per network {list(MIX_U_RANGES)}, FP32 LU + "
                                   "FP64 refinement, one hipGraph launch (one persistent kernel per occupancy group)",
                       "build": [bo.waves_per_eu, bo.pivot_tau], "cell_order": args.order,
-                      "layouts": ["wave" if n.wide else "lane" for n in nets]},
+                      "layouts": [{1: "lane", 16: "group16", 32: "group32", 64: "wave"}[n.group] for n in nets]},
            "per_network": per_net, "graph": {"launches": launches, "captures": captures},
            "autotune": report, "setup_s": setup_s,
            "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": PEAK_FP64 / 1e12,
@@ -384,6 +386,14 @@ def run_large(args):
     net.close()
 
 
+LAYOUT_NAMES = ["auto", "lane", "wave", "group16", "group32"]
+
+
+def _layout_code(kr, name):
+    return {"auto": kr.KR_LAYOUT_AUTO, "lane": kr.KR_LAYOUT_LANE, "wave": kr.KR_LAYOUT_WAVE,
+            "group16": kr.KR_LAYOUT_GROUP16, "group32": kr.KR_LAYOUT_GROUP32}[name]
+
+
 def run_h_he(args):
     """Small case: 4096 cells of the 5-species H/He/charge network (10
     reversible reactions, 6 unknowns), each cell's step 1e3 times its own
@@ -396,8 +406,7 @@ def run_h_he(args):
     dev = torch.device("cuda", 0)
     desc = sy.network_h_he(0)
     cs = sy.cells_h_he(desc, args.cells, 0)
-    net = kr.Network(desc, kr.build_options(layout={"auto": kr.KR_LAYOUT_AUTO, "lane": kr.KR_LAYOUT_LANE,
-                                                    "wave": kr.KR_LAYOUT_WAVE}[args.layout]))
+    net = kr.Network(desc, kr.build_options(layout=_layout_code(kr, args.layout)))
     n0 = torch.tensor(cs.n, device=dev)
     T0 = torch.tensor(cs.T, device=dev)
     dt = 1e3 * kr.fastest_timescale(net, n0, T0)
@@ -713,7 +722,9 @@ def main():
                     choices=["h_o_n", "h_o_n_tcv", "h_he", "mixed", "large48", "calibrate", "advect",
                              "stromgren"])
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--layout", default="auto", choices=["auto", "lane", "wave"],
+    ap.add_argument("--mix-layouts", default="auto,auto,auto",
+                    help="per-network layouts of the uneven batch (5, 9, 23 species), from " + ",".join(LAYOUT_NAMES))
+    ap.add_argument("--layout", default="auto", choices=LAYOUT_NAMES,
                     help="h_he workload: the integrator layout")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)

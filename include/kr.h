@@ -196,6 +196,12 @@ void kr_network_destroy(kr_network *net);
  *                 wavefront layout holds the Newton matrix one row per lane
  *                 and needs n_species <= 62 and 5 * 2 * n_reactions
  *                 rounded up to 320 <= 4095 (n_reactions <= 384).
+ *                 KR_LAYOUT_GROUP16 / KR_LAYOUT_GROUP32: one cell per group
+ *                 of 16 / 32 lanes (4 / 2 cells per wavefront), rows as in
+ *                 the wavefront layout; needs n_species <= 14 / 30 besides
+ *                 the wavefront layout's limits, and supports what it
+ *                 supports (KR_FP64, KR_FP32LU_REFINE; its other kernels
+ *                 are the wavefront layout's).
  *   lu_mfma       1: the FP32 LU of the KR_FP32LU_REFINE form runs blocked,
  *                 its trailing updates on FP32 MFMA tiles (wavefront layout
  *                 with n_species >= 31, where the rate table's LDS holds the
@@ -206,6 +212,8 @@ void kr_network_destroy(kr_network *net);
 #define KR_LAYOUT_AUTO 0
 #define KR_LAYOUT_LANE 1
 #define KR_LAYOUT_WAVE 2
+#define KR_LAYOUT_GROUP16 3
+#define KR_LAYOUT_GROUP32 4
 #define KR_WIDE_MIN_SPECIES 16
 typedef struct {
   int32_t waves_per_eu;
@@ -221,7 +229,8 @@ int kr_network_create_ex(const kr_network_desc *desc, const kr_build_opts *opt,
 
 /* Number of unknowns per cell (n_species + 1: abundances and temperature). */
 int kr_network_unknowns(const kr_network *net);
-/* Layout the network was compiled for: KR_LAYOUT_LANE or KR_LAYOUT_WAVE. */
+/* Layout the network was compiled for: KR_LAYOUT_LANE, KR_LAYOUT_WAVE,
+ * KR_LAYOUT_GROUP16 or KR_LAYOUT_GROUP32. */
 int kr_network_layout(const kr_network *net);
 
 /* Derived Arrhenius table actually used: out[r][dir][3] = (A, b, E), dir 0

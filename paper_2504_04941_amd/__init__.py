@@ -27,7 +27,7 @@ KR_OK, KR_EINVAL, KR_EDEVICE, KR_ENOMEM, KR_ECOMPILE = 0, -1, -2, -3, -4
 KR_FP64, KR_FP32LU_REFINE, KR_SINGLE, KR_MIXED = 0, 1, 2, 3
 KR_ADAPTIVE, KR_FIXED_STEP = 0, 1
 KR_ORDER_INPUT, KR_ORDER_WORK = 0, 1
-KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE = 0, 1, 2
+KR_LAYOUT_AUTO, KR_LAYOUT_LANE, KR_LAYOUT_WAVE, KR_LAYOUT_GROUP16, KR_LAYOUT_GROUP32 = 0, 1, 2, 3, 4
 KR_WIDE_MIN_SPECIES = 16
 KR_NOALLOC_SCRATCH_BYTES = 8 << 20
 KR_NOALLOC_MAX_ORDER_CELLS = (KR_NOALLOC_SCRATCH_BYTES - 4096) // 5
@@ -276,7 +276,10 @@ class Network:
         self.n_species = d.n_species
         self.n_reactions = d.n_reactions
         self.n_unknowns = lib().kr_network_unknowns(h)
-        self.wide = lib().kr_network_layout(h) == KR_LAYOUT_WAVE
+        self.layout = lib().kr_network_layout(h)
+        # lanes per cell: 1, 16, 32 or 64
+        self.group = {KR_LAYOUT_LANE: 1, KR_LAYOUT_GROUP16: 16, KR_LAYOUT_GROUP32: 32}.get(self.layout, 64)
+        self.wide = self.group > 1
 
     @property
     def handle(self):

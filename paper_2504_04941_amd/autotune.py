@@ -1,8 +1,9 @@
 """Autotuner for the generated integrator kernels.
 
 Tunables (compile-time, `kr_build_opts`): per network, the layout (one cell
-per lane, or one cell per wavefront with the Newton matrix one row per
-lane); for the module, the occupancy target the register allocator budgets
+per lane; one cell per group of 16 or 32 lanes, or per wavefront, with the
+Newton matrix one row per lane: the lane-group shapes G = 1, 16, 32, 64
+that the network fits); for the module, the occupancy target the register allocator budgets
 for (waves per SIMD, or 0 for the library's per-layout choice; the lane's
 Newton matrix lives in VGPRs, so a higher target trades registers for
 scratch spills) and the threshold of the LU's
@@ -26,12 +27,27 @@ import json
 import os
 import time
 
-from . import (KR_LAYOUT_LANE, KR_LAYOUT_WAVE, KR_ORDER_INPUT, KR_ORDER_WORK, BuildOpts, Multi, Network,
-               build_options, chem_integrate, default_options, multi_check, network_check)
+from . import (KR_LAYOUT_GROUP16, KR_LAYOUT_GROUP32, KR_LAYOUT_LANE, KR_LAYOUT_WAVE, KR_ORDER_INPUT,
+               KR_ORDER_WORK, BuildOpts, KrError, Multi, Network, build_options, chem_integrate,
+               default_options, multi_check, network_check)
 
 CACHE = os.environ.get("KR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "kr_autotune.json"))
 CANDIDATES = [(0, 0.1), (1, 0.1), (1, 0.01), (2, 0.1)]   # (waves_per_eu, pivot_tau); 0 = automatic
+LAYOUTS = (KR_LAYOUT_LANE, KR_LAYOUT_GROUP16, KR_LAYOUT_GROUP32, KR_LAYOUT_WAVE)
+LAYOUT_NAMES = {KR_LAYOUT_LANE: "lane", KR_LAYOUT_GROUP16: "group16", KR_LAYOUT_GROUP32: "group32",
+                KR_LAYOUT_WAVE: "wave"}
+
+
+def layout_candidates(desc):
+    """The layouts (lane-group shapes) the network fits, with their sources."""
+    out = []
+    for L in LAYOUTS:
+        try:
+            out.append((L, network_check(desc, build=build_options(layout=L))))
+        except KrError:
+            pass
+    return out
 
 
 def _key(sources, precision):
@@ -76,11 +92,13 @@ def _time_call(fn, reps):
 
 
 def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log=None):
-    """Faster layout (KR_LAYOUT_LANE or KR_LAYOUT_WAVE) of one network on a
-    sample of its cells (batch: dict as for Multi.integrate, copied before
-    every timed run).  Returns (layout, report)."""
+    """Fastest layout (lane, 16- or 32-lane groups, wavefront: those the
+    network fits) of one network on a sample of its cells (batch: dict as
+    for Multi.integrate, copied before every timed run).  Returns (layout,
+    report)."""
     import torch
-    srcs = [network_check(desc, build=build_options(layout=L)) for L in (KR_LAYOUT_LANE, KR_LAYOUT_WAVE)]
+    cands = layout_candidates(desc)
+    srcs = [src for _, src in cands]
     # the answer depends on how many cells there are per lane or wavefront
     size_class = int(batch["T"].numel()).bit_length()
     key = "layout-" + _key(srcs + [str(size_class)], precision)
@@ -90,7 +108,7 @@ def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log
     opts = default_options(precision=precision)
     report = {"candidates": [], "sample_cells": int(batch["T"].numel())}
     best, best_t = None, float("inf")
-    for L in (KR_LAYOUT_LANE, KR_LAYOUT_WAVE):
+    for L, _ in cands:
         t0 = time.time()
         net = Network(desc, build_options(layout=L))
         compile_s = time.time() - t0
@@ -107,7 +125,7 @@ def tune_layout(desc, batch, precision=0, rtol=1e-6, reps=2, use_cache=True, log
         net.close()
         report["candidates"].append({"layout": L, "ms": ms, "compile_s": compile_s})
         if log:
-            log(f"autotune layout={'lane' if L == KR_LAYOUT_LANE else 'wave'}: {ms:.2f} ms "
+            log(f"autotune layout={LAYOUT_NAMES[L]}: {ms:.2f} ms "
                 f"(compile {compile_s:.1f} s)")
         if ms < best_t:
             best, best_t = L, ms
@@ -171,7 +189,7 @@ def tune_multi(descs, batches, precision=0, rtol=1e-6, candidates=CANDIDATES, re
         return build_options(waves_per_eu=int(w), pivot_tau=float(tau)), layouts, db[key]
     nets_cache = {}
     report = {"candidates": [], "sample_cells": [int(b["T"].numel()) for b in batches],
-              "layouts": ["lane" if L == KR_LAYOUT_LANE else "wave" for L in layouts],
+              "layouts": [LAYOUT_NAMES[L] for L in layouts],
               "layout_timings": lay_reports}
     best, best_t = None, float("inf")
     for w, tau in candidates:

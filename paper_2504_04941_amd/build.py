@@ -1,7 +1,8 @@
 """Builds libkr.so (host runtime, C ABI and ahead-of-time kernels) for gfx950.
 
 The integrator's device templates (csrc/kr_device.h: one cell per lane;
-csrc/kr_wide.h: one cell per wavefront), the rate-coefficient math
+csrc/kr_wide.h: one cell per wavefront; csrc/kr_group.h: one cell per lane
+group), the rate-coefficient math
 (csrc/kr_math.h), the cell-ordering kernels (csrc/kr_order.h), the
 species advection (csrc/kr_advect.h) and the
 launch-parameter struct (csrc/kr_params.h) are embedded into the library as string literals:
@@ -34,6 +35,7 @@ def build(verbose: bool = False) -> str:
     _embed("kr_device.h", "kr_device_src.inc")
     _embed("kr_params.h", "kr_params_src.inc")
     _embed("kr_wide.h", "kr_wide_src.inc")
+    _embed("kr_group.h", "kr_group_src.inc")
     _embed("kr_math.h", "kr_math_src.inc")
     _embed("kr_order.h", "kr_order_src.inc")
     _embed("kr_advect.h", "kr_advect_src.inc")

@@ -38,6 +38,9 @@ static const char *kDeviceSource =
 static const char *kWideSource =
 #include "kr_wide_src.inc"
     ;
+static const char *kGroupSource =
+#include "kr_group_src.inc"
+    ;
 static const char *kParamsSource =
 #include "kr_params_src.inc"
     ;
@@ -147,7 +150,9 @@ struct kr_network {
   hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr, f_adv = nullptr;
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0, occ_single = 0, occ_mixed = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
-  bool wide = false;            /* one wavefront per cell */
+  bool wide = false;            /* one wavefront per cell (also the lane-group layout's
+                                   other kernels) */
+  int group = 0;                /* lane-group layout: lanes per cell (16, 32), else 0 */
   OrderBufs ord;
   unsigned long long *d_counter = nullptr;
   unsigned long long *d_max = nullptr;
@@ -370,15 +375,16 @@ static std::vector<WideDir> wide_directions(const kr_network *n) {
  * lane, each lane's terms are concatenated with a flush mark on the last
  * term of every destination, and the lists are padded to equal length and
  * interleaved by lane (term i of lane l at i * 64 + l). */
-static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pair<int, int>>> &dst, int &len) {
+static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pair<int, int>>> &dst, int &len,
+                                        int lanes_n = 64) {
   std::vector<std::pair<int, int>> order; /* (terms, destination) */
   for (const auto &kv : dst) order.push_back({(int)kv.second.size(), kv.first});
   std::stable_sort(order.begin(), order.end(),
                    [](const std::pair<int, int> &a, const std::pair<int, int> &b) { return a.first > b.first; });
-  std::vector<std::vector<uint32_t>> lanes(64);
+  std::vector<std::vector<uint32_t>> lanes(lanes_n);
   for (const auto &od : order) {
     int best = 0;
-    for (int l = 1; l < 64; ++l)
+    for (int l = 1; l < lanes_n; ++l)
       if (lanes[l].size() < lanes[best].size()) best = l;
     const auto &terms = dst.at(od.second);
     for (size_t i = 0; i < terms.size(); ++i) {
@@ -390,9 +396,9 @@ static std::vector<uint32_t> wide_lists(const std::map<int, std::vector<std::pai
   len = 1;
   for (const auto &l : lanes) len = std::max(len, (int)l.size());
   len = (len + 7) / 8 * 8;   /* the gather fetches entries eight at a time */
-  std::vector<uint32_t> tab((size_t)len * 64, 4u << 25);
-  for (int l = 0; l < 64; ++l)
-    for (size_t i = 0; i < lanes[l].size(); ++i) tab[i * 64 + l] = lanes[l][i];
+  std::vector<uint32_t> tab((size_t)len * lanes_n, 4u << 25);
+  for (int l = 0; l < lanes_n; ++l)
+    for (size_t i = 0; i < lanes[l].size(); ++i) tab[i * lanes_n + l] = lanes[l][i];
   return tab;
 }
 
@@ -407,12 +413,14 @@ static int check_wide(const kr_network *n) {
   return KR_OK;
 }
 
-/* The network-specific section of the wavefront-per-cell device source. */
-static std::string generate_wide(const kr_network *n) {
+/* Jacobian contributions of the reaction directions: destination entry of
+ * the LDS Jacobian (row stride LDJ) -> (source in the rate table P, 5
+ * entries per direction; net stoichiometric coefficient), for the full
+ * Jacobian and for the rates alone. */
+static void wide_contributions(const kr_network *n, const std::vector<WideDir> &dirs,
+                               std::map<int, std::vector<std::pair<int, int>>> &full,
+                               std::map<int, std::vector<std::pair<int, int>>> &fonly) {
   const int S = n->S, LDJ = wide_ldj(S);
-  const std::vector<WideDir> dirs = wide_directions(n);
-  const int NDR = std::max<int>(1, (int)((dirs.size() + 63) / 64)), NDP = NDR * 64;
-  std::map<int, std::vector<std::pair<int, int>>> full, fonly;
   for (size_t d = 0; d < dirs.size(); ++d) {
     const int src = 5 * (int)d;
     for (int s = 0; s < S; ++s) {
@@ -425,6 +433,15 @@ static std::string generate_wide(const kr_network *n) {
         if (dirs[d].slot[k] >= 0) full[s * LDJ + dirs[d].slot[k]].push_back({src + 2 + k, nu});
     }
   }
+}
+
+/* The network-specific section of the wavefront-per-cell device source. */
+static std::string generate_wide(const kr_network *n) {
+  const int S = n->S, LDJ = wide_ldj(S);
+  const std::vector<WideDir> dirs = wide_directions(n);
+  const int NDR = std::max<int>(1, (int)((dirs.size() + 63) / 64)), NDP = NDR * 64;
+  std::map<int, std::vector<std::pair<int, int>>> full, fonly;
+  wide_contributions(n, dirs, full, fonly);
   int NC = 0, NF = 0;
   const std::vector<uint32_t> wc = wide_lists(full, NC), wf = wide_lists(fonly, NF);
   std::string o;
@@ -465,6 +482,41 @@ static std::string generate_wide(const kr_network *n) {
   }
   o += "};\n";
   const std::pair<const char *, const std::vector<uint32_t> *> lists[2] = {{"kr_wc", &wc}, {"kr_wf", &wf}};
+  for (const auto &l : lists) {
+    o += std::string("__device__ static constexpr unsigned ") + l.first + "[" + std::to_string(l.second->size()) +
+         "] = {";
+    for (size_t i = 0; i < l.second->size(); ++i)
+      o += std::to_string((*l.second)[i]) + "u" + (i + 1 < l.second->size() ? "," : "");
+    o += "};\n";
+  }
+  return o;
+}
+
+/* The lane-group layout's section (after the wavefront layout's, whose
+ * direction tables it reads): G lanes per cell, direction rounds of G, the
+ * reactant slots with the empty slot at the group's spare lane G - 1, and
+ * the contribution lists balanced over G lanes. */
+static std::string generate_group(const kr_network *n, int G) {
+  const std::vector<WideDir> dirs = wide_directions(n);
+  const int GNDR = std::max<int>(1, (int)((dirs.size() + G - 1) / G));
+  std::map<int, std::vector<std::pair<int, int>>> full, fonly;
+  wide_contributions(n, dirs, full, fonly);
+  int NC = 0, NF = 0;
+  const std::vector<uint32_t> gc = wide_lists(full, NC, G), gf = wide_lists(fonly, NF, G);
+  std::string o = "/* lane-group layout: " + std::to_string(G) + " lanes per cell */\n";
+  o += "#define KR_G " + std::to_string(G) + "\n#define KR_GNDR " + std::to_string(GNDR) + "\n#define KR_GNC " +
+       std::to_string(NC) + "\n#define KR_GNF " + std::to_string(NF) + "\n";
+  o += "__device__ static constexpr unsigned kr_gdr[" + std::to_string(GNDR * G) + "] = {";
+  for (int d = 0; d < GNDR * G; ++d) {
+    uint32_t r = 0;
+    for (int k = 0; k < 3; ++k) {
+      const int sl = d < (int)dirs.size() ? dirs[d].slot[k] : -1;
+      r |= (uint32_t)(sl >= 0 ? sl : G - 1) << (8 * k);
+    }
+    o += std::to_string(r) + "u" + (d + 1 < GNDR * G ? "," : "");
+  }
+  o += "};\n";
+  const std::pair<const char *, const std::vector<uint32_t> *> lists[2] = {{"kr_gc", &gc}, {"kr_gf", &gf}};
   for (const auto &l : lists) {
     o += std::string("__device__ static constexpr unsigned ") + l.first + "[" + std::to_string(l.second->size()) +
          "] = {";
@@ -793,7 +845,7 @@ extern "C" void kr_default_build_options(kr_build_opts *o) {
 static int check_build_options(const kr_build_opts *o) {
   if (o->waves_per_eu < 0 || o->waves_per_eu > 8) return fail(KR_EINVAL, "waves_per_eu out of [0, 8]");
   if (!(o->pivot_tau > 0.0f && o->pivot_tau <= 1.0f)) return fail(KR_EINVAL, "pivot_tau out of (0, 1]");
-  if (o->layout < KR_LAYOUT_AUTO || o->layout > KR_LAYOUT_WAVE) return fail(KR_EINVAL, "layout out of [0, 2]");
+  if (o->layout < KR_LAYOUT_AUTO || o->layout > KR_LAYOUT_GROUP32) return fail(KR_EINVAL, "layout out of [0, 4]");
   if (o->lu_mfma != 0 && o->lu_mfma != 1) return fail(KR_EINVAL, "lu_mfma must be 0 or 1");
   return KR_OK;
 }
@@ -817,8 +869,28 @@ static bool lu_mfma_fits(int S, int n_dirs) {
   return need <= 5 * ndp * 8;
 }
 
+/* Lanes per cell of the lane-group layout the options select, else 0. */
+static int group_lanes(const kr_build_opts &o) {
+  return o.layout == KR_LAYOUT_GROUP16 ? 16 : (o.layout == KR_LAYOUT_GROUP32 ? 32 : 0);
+}
+
 static bool use_wide(const kr_network *n, const kr_build_opts &o) {
-  return o.layout == KR_LAYOUT_WAVE || (o.layout == KR_LAYOUT_AUTO && n->S >= KR_WIDE_MIN_SPECIES);
+  return o.layout == KR_LAYOUT_WAVE || group_lanes(o) > 0 ||
+         (o.layout == KR_LAYOUT_AUTO && n->S >= KR_WIDE_MIN_SPECIES);
+}
+
+/* The lane-group layout holds a cell's N = S + 1 rows on G lanes with one
+ * lane to spare (the empty reactant slot and the energy row's last column). */
+static int check_group(const kr_network *n, int G) {
+  if (n->S + 2 > G)
+    return fail(KR_EINVAL, "the %d-lane group layout takes at most %d species (got %d)", G, G - 2, n->S);
+  return KR_OK;
+}
+
+/* LDS of one lane-group block (KrGBlock), bytes */
+static int group_block_bytes(const kr_network *n, int G) {
+  const int gndr = std::max<int>(1, (int)((wide_directions(n).size() + G - 1) / G));
+  return 8 * (G + 5 * gndr * G + (n->S + 1) * wide_ldj(n->S));
 }
 
 /* Automatic occupancy target of one network's integrator.  Lane layout: one
@@ -839,6 +911,10 @@ static int wide_block_bytes(const kr_network *n) {
 static int auto_waves_per_eu(const kr_network *n, const kr_build_opts &o) {
   if (o.waves_per_eu > 0) return o.waves_per_eu;
   if (!use_wide(n, o)) return 1;
+  if (const int G = group_lanes(o)) {
+    const int per_simd = 160 * 1024 / 4 / ((64 / G) * group_block_bytes(n, G));
+    return std::max(1, std::min(2, per_simd));
+  }
   const int per_simd = 160 * 1024 / 4 / wide_block_bytes(n);
   return std::max(1, std::min(2, per_simd));
 }
@@ -852,6 +928,11 @@ static std::string lu_mfma_define(const kr_network *n, const kr_build_opts &o) {
 
 static std::string full_source(const kr_network *n, const kr_build_opts &o) {
   const int w = auto_waves_per_eu(n, o);
+  if (const int G = group_lanes(o))
+    return std::string("/* per-cell implicit thermochemistry, one cell per lane group */\n") + build_prefix(w, o) +
+           kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + generate_wide(n) + "\n" +
+           generate_group(n, G) + "#define KR_NO_KERNELS\n" + kWideSource + "\n#undef KR_NO_KERNELS\n" +
+           kGroupSource + "\n" + kAdvectSource;
   if (use_wide(n, o))
     return std::string("/* per-cell implicit thermochemistry, one wavefront per cell */\n") + build_prefix(w, o) +
            kParamsSource + "\n" + kMathSource + "\n" + kOrderSource + "\n" + lu_mfma_define(n, o) +
@@ -891,7 +972,9 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
     n->build = bo;
     n->build.waves_per_eu = auto_waves_per_eu(n, bo);
     n->wide = use_wide(n, bo);
+    n->group = group_lanes(bo);
     if (n->wide && (rc = check_wide(n)) != KR_OK) { delete n; return rc; }
+    if (n->group && (rc = check_group(n, n->group)) != KR_OK) { delete n; return rc; }
     n->source = full_source(n, bo);
     std::vector<char> code;
     std::string log;
@@ -965,7 +1048,9 @@ extern "C" int kr_network_unknowns(const kr_network *net) {
 
 extern "C" int kr_network_layout(const kr_network *net) {
   try {
-    return net ? (net->wide ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE) : KR_EINVAL;
+    if (!net) return KR_EINVAL;
+    if (net->group) return net->group == 16 ? KR_LAYOUT_GROUP16 : KR_LAYOUT_GROUP32;
+    return net->wide ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE;
   } KR_CATCH
 }
 
@@ -1004,6 +1089,7 @@ extern "C" int kr_network_check_ex(const kr_network_desc *desc, const kr_build_o
     if (bopt) bo = *bopt;
     if ((rc = check_build_options(&bo)) != KR_OK) return rc;
     if (use_wide(&n, bo) && (rc = check_wide(&n)) != KR_OK) return rc;
+    if (group_lanes(bo) && (rc = check_group(&n, group_lanes(bo))) != KR_OK) return rc;
     const std::string src = full_source(&n, bo);
     if (src_buf && src_len > 0) {
       const size_t m = std::min<size_t>((size_t)src_len - 1, src.size());
@@ -1221,7 +1307,9 @@ static int integrate_impl(const kr_network *net, int64_t n_cells, double *states
   hipFunction_t f = fs[o.precision];
   const int occ = occs[o.precision];
   long long blocks = (long long)net->cu_count * (occ > 0 ? occ : 1);
-  const long long need = net->wide ? n_cells : (n_cells + 63) / 64;   /* cells per wave: 1 or 64 */
+  /* waves with work: 64 cells per wave (lane layout), 64 / G (lane groups), 1 (wavefront) */
+  const long long cpw = net->group ? 64 / net->group : (net->wide ? 1 : 64);
+  const long long need = (n_cells + cpw - 1) / cpw;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
   void *args[] = {&p};
@@ -1540,7 +1628,9 @@ static std::vector<std::pair<int, std::vector<int>>> multi_groups(const std::vec
   std::vector<int> members[2];
   for (size_t k = 0; k < nets.size(); ++k) {
     const int g = nets[k]->wide ? 1 : 0;
-    const kr_build_opts ok{o.waves_per_eu, o.pivot_tau, g ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE, o.lu_mfma};
+    const int L = nets[k]->group ? (nets[k]->group == 16 ? KR_LAYOUT_GROUP16 : KR_LAYOUT_GROUP32)
+                                 : (g ? KR_LAYOUT_WAVE : KR_LAYOUT_LANE);
+    const kr_build_opts ok{o.waves_per_eu, o.pivot_tau, L, o.lu_mfma};
     w[g] = std::min(w[g], auto_waves_per_eu(nets[k], ok));
     members[g].push_back((int)k);
   }
@@ -1567,7 +1657,14 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
                   build_prefix(multi_waves_per_eu(nets, o), o) + "#define KR_NO_KERNELS\n" + kParamsSource + "\n" +
                   kMathSource + "\n" + kFloatMathSource + kOrderSource + "\n";
   for (size_t k = 0; k < nets.size(); ++k) {
-    if (nets[k]->wide)
+    if (nets[k]->group)
+      s += "namespace kr_m" + std::to_string(k) + " {\n" + generate_wide(nets[k]) + "\n" +
+           generate_group(nets[k], nets[k]->group) + kWideSource + "\n" + kGroupSource +
+           "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n#undef KR_LDJ\n#undef KR_NDR\n"
+           "#undef KR_NC\n#undef KR_NF\n#undef KR_NDP\n#undef KR_NOTPIV\n#undef KR_CV_POLY\n#undef KR_NTAB\n"
+           "#undef KR_TAB_NODES\n#undef KR_G\n#undef KR_GNDR\n#undef KR_GNC\n#undef KR_GNF\n#undef KR_H\n"
+           "#undef KR_GLOG\n#undef KR_GMASK\n";
+    else if (nets[k]->wide)
       s += "namespace kr_m" + std::to_string(k) + " {\n" + lu_mfma_define(nets[k], o) + generate_wide(nets[k]) +
            "\n" + kWideSource +
            "\n}\n#undef KR_S\n#undef KR_NROWS\n#undef KR_NELEM\n#undef KR_N\n#undef KR_LDJ\n#undef KR_NDR\n"
@@ -1593,8 +1690,9 @@ static std::string multi_source(const std::vector<const kr_network *> &nets, con
       for (size_t j = 0; j < mem.size(); ++j) {
         const int k = mem[j];
         s += "      case " + std::to_string(j) + ": if (" + std::to_string(k) + " < m.n_nets) kr_m" + std::to_string(k) +
-             (nets[k]->wide ? (mixed ? "::kr_wintegrate<true" : "::kr_wintegrate<false")
-                            : (mixed ? "::kr_integrate_body<1" : "::kr_integrate_body<0")) +
+             (nets[k]->group ? (mixed ? "::kr_gintegrate<true" : "::kr_gintegrate<false")
+              : nets[k]->wide ? (mixed ? "::kr_wintegrate<true" : "::kr_wintegrate<false")
+                              : (mixed ? "::kr_integrate_body<1" : "::kr_integrate_body<0")) +
              ">(m.net[" + std::to_string(k) + "]); break;\n";
       }
       s += "      default: break;\n    }\n  }\n}\n";
@@ -1797,9 +1895,11 @@ extern "C" int kr_chem_integrate_multi(kr_multi *m, const kr_batch *batches, dou
     for (int g = 0; g < n_groups; ++g) {
       f[g] = o.precision == KR_FP64 ? m->f_fp64[g] : m->f_fp32[g];
       const int occ = o.precision == KR_FP64 ? m->occ_fp64[g] : m->occ_fp32[g];
-      long long need = 0;   /* waves with work: 64 cells per wave, or one per wave (wavefront layout) */
-      for (int k : m->groups[g])
-        need += m->nets[k]->wide ? batches[k].n_cells : (batches[k].n_cells + 63) / 64;
+      long long need = 0;   /* waves with work: 64 cells per wave, 64 / G (lane groups), 1 (wavefront) */
+      for (int k : m->groups[g]) {
+        const long long cpw = m->nets[k]->group ? 64 / m->nets[k]->group : (m->nets[k]->wide ? 1 : 64);
+        need += (batches[k].n_cells + cpw - 1) / cpw;
+      }
       blocks[g] = std::min<long long>((long long)m->cu_count * (occ > 0 ? occ : 1), need);   /* 0: no work */
     }
     /* largest-work-first order of each batch: buffers reserved here, outside

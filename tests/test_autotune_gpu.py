@@ -1,5 +1,5 @@
-"""The project's autotuner on small samples: per-network layout choice
-(timed on the network's own cells) and the module build options, without the
+"""The project's autotuner on small samples: per-network layout choice among
+the lane-group shapes the network fits (timed on the network's own cells) and the module build options, without the
 on-disk cache; the chosen configuration still matches the oracle."""
 import numpy as np
 import pytest
@@ -30,7 +30,9 @@ def test_tune_layout_and_multi(oracle_lib):
         dts.append(np.array([1e-2 * on.fastest_timescale(np.r_[cs.n[:, c], cs.T[c]])
                              for c in range(cs.n_cells)]))
     L, rep = autotune.tune_layout(descs[1], _batch(css[1], dts[1]), use_cache=False)
-    assert L in (kr.KR_LAYOUT_LANE, kr.KR_LAYOUT_WAVE) and len(rep["candidates"]) == 2
+    # the lane-group shapes the 23-species network fits: 1, 32 and 64 lanes
+    assert [c["layout"] for c in rep["candidates"]] == [kr.KR_LAYOUT_LANE, kr.KR_LAYOUT_GROUP32, kr.KR_LAYOUT_WAVE]
+    assert L == min(rep["candidates"], key=lambda c: c["ms"])["layout"]
     bo, layouts, report = autotune.tune_multi(descs, [_batch(c, d) for c, d in zip(css, dts)],
                                               candidates=[(1, 0.1)], use_cache=False)
     assert len(layouts) == 2 and report["best"] == [1, 0.1]

@@ -8,8 +8,9 @@
 * the per-call totals (kr_stats) against the per-cell statistics;
 * post-processing alone (kr_postprocess, Sec. 2.2.3) in full waves of cells
   built so that stages 1-3 act, against the oracle's stages and flags;
-* the retry ladder's successful branch (status 1) in both layouts on cells
-  chosen with the oracle."""
+* the retry ladder's successful branch (status 1) in every layout on cells
+  chosen with the oracle (the lane-group layout in 16- and 32-lane groups
+  wherever the network fits)."""
 import numpy as np
 import pytest
 
@@ -30,7 +31,10 @@ def _dev(a, dtype=torch.float64):
 
 
 def _layout(kr, wave):
-    return kr.build_options(layout=kr.KR_LAYOUT_WAVE if wave else kr.KR_LAYOUT_LANE)
+    """False: one cell per lane, True: per wavefront, "group16" / "group32":
+    per lane group"""
+    return kr.build_options(layout={False: kr.KR_LAYOUT_LANE, True: kr.KR_LAYOUT_WAVE,
+                                    "group16": kr.KR_LAYOUT_GROUP16, "group32": kr.KR_LAYOUT_GROUP32}[wave])
 
 
 def _run(desc, cs, build, dt=None, dt_scalar=0.0, cap=0, hint=None, stats=False, **opt):
@@ -63,7 +67,7 @@ def _gpu_tuple(g):
     return g["n"], g["T"], g["status"], g["stats"], g["resid"]
 
 
-CASES = [("h_o_n", False), ("h_o_n", True), ("astro23", True)]
+CASES = [("h_o_n", False), ("h_o_n", True), ("astro23", True), ("h_o_n", "group16"), ("astro23", "group32")]
 
 
 def _inputs(oracle, which, ncell):
@@ -111,7 +115,7 @@ def test_substep_log_replayed_by_oracle(oracle_lib, which, wave):
                   f"{which} replay", desc=desc)
 
 
-@pytest.mark.parametrize("wave", [False, True])
+@pytest.mark.parametrize("wave", [False, True, "group16", "group32"])
 def test_h_hint_in_and_out(oracle_lib, wave):
     """A positive hint is the first substep of the first attempt; zero or NaN
     hints are ignored; the proposal out matches the oracle's where the two
@@ -284,7 +288,7 @@ def test_postprocess_matches_oracle(oracle_lib, which, wave):
 STATUS1_CELLS = [34, 475, 496, 576, 651]
 
 
-@pytest.mark.parametrize("wave", [False, True])
+@pytest.mark.parametrize("wave", [False, True, "group16", "group32"])
 def test_retry_success_status_1(oracle_lib, wave):
     kr = _kr()
     desc = sy.network_h_o_n(1)

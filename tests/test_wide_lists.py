@@ -1,4 +1,5 @@
-"""Host-side checks of the wavefront layout's generated tables (no GPU):
+"""Host-side checks of the wavefront and lane-group layouts' generated
+tables (no GPU):
 the per-lane contribution lists rebuild exactly the rate-Jacobian terms the
 network implies, every destination entry is owned by one lane and closed by
 a flush mark, and the direction tables hold the derived Arrhenius
@@ -54,12 +55,12 @@ def _expected(desc, par, S, LDJ):
     return dirs, full, fonly
 
 
-def _decode(tab, length):
+def _decode(tab, length, lanes=64):
     got, owner = defaultdict(list), {}
-    for lane in range(64):
+    for lane in range(lanes):
         open_dst = None
         for i in range(length):
-            e = tab[i * 64 + lane]
+            e = tab[i * lanes + lane]
             src, dst, nu, fl = e & 4095, (e >> 12) & 8191, ((e >> 25) & 7) - 4, e >> 28
             if nu == 0 and not fl:
                 continue                       # padding
@@ -102,6 +103,51 @@ def test_contribution_lists_rebuild_the_jacobian_terms(oracle_lib, make):
         slots = [(ut["dr"][i] >> (8 * k)) & 255 for k in range(3)]
         assert slots == [m if m >= 0 else 63 for m in re_]   # 63: an empty slot (reads 1.0)
     assert all(a == -4096.0 for a in dt["da2"][len(dirs):])
+
+
+@pytest.mark.parametrize("make,G", [(lambda: sy.network_h_o_n(1), 16), (lambda: sy.network_h_o_n(1), 32),
+                                    (lambda: sy.network_astro23(2), 32), (lambda: sy.network_h_he(0), 16)])
+def test_group_lists_rebuild_the_jacobian_terms(oracle_lib, make, G):
+    """Lane-group layout: contribution lists balanced over G lanes rebuild
+    the same Jacobian terms; reactant slots with the empty slot at the
+    group's spare lane G - 1; direction rounds of G."""
+    kr = _kr()
+    desc = make()
+    src = kr.network_check(desc, build=kr.build_options(layout=kr.KR_LAYOUT_GROUP16 if G == 16
+                                                              else kr.KR_LAYOUT_GROUP32))
+    defs = {k: int(v) for k, v in re.findall(r"#define KR_(S|LDJ|G|GNDR|GNC|GNF) (\d+)", src)}
+    assert defs["G"] == G and defs["S"] + 2 <= G
+
+    def arr(name):
+        m = re.search(r"kr_%s\[(\d+)\] = \{([^}]*)\}" % name, src)
+        return [int(x.rstrip("u")) for x in m.group(2).split(",")]
+    S, LDJ = defs["S"], defs["LDJ"]
+    par = oracle_lib.OracleNet(desc).arrhenius()
+    dirs, full, fonly = _expected(desc, par, S, LDJ)
+    assert defs["GNDR"] == max(1, -(-len(dirs) // G))
+    got = _decode(arr("gc"), defs["GNC"], G)
+    assert {k: sorted(v) for k, v in got.items()} == {k: sorted(v) for k, v in full.items()}
+    gotf = _decode(arr("gf"), defs["GNF"], G)
+    assert {k: sorted(v) for k, v in gotf.items()} == {k: sorted(v) for k, v in fonly.items()}
+    assert max(full) < (S + 1) * LDJ               # destinations inside the block's Jacobian
+    gdr = arr("gdr")
+    assert len(gdr) == defs["GNDR"] * G
+    for i in range(len(gdr)):
+        re_ = dirs[i][2] if i < len(dirs) else [-1, -1, -1]
+        assert [(gdr[i] >> (8 * k)) & 255 for k in range(3)] == [m if m >= 0 else G - 1 for m in re_]
+
+
+def test_group_layout_limits_and_compiles():
+    kr = _kr()
+    for G, L in ((16, kr.KR_LAYOUT_GROUP16), (32, kr.KR_LAYOUT_GROUP32)):
+        with pytest.raises(kr.KrError) as e:
+            kr.network_check(sy.network_large48(3) if G == 32 else sy.network_astro23(2),
+                             build=kr.build_options(layout=L))
+        assert e.value.code == kr.KR_EINVAL
+    src = kr.network_check(sy.network_astro23(2), compile=True, build=kr.build_options(layout=kr.KR_LAYOUT_GROUP32))
+    assert "one cell per lane group" in src
+    with pytest.raises(kr.KrError):
+        kr.network_check(sy.network_h_he(0), build=kr.build_options(layout=5))
 
 
 def test_wave_layout_compiles_for_gfx950():
