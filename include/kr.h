@@ -189,10 +189,12 @@ void kr_network_destroy(kr_network *net);
  *                 pivot_tau times the best candidate's (lane-per-cell
  *                 layout; the wave-per-cell LU takes the best candidate)
  *   layout        KR_LAYOUT_AUTO: one cell per lane below
- *                 KR_WIDE_MIN_SPECIES species, one cell per wavefront from
- *                 there (measured on gfx950: the lane layout is 2-10x
+ *                 KR_WIDE_MIN_SPECIES species, one cell per 32-lane group
+ *                 from there up to 30 species, one cell per wavefront
+ *                 beyond (measured on gfx950: the lane layout is 2-10x
  *                 faster at 5 and 9 species, the wavefront layout 5x faster
- *                 at 23); KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
+ *                 at 23, 32-lane groups another 8-15 % at 23);
+ *                 KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
  *                 wavefront layout holds the Newton matrix one row per lane
  *                 and needs n_species <= 62 and 5 * 2 * n_reactions
  *                 rounded up to 320 <= 4095 (n_reactions <= 384).

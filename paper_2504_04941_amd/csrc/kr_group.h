@@ -74,6 +74,66 @@ __device__ __forceinline__ float kr_gbc(float v, int src) { return __shfl(v, src
 __device__ __forceinline__ int kr_gbc(int v, int src) { return __shfl(v, src, KR_G); }
 __device__ __forceinline__ long long kr_gbc(long long v, int src) { return __shfl(v, src, KR_G); }
 
+/* v of lane s of the lane's own group, s the same for every group (a
+ * constant or a wavefront-uniform value): one readlane per group, no LDS
+ * round trip */
+template <typename F>
+__device__ __forceinline__ F kr_gat(F v, int s) {
+  F out = kr_wbc(v, s);
+#pragma unroll
+  for (int h = 1; h < KR_H; ++h) {
+    const F x = kr_wbc(v, h * KR_G + s);
+    out = (int)threadIdx.x >= h * KR_G ? x : out;
+  }
+  return out;
+}
+
+/* v of lane src of the lane's own group, src the same within each group:
+ * the groups' sources are read out as scalars, then one readlane per
+ * group (a short dependency chain, for the LU's and solves' critical
+ * paths) */
+template <typename F>
+__device__ __forceinline__ F kr_gpick(F v, int src) {
+  F out = kr_wbc(v, __builtin_amdgcn_readlane(src, 0));
+#pragma unroll
+  for (int h = 1; h < KR_H; ++h) {
+    const F x = kr_wbc(v, h * KR_G + __builtin_amdgcn_readlane(src, h * KR_G));
+    out = (int)threadIdx.x >= h * KR_G ? x : out;
+  }
+  return out;
+}
+
+/* v of the lane of the own group where c holds (its lowest such lane; lane
+ * 0 of the group if none) */
+template <typename F>
+__device__ __forceinline__ F kr_gwhere(F v, bool c) {
+  const unsigned long long bal = __ballot(c);
+  F out = v;
+#pragma unroll
+  for (int h = 0; h < KR_H; ++h) {
+    const unsigned bits = (unsigned)(bal >> (h * KR_G)) & KR_GMASK;
+    const F x = kr_wbc(v, h * KR_G + (bits ? __builtin_ctz(bits) : 0));
+    out = h == 0 ? x : ((int)threadIdx.x >= h * KR_G ? x : out);
+  }
+  return out;
+}
+
+#if KR_G == 32
+/* the value of the lane 16 apart in the same 32-lane group (the other row):
+ * v_permlane16_swap exchanges the odd rows of its first operand with the
+ * even rows of its second, so with both operands v the first result holds
+ * rows (0, 0, 2, 2) and the second rows (1, 1, 3, 3) */
+__device__ __forceinline__ unsigned kr_gx16(unsigned v) {
+  const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16u) ? (unsigned)sw[0] : (unsigned)sw[1];
+}
+__device__ __forceinline__ double kr_gx16(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = kr_gx16((unsigned)b), hi = kr_gx16((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+#endif
+
 /* Group sum: quad permutes and the half-row and row mirrors leave every lane
  * of a 16-lane row with the row's sum (each pair of lanes adds the same two
  * values, so all lanes hold the same bits); a 32-lane group adds the other
@@ -84,7 +144,7 @@ __device__ __forceinline__ double kr_gsum(double v) {
   v += kr_dpp<0x141, 0xF>(v);
   v += kr_dpp<0x140, 0xF>(v);
 #if KR_G == 32
-  v += __shfl_xor(v, 16, 64);
+  v += kr_gx16(v);
 #endif
   return v;
 }
@@ -96,7 +156,7 @@ __device__ __forceinline__ double kr_gmax(double v) {
   v = fmax(v, kr_dpp<0x141, 0xF>(v));
   v = fmax(v, kr_dpp<0x140, 0xF>(v));
 #if KR_G == 32
-  v = fmax(v, __shfl_xor(v, 16, 64));
+  v = fmax(v, kr_gx16(v));
 #endif
   return v;
 }
@@ -117,7 +177,7 @@ __device__ __forceinline__ int kr_gargmax(float key, bool cand, unsigned &best) 
   k = kr_dpp_max<0x140, 0xF>(k);
 #if KR_G == 32
   {
-    const unsigned o = (unsigned)__shfl_xor((int)k, 16, 64);
+    const unsigned o = kr_gx16(k);
     k = o > k ? o : k;
   }
 #endif
@@ -247,7 +307,7 @@ __device__ __forceinline__ void kr_gspecies(double T, double &el, double &cl) {
 /* c_V and thermal energy eps of the lane-distributed point */
 __device__ __forceinline__ void kr_gthermo(double yl, double &cv, double &eps, double &el) {
   const int r = kr_glane();
-  const double T = kr_gbc(yl, KR_S);
+  const double T = kr_gat(yl, KR_S);
   double cl;
   kr_gspecies(T, el, cl);
   cv = kr_gsum(r < KR_S ? cl * yl : 0.0);
@@ -279,34 +339,34 @@ __device__ __forceinline__ bool kr_glu_impl(F (&a)[KR_N], int &pc, F &dinv, F &b
     unsigned best;
     const int p = kr_gargmax(fabsf((float)(fabs((double)aj) * (double)sc)), cand, best);
     ok = ok && (best >> KR_GLOG) != 0u;
-    const F piv = kr_gbc(aj, p);
+    /* the pivot, the next column's entry (the next arg-max waits for it) and
+     * the carried right-hand side by readlane; the rest of the pivot row by
+     * shuffles, off the critical path */
+    const F piv = kr_gpick(aj, p);
     ok = ok && piv != F(0) && kr_finite((double)piv);
     const F inv = kr_wrcp(piv);
     if (r == p) { pc = j; dinv = inv; }
     const F l = pc == KR_NOTPIV ? aj * inv : F(0);
     if (pc == KR_NOTPIV) a[j] = l;
-    if (AUG) b = fma(-l, kr_gbc(b, p), b);
+    if (AUG) b = fma(-l, kr_gpick(b, p), b);
+    if (j + 1 < KR_N) a[j + 1] = fma(-l, kr_gpick(a[j + 1], p), a[j + 1]);
 #pragma unroll
-    for (int k = j + 1; k < KR_N; ++k) a[k] = fma(-l, kr_gbc(a[k], p), a[k]);
+    for (int k = j + 2; k < KR_N; ++k) a[k] = fma(-l, kr_gbc(a[k], p), a[k]);
   }
   return ok;
 }
 
-/* Lane of the group whose row became pivot row at column j (0 if none: a
- * failed factorisation, whose solve is discarded). */
-__device__ __forceinline__ int kr_gpivot_lane(int pc, int j) {
-  const unsigned g = (unsigned)(__ballot(pc == j) >> kr_gbase()) & KR_GMASK;
-  return g ? __builtin_ctz(g) : 0;
-}
-
+/* Back substitution with the factors of kr_glu_impl (b after the forward
+ * substitution, by row; the solution by unknown out).  Step j reads the
+ * group's pivot row of column j (found by ballot: a failed factorisation
+ * has none and its solve is discarded) by readlane. */
 template <typename F>
 __device__ __forceinline__ F kr_gback(const F (&a)[KR_N], int pc, F dinv, F b) {
   const int r = kr_glane();
   F x = F(0);
 #pragma unroll
   for (int j = KR_N - 1; j >= 0; --j) {
-    const int pj = kr_gpivot_lane(pc, j);
-    const F xj = kr_gbc(b * dinv, pj);
+    const F xj = kr_gwhere(b * dinv, pc == j);
     b = fma(-(pc < j ? a[j] : F(0)), xj, b);
     x = r == j ? xj : x;
   }
@@ -317,8 +377,7 @@ template <typename F>
 __device__ __forceinline__ F kr_gsolve(const F (&a)[KR_N], int pc, F dinv, F b) {
 #pragma unroll
   for (int j = 0; j < KR_N; ++j) {
-    const int pj = kr_gpivot_lane(pc, j);
-    const F yj = kr_gbc(b, pj);
+    const F yj = kr_gwhere(b, pc == j);
     b = fma(-(pc > j ? a[j] : F(0)), yj, b);
   }
   return kr_gback(a, pc, dinv, b);
@@ -741,11 +800,11 @@ __device__ __forceinline__ void kr_gintegrate(const KrParams &p) {
 #pragma unroll
       for (int k = 0; k < KR_N; ++k) a[k] = w.J[row * KR_LDJ + k];
       const bool er = r == KR_S;
-      const double T = kr_gbc(y, KR_S);
+      const double T = kr_gat(y, KR_S);
 #pragma unroll
       for (int k = 0; k < KR_S; ++k) {
 #if KR_CV_POLY
-        const double ek = kr_gbc(el, k);
+        const double ek = kr_gat(el, k);
 #else
         const double ek = kr_cv[k] * T;
 #endif
@@ -827,7 +886,7 @@ __device__ __forceinline__ void kr_gintegrate(const KrParams &p) {
           const double yi = y + d;
           const double ynew = r < KR_N ? yi : 0.0;
           const bool bad = r < KR_N && (!kr_finite(d) || !kr_finite(yi));
-          if (kr_gany(bad) || !(kr_gbc(ynew, KR_S) > 0.0)) {
+          if (kr_gany(bad) || !(kr_gat(ynew, KR_S) > 0.0)) {
             kr_gnewton_failed(p, C, y, yn);
           } else {
             y = ynew;
