@@ -406,7 +406,7 @@ __device__ __forceinline__ double kr_gproject(double yl, double ynl, double atol
   constexpr int V = KR_NROWS > 0 ? KR_NROWS : 1;
   const int r = kr_glane();
   const double W = r < KR_S ? fmax(fabs(yl), atol) : 0.0;
-  double G[V][V], q[V];
+  double G[V][V], q[V], Gi[V];
 #pragma unroll
   for (int a = 0; a < V; ++a) {
     const double na = r < KR_S ? (double)kr_comp[a][r] : 0.0;
@@ -424,8 +424,12 @@ __device__ __forceinline__ double kr_gproject(double yl, double ynl, double atol
       double t = G[a][b];
 #pragma unroll
       for (int k = 0; k < b; ++k) t -= G[a][k] * G[b][k];
-      if (a == b) G[a][a] = sqrt(fmax(t, 1e-300));
-      else G[a][b] = t / G[b][b];
+      if (a == b) {
+        G[a][a] = sqrt(fmax(t, 1e-300));
+        Gi[a] = 1.0 / G[a][a];
+      } else {
+        G[a][b] = t * Gi[b];
+      }
     }
   }
 #pragma unroll
@@ -433,14 +437,14 @@ __device__ __forceinline__ double kr_gproject(double yl, double ynl, double atol
     double t = q[a];
 #pragma unroll
     for (int k = 0; k < a; ++k) t -= G[a][k] * q[k];
-    q[a] = t / G[a][a];
+    q[a] = t * Gi[a];
   }
 #pragma unroll
   for (int a = V - 1; a >= 0; --a) {
     double t = q[a];
 #pragma unroll
     for (int k = a + 1; k < V; ++k) t -= G[k][a] * q[k];
-    q[a] = t / G[a][a];
+    q[a] = t * Gi[a];
   }
   double t = 0.0;
 #pragma unroll

@@ -164,16 +164,21 @@ def test_fp32lu_h_he(oracle_lib):
     assert_parity(gpu, orc, cs, 1e-6, "fp32lu h_he", desc=net)
 
 
-def test_closed_form_networks_on_gpu(oracle_lib):
+@pytest.mark.parametrize("layout", ["lane", "wave", "group16", "group32"])
+def test_closed_form_networks_on_gpu(oracle_lib, layout):
     """Isomer pair and all-unary network: GPU fixed steps equal the closed
-    forms used to pin the oracle."""
+    forms used to pin the oracle, in every layout (one cell per lane, per
+    wavefront, per 16- and per 32-lane group)."""
+    kr = _kr()
+    build = kr.build_options(layout={"lane": kr.KR_LAYOUT_LANE, "wave": kr.KR_LAYOUT_WAVE,
+                                     "group16": kr.KR_LAYOUT_GROUP16, "group32": kr.KR_LAYOUT_GROUP32}[layout])
     kf, ds = 2.0, 0.7
     kr_ = kf * np.exp(-ds)
     desc = isomer_pair(kf, ds)
     A0, B0 = 3.0, 0.25
     cs = sy.CellStates(np.array([[A0] * 70, [B0] * 70]), np.full(70, 500.0), np.ones(70), None)
     m, dt = 9, 2.0
-    n, T, st, stats, _ = run_gpu(desc, cs, dt_scalar=dt, mode=1, n_fixed=m)
+    n, T, st, stats, _ = run_gpu(desc, cs, dt_scalar=dt, build=build, mode=1, n_fixed=m)
     Aeq = kr_ * (A0 + B0) / (kf + kr_)
     exact = Aeq + (A0 - Aeq) / (1 + (kf + kr_) * dt / m) ** m
     assert np.all(st == 0)
@@ -181,7 +186,7 @@ def test_closed_form_networks_on_gpu(oracle_lib):
     desc = linear_three()
     cs = sy.CellStates(np.tile(np.array([[1.0], [2.0], [0.5]]), (1, 65)), np.full(65, 300.0),
                        np.ones(65), None)
-    gpu = run_gpu(desc, cs, dt_scalar=3.0, mode=1, n_fixed=4)
+    gpu = run_gpu(desc, cs, dt_scalar=3.0, build=build, mode=1, n_fixed=4)
     orc = run_oracle(oracle_lib, desc, cs, dt_scalar=3.0, mode="fixed", n_fixed=4)
     assert_parity(gpu, orc, cs, 1e-13, "linear3", desc=desc)
 
