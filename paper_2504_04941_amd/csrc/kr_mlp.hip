@@ -61,7 +61,10 @@ __device__ static inline float kr_gelu_grad(float z) {
   return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
-enum { KR_EPI_BIAS_GELU = 0, KR_EPI_BIAS = 1, KR_EPI_DGELU = 2, KR_EPI_STORE = 3 };
+/* epilogues: pre-activation and its BF16 GELU (training), bias only, GELU
+ * derivative, plain store, BF16 GELU only (inference: no pre-activation to
+ * keep for a backward pass) */
+enum { KR_EPI_BIAS_GELU = 0, KR_EPI_BIAS = 1, KR_EPI_DGELU = 2, KR_EPI_STORE = 3, KR_EPI_GELU = 4 };
 
 struct KrEpi {
   const float *bias;   /* [N] (BIAS_GELU, BIAS) */
@@ -178,6 +181,8 @@ __global__ void __launch_bounds__(256) kr_gemm_bf16(int M, int N, int K, const k
           const float z = v + ep.bias[col];
           ep.outf[o] = z;
           ep.outb[o] = kr_f2bf(kr_gelu(z));
+        } else if (EPI == KR_EPI_GELU) {
+          ep.outb[o] = kr_f2bf(kr_gelu(v + ep.bias[col]));
         } else if (EPI == KR_EPI_BIAS) {
           ep.outf[o] = v + ep.bias[col];
         } else if (EPI == KR_EPI_DGELU) {
@@ -467,8 +472,10 @@ static int guess_reserve(kr_guess *q, int B) {
   return KR_OK;
 }
 
-/* forward pass of B standardised rows already in a_in; out <- outputs */
-static int guess_forward(kr_guess *q, int B, hipStream_t st) {
+/* forward pass of B standardised rows already in a_in; out <- outputs.
+ * keep_z: store the hidden layers' FP32 pre-activations for a backward pass
+ * (training); inference writes only the BF16 activations. */
+static int guess_forward(kr_guess *q, int B, hipStream_t st, bool keep_z = true) {
   const kr_bf16 *a = q->a_in;
   int K = q->nin;
   for (int l = 0; l <= q->layers; ++l) {
@@ -480,7 +487,10 @@ static int guess_forward(kr_guess *q, int B, hipStream_t st) {
     if (l < q->layers) {
       ep.outf = q->zl[l];
       ep.outb = q->al[l];
-      HIP_TRY((kr_gemm<false, false, KR_EPI_BIAS_GELU>(B, N, K, a, K, W, K, ep, st)));
+      if (keep_z)
+        HIP_TRY((kr_gemm<false, false, KR_EPI_BIAS_GELU>(B, N, K, a, K, W, K, ep, st)));
+      else
+        HIP_TRY((kr_gemm<false, false, KR_EPI_GELU>(B, N, K, a, K, W, K, ep, st)));
       a = q->al[l];
     } else {
       ep.outf = q->out;
@@ -796,7 +806,7 @@ extern "C" int kr_guess_forward(kr_guess *q, int64_t n, const float *X, float *o
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
       const int B = (int)std::min<int64_t>(chunk, n - r0);
       if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X, nullptr, st))) return rc;
-      if ((rc = guess_forward(q, B, st))) return rc;
+      if ((rc = guess_forward(q, B, st, false))) return rc;
       HIP_TRY(hipMemcpyAsync(out + (size_t)r0 * q->nout, q->out, sizeof(float) * B * q->nout,
                              hipMemcpyDeviceToDevice, st));
     }
@@ -819,7 +829,7 @@ extern "C" int kr_guess_predict(kr_guess *q, int64_t n, const double *states, in
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
       const int B = (int)std::min<int64_t>(chunk, n - r0);
       if ((rc = guess_make_batch(q, B, n, 0, 0, r0, X_scratch, nullptr, st))) return rc;
-      if ((rc = guess_forward(q, B, st))) return rc;
+      if ((rc = guess_forward(q, B, st, false))) return rc;
       hipLaunchKernelGGL(kr_guess_apply_kernel, dim3((B + 255) / 256), dim3(256), 0, st, q->S, q->atoms, (long)n,
                          (long)r0, states, (long)ld, T, q->out, q->norm + 32, q->norm + 48, guess, (long)guess_ld);
       HIP_TRY(hipGetLastError());
