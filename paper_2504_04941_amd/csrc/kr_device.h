@@ -224,7 +224,9 @@ __device__ __forceinline__ bool kr_lu_factor32(float (&a)[KR_N][KR_N], float (&d
 #pragma unroll
     for (int k = 0; k < KR_N; ++k) v = fmaxf(v, fabsf(a[i][k]));
     ok = ok && (v > 0.0f) && __builtin_isfinite(v);
-    sc[i] = 1.0f / v;
+    /* hardware reciprocal estimates (about an ulp) here and for the pivots:
+     * the FP64 refinement corrects the factorisation's rounding anyway */
+    sc[i] = __builtin_amdgcn_rcpf(v);
   }
 #pragma unroll
   for (int j = 0; j < KR_N; ++j) {
@@ -257,7 +259,7 @@ __device__ __forceinline__ bool kr_lu_factor32(float (&a)[KR_N][KR_N], float (&d
     }
     float piv = a[j][j];
     ok = ok && (piv != 0.0f) && __builtin_isfinite(piv);
-    float d = 1.0f / piv;
+    float d = __builtin_amdgcn_rcpf(piv);
     dinv[j] = d;
 #pragma unroll
     for (int i = j + 1; i < KR_N; ++i) {

@@ -284,7 +284,11 @@ __device__ __forceinline__ void kr_genergy(KrGBlock &w) {
   if (m <= KR_S + 1) {
     double t = 0.0;
 #pragma unroll
-    for (int s = 0; s < KR_S; ++s) t = fma(kr_hf[s], w.J[s * KR_LDJ + m], t);
+    for (int s = 0; s < KR_S; s += 2) t = fma(kr_hf[s], w.J[s * KR_LDJ + m], t);
+    double t1 = 0.0;
+#pragma unroll
+    for (int s = 1; s < KR_S; s += 2) t1 = fma(kr_hf[s], w.J[s * KR_LDJ + m], t1);
+    t += t1;
     w.J[KR_S * KR_LDJ + m] = -t;
   }
   __syncthreads();
@@ -322,6 +326,14 @@ __device__ __forceinline__ void kr_gthermo(double yl, double &cv, double &eps, d
 /* row-per-lane LU of a group                                                */
 /* ------------------------------------------------------------------------ */
 
+/* In-place LU of the rows held by the group's lanes (lane r: row r; lanes
+ * from N hold no row), as kr_wlu_impl within a group: per column the group
+ * arg-max of the implicitly scaled candidates (Algorithm algo:lu-decomp's
+ * scaled partial pivoting), rows never moved.  On return pc = the column at
+ * which the lane's row was pivot row, a[k] the U entries for k >= pc and the
+ * L multipliers for k < pc, dinv the reciprocal pivot; AUG carries b through
+ * as an extra column (the forward substitution).  Returns false, alike in
+ * the group's lanes, for a singular or non-finite matrix. */
 template <typename F, bool AUG>
 __device__ __forceinline__ bool kr_glu_impl(F (&a)[KR_N], int &pc, F &dinv, F &b) {
   const int r = kr_glane();
@@ -337,7 +349,10 @@ __device__ __forceinline__ bool kr_glu_impl(F (&a)[KR_N], int &pc, F &dinv, F &b
     const bool cand = pc == KR_NOTPIV;
     const F aj = a[j];
     unsigned best;
-    const int p = kr_gargmax(fabsf((float)(fabs((double)aj) * (double)sc)), cand, best);
+    float key;
+    if constexpr (sizeof(F) == 4) key = fabsf(aj) * sc;
+    else key = fabsf((float)(fabs(aj) * sc));
+    const int p = kr_gargmax(key, cand, best);
     ok = ok && (best >> KR_GLOG) != 0u;
     /* the pivot, the next column's entry (the next arg-max waits for it) and
      * the carried right-hand side by readlane; the rest of the pivot row by
@@ -865,7 +880,11 @@ __device__ __forceinline__ void kr_gintegrate(const KrParams &p) {
           __syncthreads();
           double t = b;
 #pragma unroll
-          for (int k = 0; k < KR_N; ++k) t = fma(-a[k], v[k], t);
+          for (int k = 0; k < KR_N; k += 2) t = fma(-a[k], v[k], t);
+          double t1 = 0.0;
+#pragma unroll
+          for (int k = 1; k < KR_N; k += 2) t1 = fma(-a[k], v[k], t1);
+          t += t1;
           if (live) res = t;
           __syncthreads();
         }

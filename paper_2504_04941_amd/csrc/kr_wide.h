@@ -327,7 +327,10 @@ __device__ __forceinline__ F kr_wbc(F v, int src) {
 }
 
 /* 1/x: for FP64 the hardware estimate (relative error ~2^-24) refined by
- * two Newton steps, within an ulp or so of the quotient */
+ * two Newton steps, within an ulp or so of the quotient; for FP32 (the
+ * factorisation that FP64 refinement corrects) the hardware estimate alone,
+ * within about an ulp, instead of the correctly rounded division's
+ * ten-instruction sequence on every column's critical path */
 template <typename F>
 __device__ __forceinline__ F kr_wrcp(F x) {
   if constexpr (sizeof(F) == 8) {
@@ -337,7 +340,7 @@ __device__ __forceinline__ F kr_wrcp(F x) {
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
   } else {
-    return F(1) / x;
+    return __builtin_amdgcn_rcpf(x);
   }
 }
 
@@ -509,7 +512,7 @@ __device__ __forceinline__ void kr_wlu_panel(float (&a)[KR_N], int &pc, float &d
     pv[jj] = p;
     const float piv = kr_bcastf(aj, p);
     ok = ok && piv != 0.0f && kr_finite((double)piv);
-    const float inv = 1.0f / piv;
+    const float inv = kr_wrcp(piv);
     if (lane == p) { pc = j; dinv = inv; }
     const float l = pc == KR_NOTPIV ? aj * inv : 0.0f;
     if (pc == KR_NOTPIV) a[j] = l;
