@@ -110,14 +110,15 @@ def parity(desc, cs, idx, gpu_n, gpu_T, gpu_status, orc, iters):
     drift of the row totals, 4 sqrt(Newton iterations) eps n_nuc (the parity
     tests' gate).  The errors cover the cells both sides integrated (status
     0): a reverted cell keeps its input by design, which status agreement
-    reports.  Returns max and 99.9th percentile, status agreement and the
-    number of cells compared."""
+    reports.  Returns max and 99.9th percentile, the max over species above
+    1e-4 of the nuclei density and T, status agreement and the number of
+    cells compared."""
     n_o, T_o, st_o = orc
     ok = (np.asarray(gpu_status) == 0) & (np.asarray(st_o) == 0)
     out = {"status_agree": float(np.mean(gpu_status == st_o)), "cells": int(idx.size),
            "cells_compared": int(ok.sum())}
     if not ok.any():
-        return {"max_rel_err": None, "p99.9_rel_err": None, **out}
+        return {"max_rel_err": None, "p99.9_rel_err": None, "max_rel_err_major": None, **out}
     sub_n = cs.n[:, idx][:, ok]
     nnuc = np.abs(np.asarray(desc.composition)[:desc.n_elem]).sum(axis=0) @ sub_n
     n_o, gpu_n = n_o[:, ok], gpu_n[:, ok]
@@ -128,7 +129,12 @@ def parity(desc, cs, idx, gpu_n, gpu_T, gpu_status, orc, iters):
     err = np.maximum(np.abs(gpu_n - n_o) - slack, 0.0) / np.maximum(np.abs(n_o), FLOOR * nnuc[None, :])
     terr = np.abs(gpu_T[ok] - T_o[ok]) / np.abs(T_o[ok])
     both = np.concatenate([err.ravel(), terr])
-    return {"max_rel_err": float(both.max()), "p99.9_rel_err": float(np.percentile(both, 99.9)), **out}
+    # the species above 1e-4 of the nuclei density and T: the accuracy the
+    # FP32 modes can hold (an FP32 ulp of the nuclei density is far above the
+    # FP64 floor, so trace species say nothing about them)
+    major = np.concatenate([err[np.abs(n_o) > 1e-4 * nnuc[None, :]], terr])
+    return {"max_rel_err": float(both.max()), "p99.9_rel_err": float(np.percentile(both, 99.9)),
+            "max_rel_err_major": float(major.max()), **out}
 
 
 def cpu_baseline(desc, cs, dt_scalar, sample, seed=7, dt=None, gpu=None, one_core=256):

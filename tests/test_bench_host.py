@@ -32,6 +32,16 @@ def test_parity_compares_cells_both_sides_integrated():
     p = bench.parity(desc, cs, idx, gpu_n, gpu_T, st, (n_o, T_o, st), iters)
     assert abs(p["max_rel_err"] - 3e-7) < 1e-12
     assert p["status_agree"] == 1.0 and p["cells_compared"] == 6
+    nnuc = np.abs(np.asarray(desc.composition)[:desc.n_elem]).sum(axis=0) @ cs.n
+    major0 = abs(n_o[0, 1]) > 1e-4 * nnuc[1]
+    assert abs(p["max_rel_err_major"] - (3e-7 if major0 else 2e-9)) < 1e-12
+    # a trace species far off leaves the major-species figure alone
+    trace = np.argmin(np.abs(n_o[:, 3]) / nnuc[3])
+    assert abs(n_o[trace, 3]) < 1e-4 * nnuc[3] and trace not in list(desc.reservoir)
+    g2 = gpu_n.copy()
+    g2[trace, 3] *= 2.0
+    p2 = bench.parity(desc, cs, idx, g2, gpu_T, st, (n_o, T_o, st), iters)
+    assert p2["max_rel_err"] >= 0.99 and p2["max_rel_err_major"] == p["max_rel_err_major"]
     # a reverted cell (status 2, input kept) leaves the error statistics and
     # shows in the status agreement only
     gpu_st = st.copy()
