@@ -193,7 +193,9 @@ void kr_network_destroy(kr_network *net);
  *                 from there up to 30 species, one cell per wavefront
  *                 beyond (measured on gfx950: the lane layout is 2-10x
  *                 faster at 5 and 9 species, the wavefront layout 5x faster
- *                 at 23, 32-lane groups another 8-15 % at 23);
+ *                 at 23, 32-lane groups another 8-15 % at 23); networks
+ *                 with photoreactions or extra heat terms stay one cell per
+ *                 lane at any size (the only layout that has them);
  *                 KR_LAYOUT_LANE / KR_LAYOUT_WAVE force one.  The
  *                 wavefront layout holds the Newton matrix one row per lane
  *                 and needs n_species <= 62 and 5 * 2 * n_reactions

@@ -873,14 +873,19 @@ static bool lu_mfma_fits(int S, int n_dirs) {
  * automatic choice takes 32-lane groups from KR_WIDE_MIN_SPECIES species up
  * to the 30 a group holds (measured on the 23-species network: 15 % faster
  * than one cell per wavefront in FP64, 8 % with the FP32 LU). */
+/* Photoreactions and extra heat terms exist in the lane layout only: the
+ * automatic choice keeps such networks there at any size. */
+static bool lane_only(const kr_network *n) { return n->has_photo || !n->qx.empty(); }
+
 static int group_lanes(const kr_network *n, const kr_build_opts &o) {
-  if (o.layout == KR_LAYOUT_AUTO) return n->S >= KR_WIDE_MIN_SPECIES && n->S + 2 <= 32 ? 32 : 0;
+  if (o.layout == KR_LAYOUT_AUTO)
+    return !lane_only(n) && n->S >= KR_WIDE_MIN_SPECIES && n->S + 2 <= 32 ? 32 : 0;
   return o.layout == KR_LAYOUT_GROUP16 ? 16 : (o.layout == KR_LAYOUT_GROUP32 ? 32 : 0);
 }
 
 static bool use_wide(const kr_network *n, const kr_build_opts &o) {
   return o.layout == KR_LAYOUT_WAVE || group_lanes(n, o) > 0 ||
-         (o.layout == KR_LAYOUT_AUTO && n->S >= KR_WIDE_MIN_SPECIES);
+         (o.layout == KR_LAYOUT_AUTO && !lane_only(n) && n->S >= KR_WIDE_MIN_SPECIES);
 }
 
 /* The lane-group layout holds a cell's N = S + 1 rows on G lanes with one

@@ -172,3 +172,22 @@ def test_photoreaction_code_and_validation():
         with pytest.raises(kr.KrError) as e:
             kr.network_check(bad)
         assert e.value.code == kr.KR_EINVAL
+
+
+def test_automatic_layout_keeps_lane_only_terms_in_the_lane_layout():
+    """Photoreactions and extra heat terms exist in the lane layout only: the
+    automatic layout keeps such a network one cell per lane at any size (a
+    23-species network with extra heat compiles there), while the same
+    network without them goes to 32-lane groups; forcing another layout is
+    refused."""
+    kr = _kr()
+    desc = sy.network_astro23(2)
+    assert "one cell per lane group" in kr.network_check(desc)
+    desc.heat_extra = np.zeros((desc.n_reactions, 3))
+    desc.heat_extra[0] = (10.0, 0.0, 0.0)
+    src = kr.network_check(desc)
+    assert "network-specialised device code" in src and "const R qx" in src
+    for L in (kr.KR_LAYOUT_WAVE, kr.KR_LAYOUT_GROUP32):
+        with pytest.raises(kr.KrError) as e:
+            kr.network_check(desc, build=kr.build_options(layout=L))
+        assert e.value.code == kr.KR_EINVAL
