@@ -81,22 +81,23 @@ def flops_per_unit(desc):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "kr_integrate_fp64_h_o_n_1M.md")
+PROFILE_ADVECT = os.path.join(ROOT, "profiles", "kr_advect_h_o_n_1M.md")
 
 
-def measured_traffic(kernel_source):
+def measured_traffic(kernel_source, profile=PROFILE, key="traffic_bytes"):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on this exact kernel (hash of the generated device source); else
     None."""
     import hashlib
     import re
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
         rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))
     except (OSError, AttributeError, ValueError):
         return None
     if rec.get("source_sha256") != hashlib.sha256(kernel_source.encode()).hexdigest():
         return None
-    return rec["traffic_bytes"]
+    return rec.get(key)
 
 
 EPS = float(np.finfo(np.float64).eps)
@@ -578,13 +579,15 @@ def run_stromgren(args):
 
 
 def run_advect(args):
-    """Species advection (Sec. 2.1): one SSP-RK2 step (two kr_advect_plm
-    stages) of the stoichiometry-compatible PLM over lines of cells with
-    periodic ends, 9-species combustion network, non-uniform grid, density
-    and velocity per line as synthetic.advection_lines draws them.  HBM
-    bound: per cell and step the algorithmic traffic is (5 S + 4) 8 bytes
-    (stage 1 reads n, rho, the face flux and writes n; stage 2 also reads the
-    step's initial state)."""
+    """Species advection (Sec. 2.1): one SSP-RK2 step of the
+    stoichiometry-compatible PLM over lines of cells with periodic ends,
+    9-species combustion network, non-uniform grid, density and velocity per
+    line as synthetic.advection_lines draws them.  HBM bound.  Fused form
+    (kr_advect_plm_ssprk2, the default): per cell and step the algorithmic
+    traffic is (2 S + 4) 8 bytes (n in and out, both stages' density and
+    face flux).  Two-stage form (--advect-form stages, two kr_advect_plm
+    calls): (5 S + 4) 8 bytes (stage 1 reads n, rho, the face flux and
+    writes n; stage 2 also reads the step's initial state)."""
     import torch
     import paper_2504_04941_amd as kr
     import synthetic as sy
@@ -608,6 +611,10 @@ def run_advect(args):
     u2 = torch.empty_like(u0)
     rho = torch.tensor(rho_h, device=dev)
     F = torch.tensor(F_h, device=dev)
+    # the second stage's density and fluxes in buffers of their own (equal
+    # values: see the note in step())
+    rho1, F1 = rho.clone(), F.clone()
+    fused = args.advect_form == "fused"
     xc, xf = torch.tensor(xc_h, device=dev), torch.tensor(xf_h, device=dev)
     dt = 0.4 * float(np.min(np.diff(xf_h)))
     stream = torch.cuda.current_stream()
@@ -618,9 +625,12 @@ def run_advect(args):
         # per mass the test of the kernel covers; the work per cell is the same
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        kr.advect_plm(net, u, u1, rho, F, xc, xf, dt, n_lines=n_lines, stream=stream)
-        kr.advect_plm(net, u1, u2, rho, F, xc, xf, dt, n_lines=n_lines, base=u, alpha=0.5, beta=0.5,
-                      stream=stream)
+        if fused:
+            kr.advect_plm_ssprk2(net, u, u2, rho, F, rho1, F1, xc, xf, dt, n_lines=n_lines, stream=stream)
+        else:
+            kr.advect_plm(net, u, u1, rho, F, xc, xf, dt, n_lines=n_lines, stream=stream)
+            kr.advect_plm(net, u1, u2, rho1, F1, xc, xf, dt, n_lines=n_lines, base=u, alpha=0.5, beta=0.5,
+                          stream=stream)
         ev1.record(stream)
         return ev0, ev1
 
@@ -633,21 +643,25 @@ def run_advect(args):
     wall = time.perf_counter() - t0
     kernel_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
     cells = n_lines * n_cells
-    bytes_step = cells * (5 * S + 4) * 8.0
+    per_cell = (2 * S + 4) * 8 if fused else (5 * S + 4) * 8
+    bytes_step = cells * float(per_cell)
     out = {"metric": "cell-steps/s species advection (projected PLM, SSP-RK2), 1 GPU",
            "value": cells * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"advect: {n_lines} periodic lines x {n_cells} cells, h_o_n 9 species, "
-                                  "non-uniform grid, projected PLM, SSP-RK2 (2 stages)"},
+                                  "non-uniform grid, projected PLM, SSP-RK2 "
+                                  + ("(both stages in one kernel)" if fused else "(2 stage kernels)")},
            "kernel_ms_per_step": kernel_s * 1e3, "setup_s": setup_s,
            "roofline": {"bound": "hbm", "achieved": bytes_step / kernel_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                        "frac": bytes_step / kernel_s / 8e12, "traffic": None, "kernel": "kr_advect",
-                        "bytes_per_cell_step": (5 * S + 4) * 8}}
+                        "frac": bytes_step / kernel_s / 8e12,
+                        "traffic": (measured_traffic(kr.network_check(desc), PROFILE_ADVECT, "traffic_bytes_per_step")
+                                    if fused else None),
+                        "kernel": "kr_advect2" if fused else "kr_advect", "bytes_per_cell_step": per_cell}}
     if not args.no_cpu_baseline:
         from oracle import plm
         P = plm.projector_svd(desc.composition)
-        k = min(n_lines, 64)
+        k = n_lines
         got = u2.cpu().numpy()
         cores = len(os.sched_getaffinity(0))
         t1 = time.perf_counter()
@@ -740,6 +754,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--advect-form", default="fused", choices=["fused", "stages"],
+                    help="advect workload: both SSP-RK2 stages in one kernel, or two stage kernels")
     ap.add_argument("--order", default="default", choices=["default", "work", "input"],
                     help="order in which the persistent kernel hands out cells: largest expected "
                          "work first or input order (default: the faster one for the workload)")

@@ -491,6 +491,37 @@ int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells,
                   const double *base, double alpha, double beta, int32_t mode,
                   kr_stream_t stream);
 
+/* One whole SSP-RK2 step of the same advection (Sec. 2.1; the time
+ * integrator of the test of Sec. 4.1) in one pass over memory, for networks
+ * of up to 16 species:
+ *   u1    = n_in - dt / dx (F(i+1/2) - F(i-1/2))   the faces of n_in / rho0
+ *                                                  with the mass fluxes flux0
+ *   n_out = 1/2 n_in + 1/2 (u1 - dt / dx (F1(i+1/2) - F1(i-1/2)))
+ *                                                  the faces of u1 / rho1
+ *                                                  with the mass fluxes flux1
+ * -- the two kr_advect_plm stages with (alpha, beta) = (0, 1) and (1/2,
+ * 1/2), base n_in, with the same bits, but the intermediate u1 stays in
+ * registers (each wavefront updates the first stage on a halo of two cells
+ * around its own), so the step reads n_in and writes n_out once.  rho1 and
+ * flux1 are the first stage's density and its face mass fluxes, which the
+ * caller computes from rho0 and flux0 (the density's own update is the
+ * caller's, as for kr_advect_plm).
+ *   n_lines, n_cells   lines and cells per line (>= 4); cell i of line l is
+ *                      column l * line_stride + i of the [S][ld] arrays
+ *   n_in, n_out        device [n_species][ld]; n_out must not alias n_in
+ *   rho0, flux0        device [cells]: density and left-face mass flux of
+ *                      the step's start
+ *   rho1, flux1        device [cells]: the same after the first stage
+ *   xc, xf, dt, mode   as for kr_advect_plm
+ * Errors: KR_EINVAL (also for networks of more than 16 species: take two
+ * kr_advect_plm stages there), KR_EDEVICE.  Asynchronous on the stream. */
+int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int64_t n_cells,
+                         int64_t line_stride, const double *n_in, double *n_out,
+                         int64_t ld, const double *rho0, const double *flux0,
+                         const double *rho1, const double *flux1,
+                         const double *xc, const double *xf, double dt,
+                         int32_t mode, kr_stream_t stream);
+
 /* Fastest self-coupling timescale of each cell at its (pre-processed) input
  * state, out[c] = 1 / max(max_s |df_s/dn_s|, |dQ/dT| / c_V), capped at 1e7 s
  * (device arrays; used to express steps in units of the cell's stiffness). */

@@ -35,7 +35,7 @@ KR_NOALLOC_MAX_ORDER_CELLS = (KR_NOALLOC_SCRATCH_BYTES - 4096) // 5
 EXPORTED = ("kr_network_create", "kr_network_destroy", "kr_network_unknowns", "kr_network_layout",
             "kr_network_arrhenius", "kr_network_source", "kr_network_check", "kr_network_check_ex",
             "kr_default_options", "kr_chem_integrate", "kr_element_residual", "kr_postprocess",
-            "kr_advect_plm", "kr_chem_integrate_noalloc",
+            "kr_advect_plm", "kr_advect_plm_ssprk2", "kr_chem_integrate_noalloc",
             "kr_last_error", "kr_guess_create", "kr_guess_destroy", "kr_guess_num_params",
             "kr_guess_get_params", "kr_guess_set_params", "kr_guess_get_normalization",
             "kr_guess_set_normalization", "kr_guess_features", "kr_guess_targets",
@@ -137,6 +137,9 @@ def lib():
         L.kr_advect_plm.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                     C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p]
+        L.kr_advect_plm_ssprk2.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]
         L.kr_postprocess.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_void_p, C.c_void_p]
         L.kr_last_error.restype = C.c_char_p
@@ -433,6 +436,25 @@ def advect_plm(net: Network, n_in, n_out, rho, flux, xc, xf, dt: float, n_lines:
                                _dev_ptr(xf, torch.float64, "xf"), float(dt),
                                _dev_ptr(base, torch.float64, "base"), float(alpha), float(beta), int(mode),
                                _stream_ptr(stream)))
+
+
+def advect_plm_ssprk2(net: Network, n_in, n_out, rho0, flux0, rho1, flux1, xc, xf, dt: float, n_lines: int = 1,
+                      line_stride: int | None = None, mode: int = ADVECT_PROJECTED, stream=None) -> None:
+    """kr_advect_plm_ssprk2: one whole SSP-RK2 step of the same advection in
+    one pass (networks of up to 16 species): rho0/flux0 the density and face
+    mass fluxes of the step's start, rho1/flux1 those after the first stage.
+    n_in, n_out: float64 [S, ld] (unit stride along cells)."""
+    import torch
+    if n_in.dim() != 2 or n_in.stride(1) != 1 or n_out.stride() != n_in.stride():
+        raise ValueError("n_in/n_out must be [n_species, ld] with the same layout")
+    n_cells = int(xc.numel())
+    stride = n_cells if line_stride is None else int(line_stride)
+    _check(lib().kr_advect_plm_ssprk2(net.handle, int(n_lines), n_cells, stride,
+                                      _dev_ptr(n_in, torch.float64, "n_in"), _dev_ptr(n_out, torch.float64, "n_out"),
+                                      int(n_in.stride(0)), _dev_ptr(rho0, torch.float64, "rho0"),
+                                      _dev_ptr(flux0, torch.float64, "flux0"), _dev_ptr(rho1, torch.float64, "rho1"),
+                                      _dev_ptr(flux1, torch.float64, "flux1"), _dev_ptr(xc, torch.float64, "xc"),
+                                      _dev_ptr(xf, torch.float64, "xf"), float(dt), int(mode), _stream_ptr(stream)))
 
 
 def work_order(net: Network, states, T, rho=None, dt=None, dt_scalar: float = 0.0,

@@ -148,6 +148,7 @@ struct kr_network {
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
   hipFunction_t f_single = nullptr, f_mixed = nullptr;   /* lane layout only */
   hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr, f_adv = nullptr;
+  hipFunction_t f_adv2 = nullptr;    /* fused SSP-RK2 advection (up to 16 species) */
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0, occ_single = 0, occ_mixed = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
   bool wide = false;            /* one wavefront per cell (also the lane-group layout's
@@ -1015,6 +1016,7 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
     CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
     CREATE_TRY(hipModuleGetFunction(&n->f_post, n->module, "kr_post"));
     CREATE_TRY(hipModuleGetFunction(&n->f_adv, n->module, "kr_advect"));
+    if (n->S <= 16) CREATE_TRY(hipModuleGetFunction(&n->f_adv2, n->module, "kr_advect2"));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
     if (!n->wide) {
@@ -1538,6 +1540,47 @@ extern "C" int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_c
     const long long blocks = std::min<long long>(reg ? (units + 3) / 4 : units, (long long)net->cu_count * 64);
     void *args[] = {&p};
     HIP_TRY(hipModuleLaunchKernel(net->f_adv, (unsigned)blocks, 1, 1, threads, 1, 1, 0, (hipStream_t)stream, args,
+                                  nullptr));
+    return KR_OK;
+  } KR_CATCH
+}
+
+struct KrAdv2ParamsHost {         /* mirrors the device struct KrAdv2Params (kr_advect.h) */
+  long long n_lines, n_cells, line_stride;
+  const double *n_in;
+  double *n_out;
+  long long ld;
+  const double *rho0, *flux0, *rho1, *flux1, *xc, *xf;
+  double dt;
+  int mode;
+};
+
+extern "C" int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int64_t n_cells, int64_t line_stride,
+                                    const double *n_in, double *n_out, int64_t ld, const double *rho0,
+                                    const double *flux0, const double *rho1, const double *flux1,
+                                    const double *xc, const double *xf, double dt, int32_t mode,
+                                    kr_stream_t stream) {
+  try {
+    if (!net) return fail(KR_EINVAL, "null network");
+    if (!net->f_adv2) return fail(KR_EINVAL, "the fused step holds up to 16 species (network has %d)", net->S);
+    if (n_lines < 0 || n_cells < 0 || (n_lines > 1 && line_stride < n_cells) || (n_lines == 1 && line_stride < 0))
+      return fail(KR_EINVAL, "bad line sizes");
+    if (n_lines == 0 || n_cells == 0) return KR_OK;
+    if (n_cells < 4) return fail(KR_EINVAL, "the fused step needs lines of at least 4 cells");
+    if ((n_lines - 1) * line_stride + n_cells > ld) return fail(KR_EINVAL, "ld too small for the lines");
+    if (!n_in || !n_out || !rho0 || !flux0 || !rho1 || !flux1 || !xc || !xf) return fail(KR_EINVAL, "null array");
+    if (n_in == n_out) return fail(KR_EINVAL, "n_out must not alias n_in");
+    if (mode < 0 || mode > 2) return fail(KR_EINVAL, "mode out of [0, 2]");
+    if (!std::isfinite(dt)) return fail(KR_EINVAL, "bad dt");
+    HIP_TRY(hipSetDevice(net->device));
+    KrAdv2ParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho0, flux0, rho1, flux1,
+                       xc, xf, dt, mode};
+    /* 56 cells per wavefront (four halo cells on each side), 4 independent
+     * wavefronts per workgroup */
+    const long long units = n_lines * ((n_cells + 55) / 56);
+    const long long blocks = std::min<long long>((units + 3) / 4, (long long)net->cu_count * 64);
+    void *args[] = {&p};
+    HIP_TRY(hipModuleLaunchKernel(net->f_adv2, (unsigned)blocks, 1, 1, 256, 1, 1, 0, (hipStream_t)stream, args,
                                   nullptr));
     return KR_OK;
   } KR_CATCH

@@ -161,3 +161,128 @@ def test_projected_stage_keeps_element_abundances(which):
     e_before = comp @ (n / rho[None, :])
     e_after = comp @ (got / rho2[None, :])
     assert np.max(np.abs(e_after - e_before) / np.abs(e_before).max(axis=1, keepdims=True)) <= 1e-13
+
+
+def _stage_density(rho, F, xf, n_lines, n_cells, dt):
+    """The first stage's density (the caller's update by the same mass
+    fluxes), line by line."""
+    dx = np.diff(xf)
+    out = np.empty_like(rho)
+    for l in range(n_lines):
+        sl = slice(l * n_cells, (l + 1) * n_cells)
+        out[sl] = rho[sl] - dt / dx * (np.roll(F[sl], -1) - F[sl])
+    return out
+
+
+FUSED_CASES = [(w, n, False) for w in ("e1", "h_he", "h_o_n") for n in (128, 77, 56, 57, 4)] + \
+    [("h_o_n", 128, True), ("e1", 57, True), ("h_he", 4, True)]
+
+
+@pytest.mark.parametrize("which,n_cells,flip", FUSED_CASES)
+@pytest.mark.parametrize("mode,label", MODES)
+def test_fused_step_matches_two_stages_and_oracle(which, n_cells, flip, mode, label):
+    """kr_advect_plm_ssprk2 against the two kr_advect_plm stages it fuses
+    (bit for bit) and the oracle's SSP-RK2 step (within 1e-13 of the line's
+    largest abundance), with the density evolving through the step, lines
+    one chunk long, one cell over, ragged and of the minimum 4 cells, a line
+    stride and leading dimension larger than the batch; flip: the second
+    stage's mass flux reversed at a random third of the faces (the upwind
+    cell, hence the face geometry, changes between the stages)."""
+    kr = _kr()
+    desc = {"e1": sy.network_e1(), "h_he": sy.network_h_he(0), "h_o_n": sy.network_h_o_n(1)}[which]
+    n_lines = 5
+    n, rho, xc, xf, v = sy.advection_lines(desc, n_lines, n_cells)
+    dt = 0.3 * np.min(np.diff(xf))
+    F0 = _face_flux(rho, v, n_lines, n_cells)
+    rho1 = _stage_density(rho, F0, xf, n_lines, n_cells, dt)
+    F1 = _face_flux(rho1, v, n_lines, n_cells)
+    if flip:
+        F1 = np.where(np.random.default_rng(11).uniform(size=F1.size) < 1 / 3, -F1, F1)
+    S = desc.n_species
+    stride, ld = n_cells + 3, n_lines * (n_cells + 3) + 5
+
+    def spread(a, fill):
+        out = np.full(a.shape[:-1] + (ld,), fill)
+        for l in range(n_lines):
+            out[..., l * stride:l * stride + n_cells] = a[..., l * n_cells:(l + 1) * n_cells]
+        return out
+    print(f"fused advection {which} n_cells={n_cells} flip={flip} mode={label}", flush=True)
+    net = kr.Network(desc)
+    n_d = _dev(spread(n, 0.0))
+    r0, f0, r1, f1 = (_dev(spread(a, 1.0 if i % 2 == 0 else 0.0)) for i, a in enumerate((rho, F0, rho1, F1)))
+    xcd, xfd = _dev(xc), _dev(xf)
+    fused = torch.full((S, ld), -9.0, dtype=torch.float64, device="cuda")
+    kr.advect_plm_ssprk2(net, n_d, fused, r0, f0, r1, f1, xcd, xfd, dt, n_lines=n_lines, line_stride=stride,
+                         mode=mode)
+    u1 = torch.full_like(fused, -9.0)
+    two = torch.full_like(fused, -9.0)
+    kr.advect_plm(net, n_d, u1, r0, f0, xcd, xfd, dt, n_lines=n_lines, line_stride=stride, mode=mode)
+    kr.advect_plm(net, u1, two, r1, f1, xcd, xfd, dt, n_lines=n_lines, line_stride=stride, base=n_d, alpha=0.5,
+                  beta=0.5, mode=mode)
+    torch.cuda.synchronize()
+    got = fused.cpu().numpy()
+    net.close()
+    P = plm.projector_svd(desc.composition) if mode == 1 else None
+    for l in range(n_lines):
+        sl = slice(l * n_cells, (l + 1) * n_cells)
+        dl = slice(l * stride, l * stride + n_cells)
+        a1, _ = plm.stage(n[:, sl], rho[sl], F0[sl], xc, xf, dt, P, limit=mode != 2)
+        a2, _ = plm.stage(a1, rho1[sl], F1[sl], xc, xf, dt, P, limit=mode != 2)
+        want = 0.5 * (n[:, sl] + a2)
+        err = np.abs(got[:, dl] - want).max() / np.abs(n[:, sl]).max()
+        assert err <= 1e-13, (l, err)
+        # cells outside the lines are not written
+        assert np.all(got[:, l * stride + n_cells:(l + 1) * stride] == -9.0)
+    assert np.all(got[:, n_lines * stride:] == -9.0)
+    diff = np.abs(got - two.cpu().numpy())
+    assert torch.equal(fused, two), (int(np.count_nonzero(diff)), float(diff.max()))
+
+
+def test_fused_step_e1_advection_test():
+    """The test of Sec. 4.1 with the fused step: the same profiles as two
+    stages per step bit for bit, element abundances exact to <= 1e-14."""
+    kr = _kr()
+    net = kr.Network(sy.network_e1())
+    n0, u_two, steps = _gpu_e1(kr, net, 128, kr.ADVECT_PROJECTED)
+    xc, xf = sy.uniform_grid(128)
+    a, b = _dev(n0), torch.empty_like(_dev(n0))
+    rho = torch.ones(128, dtype=torch.float64, device="cuda")
+    F = torch.ones(128, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        kr.advect_plm_ssprk2(net, a, b, rho, F, rho, F, _dev(xc), _dev(xf), 1.0 / steps)
+        a, b = b, a
+    torch.cuda.synchronize()
+    u = a.cpu().numpy()
+    net.close()
+    np.testing.assert_array_equal(u, u_two)
+    E0 = plm.E1_COMP @ n0
+    assert np.max(np.abs(plm.E1_COMP @ u - E0) / E0) <= 1e-14
+
+
+def test_fused_step_refusals():
+    """More than 16 species, lines under 4 cells, aliasing, a bad mode: the
+    host refuses them before any launch; empty batches are no-ops."""
+    kr = _kr()
+    big = kr.Network(sy.network_astro23(2))
+    d = torch.ones((23, 64), dtype=torch.float64, device="cuda")
+    o = torch.empty_like(d)
+    r = torch.ones(64, dtype=torch.float64, device="cuda")
+    xc, xf = _dev(np.linspace(0.5 / 64, 1 - 0.5 / 64, 64)), _dev(np.linspace(0, 1, 65))
+    with pytest.raises(kr.KrError) as e:
+        kr.advect_plm_ssprk2(big, d, o, r, r, r, r, xc, xf, 1e-3)
+    assert e.value.code == kr.KR_EINVAL
+    big.close()
+    net = kr.Network(sy.network_h_o_n(1))
+    d = torch.ones((9, 64), dtype=torch.float64, device="cuda")
+    o = torch.full_like(d, -9.0)
+    for args, kw in (((d, o, r[:3], r[:3], r[:3], r[:3], xc[:3], xf[:4], 1e-3), {}),
+                     ((d, d, r, r, r, r, xc, xf, 1e-3), {}),
+                     ((d, o, r, r, r, r, xc, xf, 1e-3), {"mode": 3}),
+                     ((d, o, r, r, r, r, xc, xf, float("nan")), {})):
+        with pytest.raises(kr.KrError) as e:
+            kr.advect_plm_ssprk2(net, *args, **kw)
+        assert e.value.code == kr.KR_EINVAL
+    kr.advect_plm_ssprk2(net, d, o, r, r, r, r, xc, xf, 1e-3, n_lines=0)
+    torch.cuda.synchronize()
+    assert torch.all(o == -9.0)
+    net.close()
