@@ -593,7 +593,8 @@ def run_advect(args):
     import synthetic as sy
 
     dev = torch.device("cuda", 0)
-    desc = sy.network_h_o_n(1)
+    desc = {"h_o_n": lambda: sy.network_h_o_n(1), "astro23": lambda: sy.network_astro23(2),
+            "large48": lambda: sy.network_large48(3)}[args.advect_net]()
     S = desc.n_species
     n_cells = 256
     n_lines = max(1, args.cells // n_cells)
@@ -649,7 +650,7 @@ def run_advect(args):
            "value": cells * args.steps / wall, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"advect: {n_lines} periodic lines x {n_cells} cells, h_o_n 9 species, "
+           "config": {"workload": f"advect: {n_lines} periodic lines x {n_cells} cells, {desc.name}, "
                                   "non-uniform grid, projected PLM, SSP-RK2 "
                                   + ("(both stages in one kernel)" if fused else "(2 stage kernels)")},
            "kernel_ms_per_step": kernel_s * 1e3, "setup_s": setup_s,
@@ -754,6 +755,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--advect-net", default="h_o_n", choices=["h_o_n", "astro23", "large48"],
+                    help="advect workload: the network whose species are advected")
     ap.add_argument("--advect-form", default="fused", choices=["fused", "stages"],
                     help="advect workload: both SSP-RK2 stages in one kernel, or two stage kernels")
     ap.add_argument("--order", default="default", choices=["default", "work", "input"],

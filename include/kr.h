@@ -492,17 +492,17 @@ int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells,
                   kr_stream_t stream);
 
 /* One whole SSP-RK2 step of the same advection (Sec. 2.1; the time
- * integrator of the test of Sec. 4.1) in one pass over memory, for networks
- * of up to 16 species:
+ * integrator of the test of Sec. 4.1) in one pass over memory:
  *   u1    = n_in - dt / dx (F(i+1/2) - F(i-1/2))   the faces of n_in / rho0
  *                                                  with the mass fluxes flux0
  *   n_out = 1/2 n_in + 1/2 (u1 - dt / dx (F1(i+1/2) - F1(i-1/2)))
  *                                                  the faces of u1 / rho1
  *                                                  with the mass fluxes flux1
  * -- the two kr_advect_plm stages with (alpha, beta) = (0, 1) and (1/2,
- * 1/2), base n_in, with the same bits, but the intermediate u1 stays in
- * registers (each wavefront updates the first stage on a halo of two cells
- * around its own), so the step reads n_in and writes n_out once.  rho1 and
+ * 1/2), base n_in, with the same bits, but the intermediate u1 stays on
+ * chip (registers up to 16 species, LDS beyond; each wavefront or
+ * workgroup updates the first stage on a halo of two cells around its
+ * own), so the step reads n_in and writes n_out once.  rho1 and
  * flux1 are the first stage's density and its face mass fluxes, which the
  * caller computes from rho0 and flux0 (the density's own update is the
  * caller's, as for kr_advect_plm).
@@ -513,8 +513,7 @@ int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells,
  *                      the step's start
  *   rho1, flux1        device [cells]: the same after the first stage
  *   xc, xf, dt, mode   as for kr_advect_plm
- * Errors: KR_EINVAL (also for networks of more than 16 species: take two
- * kr_advect_plm stages there), KR_EDEVICE.  Asynchronous on the stream. */
+ * Errors: KR_EINVAL, KR_EDEVICE.  Asynchronous on the stream. */
 int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int64_t n_cells,
                          int64_t line_stride, const double *n_in, double *n_out,
                          int64_t ld, const double *rho0, const double *flux0,

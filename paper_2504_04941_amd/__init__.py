@@ -441,7 +441,7 @@ def advect_plm(net: Network, n_in, n_out, rho, flux, xc, xf, dt: float, n_lines:
 def advect_plm_ssprk2(net: Network, n_in, n_out, rho0, flux0, rho1, flux1, xc, xf, dt: float, n_lines: int = 1,
                       line_stride: int | None = None, mode: int = ADVECT_PROJECTED, stream=None) -> None:
     """kr_advect_plm_ssprk2: one whole SSP-RK2 step of the same advection in
-    one pass (networks of up to 16 species): rho0/flux0 the density and face
+    one pass: rho0/flux0 the density and face
     mass fluxes of the step's start, rho1/flux1 those after the first stage.
     n_in, n_out: float64 [S, ld] (unit stride along cells)."""
     import torch

@@ -148,7 +148,7 @@ struct kr_network {
   hipFunction_t f_fp64 = nullptr, f_fp32 = nullptr, f_reset = nullptr, f_tau = nullptr;
   hipFunction_t f_single = nullptr, f_mixed = nullptr;   /* lane layout only */
   hipFunction_t f_keys = nullptr, f_scan = nullptr, f_scatter = nullptr, f_post = nullptr, f_adv = nullptr;
-  hipFunction_t f_adv2 = nullptr;    /* fused SSP-RK2 advection (up to 16 species) */
+  hipFunction_t f_adv2 = nullptr;    /* fused SSP-RK2 advection */
   int device = -1, cu_count = 0, occ_fp64 = 0, occ_fp32 = 0, occ_single = 0, occ_mixed = 0;
   kr_build_opts build{1, 0.1f, KR_LAYOUT_AUTO, 0};
   bool wide = false;            /* one wavefront per cell (also the lane-group layout's
@@ -1016,7 +1016,7 @@ extern "C" int kr_network_create_ex(const kr_network_desc *desc, const kr_build_
     CREATE_TRY(hipModuleGetFunction(&n->f_scatter, n->module, "kr_order_scatter"));
     CREATE_TRY(hipModuleGetFunction(&n->f_post, n->module, "kr_post"));
     CREATE_TRY(hipModuleGetFunction(&n->f_adv, n->module, "kr_advect"));
-    if (n->S <= 16) CREATE_TRY(hipModuleGetFunction(&n->f_adv2, n->module, "kr_advect2"));
+    CREATE_TRY(hipModuleGetFunction(&n->f_adv2, n->module, "kr_advect2"));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp64, n->f_fp64, 64, 0));
     CREATE_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n->occ_fp32, n->f_fp32, 64, 0));
     if (!n->wide) {
@@ -1562,7 +1562,6 @@ extern "C" int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int6
                                     kr_stream_t stream) {
   try {
     if (!net) return fail(KR_EINVAL, "null network");
-    if (!net->f_adv2) return fail(KR_EINVAL, "the fused step holds up to 16 species (network has %d)", net->S);
     if (n_lines < 0 || n_cells < 0 || (n_lines > 1 && line_stride < n_cells) || (n_lines == 1 && line_stride < 0))
       return fail(KR_EINVAL, "bad line sizes");
     if (n_lines == 0 || n_cells == 0) return KR_OK;
@@ -1575,12 +1574,15 @@ extern "C" int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int6
     HIP_TRY(hipSetDevice(net->device));
     KrAdv2ParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho0, flux0, rho1, flux1,
                        xc, xf, dt, mode};
-    /* 56 cells per wavefront (four halo cells on each side), 4 independent
-     * wavefronts per workgroup */
-    const long long units = n_lines * ((n_cells + 55) / 56);
-    const long long blocks = std::min<long long>((units + 3) / 4, (long long)net->cu_count * 64);
+    /* up to 16 species: 56 cells per wavefront (four halo cells on each
+     * side), 4 independent wavefronts per workgroup; more: one LDS-staged
+     * chunk of 64 cells per workgroup (the kernel's KR_ADV_REG / KR_ADV_CHUNK) */
+    const bool reg = net->S <= 16;
+    const int per = reg ? 56 : 64, threads = reg ? 256 : 64;
+    const long long units = n_lines * ((n_cells + per - 1) / per);
+    const long long blocks = std::min<long long>(reg ? (units + 3) / 4 : units, (long long)net->cu_count * 64);
     void *args[] = {&p};
-    HIP_TRY(hipModuleLaunchKernel(net->f_adv2, (unsigned)blocks, 1, 1, 256, 1, 1, 0, (hipStream_t)stream, args,
+    HIP_TRY(hipModuleLaunchKernel(net->f_adv2, (unsigned)blocks, 1, 1, threads, 1, 1, 0, (hipStream_t)stream, args,
                                   nullptr));
     return KR_OK;
   } KR_CATCH
