@@ -639,6 +639,18 @@ static std::string network_tables(const kr_network *n) {
     o += i + 1 < S ? "}," : "}";
   }
   o += "};\n";
+  /* the same projector in low-rank form, P chi = chi - Q^T (Q chi): the
+   * basis rows themselves (a zero row when there is none) */
+  const int R = (int)Q.size();
+  o += "#define KR_PROJ_R " + std::to_string(R) + "\n";
+  o += "__device__ static constexpr double kr_projq[" + std::to_string(R > 0 ? R : 1) + "][" + std::to_string(S) +
+       "] = {";
+  for (int r = 0; r < (R > 0 ? R : 1); ++r) {
+    o += "{";
+    for (int j = 0; j < S; ++j) o += hexd(R > 0 ? (double)Q[r][j] : 0.0) + (j + 1 < S ? "," : "");
+    o += r + 1 < (R > 0 ? R : 1) ? "}," : "}";
+  }
+  o += "};\n";
   return o;
 }
 
