@@ -34,6 +34,27 @@ def _kr():
     return kr
 
 
+_NETS = {}
+
+
+def _net(which):
+    """One network per description for the whole module (creating one
+    compiles its module); closed when the module's tests end."""
+    if which not in _NETS:
+        desc = {"e1": sy.network_e1(), "h_he": sy.network_h_he(0), "h_o_n": sy.network_h_o_n(1),
+                "astro23": sy.network_astro23(2), "large48": sy.network_large48(3)}[which]
+        _NETS[which] = (_kr().Network(desc), desc)
+    return _NETS[which]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _close_networks():
+    yield
+    for net, _ in _NETS.values():
+        net.close()
+    _NETS.clear()
+
+
 def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
 
@@ -55,7 +76,7 @@ MODES = [(1, "projected"), (0, "plain"), (2, "donor")]
 @pytest.mark.parametrize("mode,label", MODES)
 def test_stage_matches_oracle(which, n_cells, mode, label):
     kr = _kr()
-    desc = {"e1": sy.network_e1(), "h_o_n": sy.network_h_o_n(1), "large48": sy.network_large48(3)}[which]
+    net, desc = _net(which)
     n_lines = 6
     n, rho, xc, xf, v = sy.advection_lines(desc, n_lines, n_cells)
     F = _face_flux(rho, v, n_lines, n_cells)
@@ -73,13 +94,11 @@ def test_stage_matches_oracle(which, n_cells, mode, label):
         base[:, dl] = n[:, sl] * rng.uniform(0.9, 1.1, (S, n_cells))
         rho_p[dl] = rho[sl]
         F_p[dl] = F[sl]
-    net = kr.Network(desc)
     out = torch.full((S, ld), -9.0, dtype=torch.float64, device="cuda")
     kr.advect_plm(net, _dev(n_in), out, _dev(rho_p), _dev(F_p), _dev(xc), _dev(xf), dt, n_lines=n_lines,
                   line_stride=stride, base=_dev(base), alpha=0.25, beta=0.75, mode=mode)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    net.close()
     P = plm.projector_svd(desc.composition) if mode == 1 else None
     for l in range(n_lines):
         sl = slice(l * n_cells, (l + 1) * n_cells)
@@ -116,7 +135,7 @@ def _gpu_e1(kr, net, n_cells, mode):
 
 def test_e1_advection_test_on_gpu():
     kr = _kr()
-    net = kr.Network(sy.network_e1())
+    net, _ = _net("e1")
     comp = plm.E1_COMP
     n0, u, steps = _gpu_e1(kr, net, 128, kr.ADVECT_PROJECTED)
     E0 = comp @ n0
@@ -133,7 +152,6 @@ def test_e1_advection_test_on_gpu():
     _, u_plain, _ = _gpu_e1(kr, net, 128, kr.ADVECT_PLAIN)
     drift = np.max(np.abs(comp @ u_plain - E0)[0] / E0[0])
     assert 1e-4 < drift < 3e-2, drift
-    net.close()
 
 
 @pytest.mark.parametrize("which", ["h_o_n", "large48"])
@@ -142,17 +160,15 @@ def test_projected_stage_keeps_element_abundances(which):
     stage keeps every cell's element abundances per mass (the fluxes carry
     elements in proportion to mass) to rounding."""
     kr = _kr()
-    desc = {"h_o_n": sy.network_h_o_n(1), "large48": sy.network_large48(3)}[which]
+    net, desc = _net(which)
     n_lines, n_cells = 8, 256
     n, rho, xc, xf, v = sy.advection_lines(desc, n_lines, n_cells)
     F = _face_flux(rho, v, n_lines, n_cells)
     dt = 0.4 * np.min(np.diff(xf))
-    net = kr.Network(desc)
     out = torch.empty((desc.n_species, n_lines * n_cells), dtype=torch.float64, device="cuda")
     kr.advect_plm(net, _dev(n), out, _dev(rho), _dev(F), _dev(xc), _dev(xf), dt, n_lines=n_lines)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    net.close()
     comp = np.asarray(desc.composition, np.float64)
     # the density after the same mass fluxes
     rho2 = np.empty_like(rho)
@@ -196,8 +212,7 @@ def test_fused_step_matches_two_stages_and_oracle(which, n_cells, flip, mode, la
     a random third of the faces (the upwind cell, hence the face geometry,
     changes between the stages)."""
     kr = _kr()
-    desc = {"e1": sy.network_e1(), "h_he": sy.network_h_he(0), "h_o_n": sy.network_h_o_n(1),
-            "astro23": sy.network_astro23(2), "large48": sy.network_large48(3)}[which]
+    net, desc = _net(which)
     n_lines = 5
     n, rho, xc, xf, v = sy.advection_lines(desc, n_lines, n_cells)
     dt = 0.3 * np.min(np.diff(xf))
@@ -215,7 +230,6 @@ def test_fused_step_matches_two_stages_and_oracle(which, n_cells, flip, mode, la
             out[..., l * stride:l * stride + n_cells] = a[..., l * n_cells:(l + 1) * n_cells]
         return out
     print(f"fused advection {which} n_cells={n_cells} flip={flip} mode={label}", flush=True)
-    net = kr.Network(desc)
     n_d = _dev(spread(n, 0.0))
     r0, f0, r1, f1 = (_dev(spread(a, 1.0 if i % 2 == 0 else 0.0)) for i, a in enumerate((rho, F0, rho1, F1)))
     xcd, xfd = _dev(xc), _dev(xf)
@@ -229,7 +243,6 @@ def test_fused_step_matches_two_stages_and_oracle(which, n_cells, flip, mode, la
                   beta=0.5, mode=mode)
     torch.cuda.synchronize()
     got = fused.cpu().numpy()
-    net.close()
     P = plm.projector_svd(desc.composition) if mode == 1 else None
     for l in range(n_lines):
         sl = slice(l * n_cells, (l + 1) * n_cells)
@@ -250,7 +263,7 @@ def test_fused_step_e1_advection_test():
     """The test of Sec. 4.1 with the fused step: the same profiles as two
     stages per step bit for bit, element abundances exact to <= 1e-14."""
     kr = _kr()
-    net = kr.Network(sy.network_e1())
+    net, _ = _net("e1")
     n0, u_two, steps = _gpu_e1(kr, net, 128, kr.ADVECT_PROJECTED)
     xc, xf = sy.uniform_grid(128)
     a, b = _dev(n0), torch.empty_like(_dev(n0))
@@ -261,7 +274,6 @@ def test_fused_step_e1_advection_test():
         a, b = b, a
     torch.cuda.synchronize()
     u = a.cpu().numpy()
-    net.close()
     np.testing.assert_array_equal(u, u_two)
     E0 = plm.E1_COMP @ n0
     assert np.max(np.abs(plm.E1_COMP @ u - E0) / E0) <= 1e-14
@@ -273,7 +285,7 @@ def test_fused_step_refusals():
     kr = _kr()
     r = torch.ones(64, dtype=torch.float64, device="cuda")
     xc, xf = _dev(np.linspace(0.5 / 64, 1 - 0.5 / 64, 64)), _dev(np.linspace(0, 1, 65))
-    net = kr.Network(sy.network_h_o_n(1))
+    net, _ = _net("h_o_n")
     d = torch.ones((9, 64), dtype=torch.float64, device="cuda")
     o = torch.full_like(d, -9.0)
     for args, kw in (((d, o, r[:3], r[:3], r[:3], r[:3], xc[:3], xf[:4], 1e-3), {}),
@@ -286,4 +298,3 @@ def test_fused_step_refusals():
     kr.advect_plm_ssprk2(net, d, o, r, r, r, r, xc, xf, 1e-3, n_lines=0)
     torch.cuda.synchronize()
     assert torch.all(o == -9.0)
-    net.close()
