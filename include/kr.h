@@ -500,7 +500,7 @@ int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_cells,
  *                                                  with the mass fluxes flux1
  * -- the two kr_advect_plm stages with (alpha, beta) = (0, 1) and (1/2,
  * 1/2), base n_in, with the same bits, but the intermediate u1 stays on
- * chip (registers up to 16 species, LDS beyond; each wavefront or
+ * chip (registers up to 32 species, LDS beyond; each wavefront or
  * workgroup updates the first stage on a halo of two cells around its
  * own), so the step reads n_in and writes n_out once.  rho1 and
  * flux1 are the first stage's density and its face mass fluxes, which the

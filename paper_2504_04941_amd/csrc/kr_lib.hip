@@ -1543,10 +1543,10 @@ extern "C" int kr_advect_plm(const kr_network *net, int64_t n_lines, int64_t n_c
     HIP_TRY(hipSetDevice(net->device));
     KrAdvParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho, flux, xc, xf,
                       base, dt, base ? alpha : 0.0, beta, mode};
-    /* up to 16 species: 60 cells per wavefront, 4 independent wavefronts
+    /* up to 32 species: 60 cells per wavefront, 4 independent wavefronts
      * per workgroup; more: one LDS-staged chunk of 64 cells per workgroup
      * (the kernel's KR_ADV_REG / KR_ADV_CHUNK) */
-    const bool reg = net->S <= 16;
+    const bool reg = net->S <= 32;
     const int per = reg ? 60 : 64, threads = reg ? 256 : 64;
     const long long units = n_lines * ((n_cells + per - 1) / per);
     const long long blocks = std::min<long long>(reg ? (units + 3) / 4 : units, (long long)net->cu_count * 64);
@@ -1586,10 +1586,10 @@ extern "C" int kr_advect_plm_ssprk2(const kr_network *net, int64_t n_lines, int6
     HIP_TRY(hipSetDevice(net->device));
     KrAdv2ParamsHost p{n_lines, n_cells, n_lines > 1 ? line_stride : 0, n_in, n_out, ld, rho0, flux0, rho1, flux1,
                        xc, xf, dt, mode};
-    /* up to 16 species: 56 cells per wavefront (four halo cells on each
+    /* up to 32 species: 56 cells per wavefront (four halo cells on each
      * side), 4 independent wavefronts per workgroup; more: one LDS-staged
      * chunk of 64 cells per workgroup (the kernel's KR_ADV_REG / KR_ADV_CHUNK) */
-    const bool reg = net->S <= 16;
+    const bool reg = net->S <= 32;
     const int per = reg ? 56 : 64, threads = reg ? 256 : 64;
     const long long units = n_lines * ((n_cells + per - 1) / per);
     const long long blocks = std::min<long long>(reg ? (units + 3) / 4 : units, (long long)net->cu_count * 64);

@@ -207,8 +207,8 @@ def test_fused_step_matches_two_stages_and_oracle(which, n_cells, flip, mode, la
     largest abundance), with the density evolving through the step, lines
     one chunk long, one cell over, ragged and of the minimum 4 cells, a line
     stride and leading dimension larger than the batch; the register form
-    (4, 5 and 9 species: 56-cell chunks) and the LDS form (23 and 48
-    species: 64-cell chunks); flip: the second stage's mass flux reversed at
+    (4, 5, 9 and 23 species: 56-cell chunks) and the LDS form (48 species:
+    64-cell chunks); flip: the second stage's mass flux reversed at
     a random third of the faces (the upwind cell, hence the face geometry,
     changes between the stages)."""
     kr = _kr()
